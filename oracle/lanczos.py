@@ -1,0 +1,311 @@
+"""Randomized small-block Lanczos on B = A^T A + eps D (oracle; test infrastructure only).
+
+Two routines, written from the paper in its notation (blocks Q_j of width d,
+diagonal blocks Xi_j, subdiagonal blocks Gamma_j, kept Ritz values Theta and
+coupling block F):
+
+* :func:`algorithm1` -- Algorithm 1 (Sec. 1.2): ell block-Lanczos steps with
+  full reorthogonalisation (classical Gram-Schmidt, twice, against every
+  previous block), Rayleigh-Ritz on T_ell, nullity N = #{theta < 3 eps}
+  (Remark "cormain").
+* :func:`algorithm2` -- Algorithm 2 (Sec. 4.3): thick restart (Sec. 4.1),
+  partial reorthogonalisation driven by the W-recurrence (Sec. 4.2),
+  adaptive nullity and the convergence-speed stopping rule (Sec. 4.3).
+
+Readings taken where the paper is silent, garbled or inconsistent (each is
+listed with its justification in the design notes):
+
+  R1  restart size: k_keep = d * floor((N_ell + dimK) / (2 d)) vectors,
+      clamped to [d, dimK - 2d]; ell_0 = k_keep / d blocks.
+  R2  the three-term recurrence subtracts Q_{ell-1} Gamma_{ell-1}^T (the
+      transpose printed in Eq. "laniterfp"; identical for d = 1).
+  R3  for kept blocks k <= ell_0 the coupling is B Q_k = Q_k Theta_k +
+      Q_{ell_0+1} F_k, so the first W case reads
+      w_{k,l+1} = |G_l^-1| (w_{k,l}(|Theta_k|+|Xi_l|) + w_{l0+1,l}|F_k|
+                             + w_{k,l-1}|G_{l-1}| + 2 u_d).
+  R4  W next to the diagonal: w_{l,l+1} = u_d (local orthogonality from the
+      explicit subtraction of Q_l Xi_l); for k = l-1 the pair
+      w_{k+1,l}|G_k| + w_{k,l-1}|G_{l-1}| cancels exactly in the derivation
+      (the Q_{l-1} coupling is subtracted explicitly) and is dropped.
+  R5  "reorthogonalize" = classical Gram-Schmidt applied twice (CGS2).
+  R6  QR = orthonormal factor with positive-diagonal triangular factor (the
+      unique thin QR of a full-rank block); d = 1 is normalisation.
+  R7  ||B|| in u_d: ||A||_1 ||A||_inf + eps in the first cycle, then the
+      largest Ritz value.
+  R8  u = 2^-52 (the value quoted in Sec. 5.3); u_RO = sqrt(u).
+  R9  block norms in the W-recurrence are Frobenius norms (upper bounds of
+      the spectral norms, so W stays an upper bound); |G_l^-1| is the
+      Frobenius norm of the inverse triangular factor.
+  R10 stopping rule: at each restart record (matvecs, N_ell); each increase
+      of N_ell after the first gives a speed sample (matvecs since the
+      previous increase) * d / (increase); s = 2 * max sample; stop once at
+      least one sample exists and more than s matvecs passed since the last
+      increase.  The interval before the first increase is not a sample: the
+      first Ritz value only has to separate the perturbed-zero cluster from
+      the rest of the spectrum, the later ones must also resolve the cluster,
+      so it under-estimates s.  With a single increase the run continues to
+      the matvec budget.
+  R11 the restart's coupling block is F = R Gamma_ell V_Z(last d rows, 1:k_keep),
+      where R (~ I) is the triangular factor of re-orthonormalising Q_{ell+1}
+      against the new Z_{ell_0}; the printed "[O, Gamma_{ell_0}] V_Z" drops
+      Gamma_ell (Sec. 4.1 derives F = E_{ell+1} V_Z with E_{ell+1} = [0, Gamma_ell]).
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+
+from .operator import apply_b, norm_upper_bound_ata
+
+U = 2.0 ** -52
+
+
+def block_qr(p: np.ndarray):
+    """Thin QR with positive diagonal R (reading R6)."""
+    q, r = np.linalg.qr(p)
+    s = np.sign(np.diag(r)).copy()
+    s[s == 0] = 1.0
+    return q * s[None, :], r * s[:, None]
+
+
+def cgs2(z: np.ndarray, p: np.ndarray) -> np.ndarray:
+    """(I - Z Z^T) P by classical Gram-Schmidt applied twice (reading R5)."""
+    if z.shape[1] == 0:
+        return p
+    p = p - z @ (z.T @ p)
+    p = p - z @ (z.T @ p)
+    return p
+
+
+def _fro(x) -> float:
+    return float(np.linalg.norm(np.atleast_2d(x)))
+
+
+def _inv_fro(g: np.ndarray) -> float:
+    return _fro(np.linalg.inv(np.atleast_2d(g)))
+
+
+# ---------------------------------------------------------------------------
+# Algorithm 1
+# ---------------------------------------------------------------------------
+def algorithm1(a, eps: float, dvec: np.ndarray, omega: np.ndarray, ell: int):
+    """Algorithm 1 with full reorthogonalisation.
+
+    Returns dict(V, theta, N, Z, T, Q_next, Gamma_last) with V = Z_ell V_Z(:, 1:N)
+    and N = #{theta < 3 eps}.
+    """
+    n, d = omega.shape
+    q1, _ = block_qr(omega)
+    blocks = [q1]
+    xis, gams = [], []
+    for j in range(ell):
+        qj = blocks[-1]
+        p = apply_b(a, eps, dvec, qj)
+        if j > 0:
+            p = p - blocks[-2] @ gams[-1].T
+        xi = qj.T @ p
+        p = p - qj @ xi
+        p = cgs2(np.hstack(blocks), p)
+        qn, g = block_qr(p)
+        xis.append(0.5 * (xi + xi.T))
+        gams.append(g)
+        blocks.append(qn)
+    t = np.zeros((ell * d, ell * d))
+    for j in range(ell):
+        t[j * d:(j + 1) * d, j * d:(j + 1) * d] = xis[j]
+        if j + 1 < ell:
+            t[(j + 1) * d:(j + 2) * d, j * d:(j + 1) * d] = gams[j]
+            t[j * d:(j + 1) * d, (j + 1) * d:(j + 2) * d] = gams[j].T
+    z = np.hstack(blocks[:ell])
+    theta, vz = np.linalg.eigh(t)
+    nul = int(np.sum(theta < 3.0 * eps))
+    return dict(V=z @ vz[:, :nul], theta=theta, N=nul, Z=z, T=t, Q_next=blocks[ell],
+                Gamma_last=gams[-1])
+
+
+# ---------------------------------------------------------------------------
+# Algorithm 2
+# ---------------------------------------------------------------------------
+class _WRecurrence:
+    """Upper bounds w_{k,j} >= ||Q_k^T Q_j|| (Sec. 4.2), blocks numbered from 1."""
+
+    def __init__(self, nblocks: int):
+        self.w = np.zeros((nblocks + 2, nblocks + 2))
+
+    def reset_column(self, j: int, u_d: float):
+        self.w[1:j, j] = u_d
+
+    def next_column(self, ell, l0, u_d, n_theta, n_f, n_xi, n_gam, gi):
+        """Column ell+1 from columns ell and ell-1 (readings R3, R4)."""
+        w = self.w
+        col = np.zeros(ell + 1)
+        sum_f = sum(w[i, ell] * n_f[i] for i in range(1, l0 + 1))
+        for k in range(1, ell + 1):
+            if k == ell:
+                col[k] = u_d
+            elif k <= l0:
+                col[k] = gi * (w[k, ell] * (n_theta[k] + n_xi[ell]) + w[l0 + 1, ell] * n_f[k]
+                               + w[k, ell - 1] * n_gam[ell - 1] + 2 * u_d)
+            elif k == l0 + 1:
+                acc = w[k, ell] * (n_xi[k] + n_xi[ell]) + sum_f + 2 * u_d
+                if k < ell - 1:
+                    acc += w[k + 1, ell] * n_gam[k] + w[k, ell - 1] * n_gam[ell - 1]
+                col[k] = gi * acc
+            else:
+                acc = w[k, ell] * (n_xi[k] + n_xi[ell]) + w[k - 1, ell] * n_gam[k - 1] + 2 * u_d
+                if k < ell - 1:
+                    acc += w[k + 1, ell] * n_gam[k] + w[k, ell - 1] * n_gam[ell - 1]
+                col[k] = gi * acc
+        w[1:ell + 1, ell + 1] = col[1:]
+        return float(col[1:ell].max()) if ell > 1 else 0.0
+
+
+def _assemble_t(theta_kept, f, xis, gams, l0, nblocks, d):
+    """Block tridiagonal T with the arrowhead [Theta, F^T; F, Xi_{l0+1}] (Eq. "defT")."""
+    kk = l0 * d
+    t = np.zeros((nblocks * d, nblocks * d))
+    if kk:
+        t[np.arange(kk), np.arange(kk)] = theta_kept
+        t[kk:kk + d, :kk] = f
+        t[:kk, kk:kk + d] = f.T
+    for j in range(l0 + 1, nblocks + 1):
+        r = (j - 1) * d
+        t[r:r + d, r:r + d] = xis[j]
+        if j < nblocks:
+            t[r + d:r + 2 * d, r:r + d] = gams[j]
+            t[r:r + d, r + d:r + 2 * d] = gams[j].T
+    return t
+
+
+def restart_size(n_ell: int, dim_k: int, d: int) -> int:
+    """Reading R1."""
+    k_keep = d * ((n_ell + dim_k) // (2 * d))
+    return int(min(max(k_keep, d), dim_k - 2 * d))
+
+
+def speed_rule(history, d: int):
+    """Reading R10: returns (stop, s) from the restart history [(matvecs, N_ell), ...]."""
+    events = [(0, 0)]
+    best = 0
+    for mv, nl in history:
+        if nl > best:
+            events.append((mv, nl))
+            best = nl
+    if best == 0:
+        return False, math.inf
+    samples = [(events[i][0] - events[i - 1][0]) * d / (events[i][1] - events[i - 1][1])
+               for i in range(2, len(events))]
+    if not samples:
+        return False, math.inf
+    s = 2.0 * max(samples)
+    last_mv = events[-1][0]
+    return (history[-1][0] - last_mv) > s, s
+
+
+def algorithm2(a, eps: float, dvec: np.ndarray, omega: np.ndarray, dim_k: int,
+               max_matvec: int = 10 ** 7, ro_tol: float | None = None, full_reorth: bool = False,
+               track_orth: bool = False, max_cycles: int | None = None):
+    """Algorithm 2: restarted randomized small-block Lanczos with partial reorthogonalisation.
+
+    Returns dict(V, N, theta, matvecs, restarts, reorths, history, converged,
+    orth_trace) where V = Z_ell V_Z(:, 1:N_ell) from the final cycle.
+    ``track_orth`` records max_k ||Q_k^T Q_{ell+1}|| (true value) next to the W
+    bound at every step, for testing that the bound holds.
+    """
+    n, d = omega.shape
+    if dim_k % d or dim_k < 3 * d:
+        raise ValueError("dim_k must be a multiple of d and at least 3d")
+    nb = dim_k // d
+    u_ro = math.sqrt(U) if ro_tol is None else ro_tol
+    norm_b = norm_upper_bound_ata(a) + eps * float(np.max(dvec))
+    u_d = d * math.sqrt(n) * U * norm_b
+
+    zb = np.zeros((n, dim_k + d))
+    zb[:, :d], _ = block_qr(omega)
+    l0 = 0
+    theta_kept = np.zeros(0)
+    f = np.zeros((d, 0))
+    matvecs = restarts = reorths = 0
+    history = []
+    orth_trace = []
+    bop = lambda x: apply_b(a, eps, dvec, x)  # noqa: E731
+
+    while True:
+        xis, gams = {}, {}
+        wrec = _WRecurrence(nb + 1)
+        kk = l0 * d
+        # ---- first step of the cycle: Q' = B Q_{l0+1}, Xi, QR of the projected Q'
+        qa = zb[:, kk:kk + d]
+        p = bop(qa)
+        matvecs += d
+        xis[l0 + 1] = qa.T @ p
+        xis[l0 + 1] = 0.5 * (xis[l0 + 1] + xis[l0 + 1].T)
+        p = cgs2(zb[:, :kk + d], p)
+        qn, g = block_qr(p)
+        gams[l0 + 1] = g
+        zb[:, kk + d:kk + 2 * d] = qn
+        wrec.reset_column(l0 + 1, u_d)
+        wrec.reset_column(l0 + 2, u_d)
+        # block norms used by the W-recurrence (reading R9)
+        n_theta = {k: float(np.max(np.abs(theta_kept[(k - 1) * d:k * d]))) for k in range(1, l0 + 1)}
+        n_f = {k: _fro(f[:, (k - 1) * d:k * d]) for k in range(1, l0 + 1)}
+        n_xi = {l0 + 1: _fro(xis[l0 + 1])}
+        n_gam = {l0 + 1: _fro(gams[l0 + 1])}
+        # ---- Lanczos steps ell = l0+2 .. nb
+        for ell in range(l0 + 2, nb + 1):
+            c = (ell - 1) * d
+            ql = zb[:, c:c + d]
+            p = bop(ql) - zb[:, c - d:c] @ gams[ell - 1].T
+            matvecs += d
+            xi = ql.T @ p
+            qn, g = block_qr(p - ql @ xi)
+            if full_reorth:
+                qn, g2 = block_qr(cgs2(zb[:, :c + d], qn))
+                g = g2 @ g
+            zb[:, c + d:c + 2 * d] = qn
+            xis[ell] = 0.5 * (xi + xi.T)
+            gams[ell] = g
+            n_xi[ell] = _fro(xis[ell])
+            n_gam[ell] = _fro(g)
+            wmax = wrec.next_column(ell, l0, u_d, n_theta, n_f, n_xi, n_gam, _inv_fro(g))
+            if track_orth:
+                true = float(np.max(np.abs(zb[:, :c + d].T @ zb[:, c + d:c + 2 * d])))
+                orth_trace.append((ell, wmax, true))
+            if not full_reorth and wmax > u_ro:
+                # reorthogonalise Q_ell and Q_{ell+1} against Z_{ell-1} (Sec. 4.2)
+                blk = cgs2(zb[:, :c], zb[:, c:c + 2 * d])
+                qlr, _ = block_qr(blk[:, :d])
+                qnr, _ = block_qr(cgs2(qlr, blk[:, d:]))
+                zb[:, c:c + d] = qlr
+                zb[:, c + d:c + 2 * d] = qnr
+                wrec.reset_column(ell, u_d)
+                wrec.reset_column(ell + 1, u_d)
+                reorths += 1
+        # ---- Rayleigh-Ritz on T_ell (Alg. 2, after the inner loop)
+        t = _assemble_t(theta_kept, f, xis, gams, l0, nb, d)
+        theta, vz = np.linalg.eigh(t)
+        n_ell = int(np.sum(theta < 3.0 * eps))
+        history.append((matvecs, n_ell))
+        stop, _ = speed_rule(history, d)
+        out_of_budget = matvecs >= max_matvec or (max_cycles is not None and restarts + 1 >= max_cycles)
+        if stop or out_of_budget:
+            v = zb[:, :dim_k] @ vz[:, :n_ell]
+            return dict(V=v, N=n_ell, theta=theta, matvecs=matvecs, restarts=restarts,
+                        reorths=reorths, history=history, converged=bool(stop),
+                        orth_trace=orth_trace, u_d=u_d)
+        # ---- thick restart (Sec. 4.1)
+        k_keep = restart_size(n_ell, dim_k, d)
+        if n_ell > k_keep:
+            raise RuntimeError("dim_k too small for the detected nullity")
+        z_new = zb[:, :dim_k] @ vz[:, :k_keep]
+        q_last = zb[:, dim_k:dim_k + d]
+        qn, r = block_qr(cgs2(z_new, q_last))
+        f = r @ gams[nb] @ vz[dim_k - d:dim_k, :k_keep]
+        theta_kept = theta[:k_keep].copy()
+        zb[:, :k_keep] = z_new
+        zb[:, k_keep:k_keep + d] = qn
+        l0 = k_keep // d
+        restarts += 1
+        norm_b = float(np.max(theta))  # reading R7
+        u_d = d * math.sqrt(n) * U * norm_b
