@@ -1,0 +1,176 @@
+/*
+ * nullspace.h -- C ABI of the MI355X null-space library.
+ *
+ * The library computes an orthonormal basis V (n x N) of the null space of a
+ * large sparse A (m x n, CSR) with the randomized small-block Lanczos method
+ * of Kressner & Shao, "On a randomized small-block Lanczos method for
+ * large-scale null space computations": block Lanczos with block size d >= 1
+ * on B = A^T A + eps D (Eq. "defB", Sec. 1.2), D a random diagonal with iid
+ * U[0,1) entries and a Gaussian start block Omega (Alg. 1), thick restarts with
+ * Ritz vectors (Sec. 4.1), partial reorthogonalisation monitored by the
+ * W-recurrence (Sec. 4.2), adaptive nullity detection N = #{theta < 3 eps}
+ * (Remark "cormain") and the convergence-speed stop (Alg. 2, Sec. 4.3).
+ * B is applied matrix-free as y = A x, z = A^T y + eps D x (Sec. 1.2), with A^T
+ * stored as its own CSR so the second product needs no atomics.
+ *
+ * Beyond the paper: an FP64 refinement of the Ritz basis (Rayleigh-Ritz with
+ * the perturbation removed, as in the Remark after Alg. 1, then a projection
+ * onto null(A) by range-restricted CGLS), a backward pass (gradient of a loss on
+ * the null projector P = V V^T w.r.t. the stored values of A), and a mixed
+ * precision mode.
+ *
+ * Conventions for every call:
+ *  - Array arguments are DEVICE pointers (HIP, gfx950) owned by the caller,
+ *    unless a comment says "host".  The library never frees caller memory.
+ *  - Dense matrices are column-major with an explicit leading dimension.
+ *  - All GPU work is ordered on the stream passed to nullspace_init.  Calls
+ *    that return host data synchronise that stream before returning.
+ *  - Every call returns an nsp_status; no C++ exception crosses the ABI.  On
+ *    failure nullspace_last_error() returns a message for the calling thread.
+ *  - A context is not thread-safe; distinct contexts are independent.
+ */
+#ifndef NULLSPACE_H
+#define NULLSPACE_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct nsp_ctx nsp_ctx;
+
+typedef enum {
+  NSP_OK = 0,
+  NSP_ERR_ARG = 1,       /* invalid argument (shape, pointer, parameter)            */
+  NSP_ERR_HIP = 2,       /* a HIP / rocBLAS / rocSOLVER call failed                 */
+  NSP_ERR_NOMEM = 3,     /* device allocation failed                                */
+  NSP_ERR_STATE = 4,     /* call out of order (e.g. extract_basis before the solve) */
+  NSP_ERR_NOCONV = 5,    /* matvec budget exhausted before the stopping rule fired;
+                            the basis from the last cycle is still extractable      */
+  NSP_ERR_BREAKDOWN = 6, /* a Lanczos block lost rank (invariant Krylov subspace)   */
+  NSP_ERR_NONFINITE = 7  /* NaN/Inf met in the input or during the iteration        */
+} nsp_status;
+
+typedef enum {
+  NSP_PREC_FP64 = 0,  /* everything in FP64                                          */
+  NSP_PREC_MIXED = 1  /* FP32 SpMV, FP32 basis and reorthogonalisation; FP64 for the
+                         T / Ritz eigenproblem, the Lanczos scalars, the refinement,
+                         the residual check and the backward pass                    */
+} nsp_precision;
+
+/* Solver parameters (host struct).  nsp_default_params() fills defaults. */
+typedef struct {
+  double eps;            /* perturbation strength eps > 0 (Eq. "defB"); the paper's
+                            analysis needs eps < sigma_min(A)^2 / 3 (Thm. "thmmain") */
+  int32_t d;             /* block size, 1..8                                         */
+  int32_t max_dim;       /* dim K: maximum Krylov dimension, multiple of d, >= 3d    */
+  int64_t max_matvec;    /* budget of single-vector B applications                   */
+  double ro_tol;         /* reorthogonalisation threshold u_RO; 0 -> sqrt(u)          */
+  int32_t prec;          /* nsp_precision                                            */
+  int32_t refine;        /* 1: run the FP64 refinement after the Lanczos iteration   */
+  double tol_rel_resid;  /* refinement stops a column once ||A v|| <= this * ||A||_F  */
+  double tol_abs_resid;  /* ... or once ||A v|| <= this (absolute); the larger
+                            threshold of the two applies; 0 disables a criterion      */
+  int64_t max_refine_iter; /* CGLS iteration cap of the refinement                   */
+  int32_t max_cycles;    /* stop after this many restart cycles (0 = no limit)       */
+  uint64_t seed;         /* seed of the built-in Philox4x32-10 draws of D and Omega,
+                            used only when the caller passes D or Omega as NULL       */
+} nsp_params;
+
+/* Statistics of the last lanczos_run (host struct). */
+typedef struct {
+  int32_t nullity;         /* N: number of Ritz values below 3 eps at the end         */
+  int32_t converged;       /* 1 if the convergence-speed rule stopped the iteration   */
+  int32_t restarts;        /* number of thick restarts                                */
+  int32_t cycles;          /* number of Rayleigh-Ritz extractions                     */
+  int64_t matvecs;         /* single-vector applications of B                          */
+  int64_t reorths;         /* partial reorthogonalisation events                       */
+  int64_t refine_iters;    /* CGLS iterations of the refinement                        */
+  double norm_b;           /* ||B|| estimate used in u_d                               */
+  double theta_last;       /* largest Ritz value below 3 eps                           */
+  double theta_next;       /* smallest Ritz value at or above 3 eps                    */
+  double rel_resid_fro;    /* ||A V||_F / ||A||_F after refinement (FP64)               */
+  double orth_err_fro;     /* ||V^T V - I||_F                                           */
+  double t_total_s;        /* wall time of lanczos_run                                  */
+  double t_lanczos_s;      /* time in the Lanczos steps (device events)                 */
+  double t_restart_s;      /* time in Rayleigh-Ritz + restarts                          */
+  double t_refine_s;       /* time in the refinement                                    */
+} nsp_stats;
+
+/* Fill *p with defaults: eps = 1e-3 (Sec. 5.3), d = 1, max_dim = 64,
+   max_matvec = 10^7, ro_tol = 0, prec = FP64, refine = 1, tol_rel_resid = 1e-10,
+   tol_abs_resid = 0, max_refine_iter = 10^6, max_cycles = 0, seed = 20240704. */
+void nsp_default_params(nsp_params* p);
+
+/* Create a solver context for A (m x n, nnz stored entries, CSR).
+ *  rowptr  [m+1] int64, device; rowptr[0] = 0, non-decreasing, rowptr[m] = nnz.
+ *  colind  [nnz] int32, device; 0 <= colind < n.
+ *  vals    [nnz] float64, device; must stay valid and unchanged until destroy
+ *          (the context keeps the pointer, and copies it for A^T).
+ *  D       [n] float64, device or NULL: the perturbation diagonal (entries in
+ *          [0,1]); NULL -> drawn with Philox4x32-10 (Salmon et al., SC'11) from
+ *          p->seed.  Copied.
+ *  Omega   [n x d] float64 column-major (ld = n), device or NULL: the Gaussian
+ *          start block; NULL -> drawn with Philox + Box-Muller.  Copied.
+ *  p       host parameters (copied).
+ *  stream  hipStream_t to order all work on (NULL = default stream).
+ * Builds the transposed CSR (A^T) once.  nnz must be < 2^31.
+ * Errors: NSP_ERR_ARG (shape, NULL pointer, bad parameter, colind out of range),
+ *         NSP_ERR_NOMEM, NSP_ERR_HIP.  On error *out is NULL. */
+nsp_status nullspace_init(nsp_ctx** out, int64_t m, int64_t n, int64_t nnz,
+                          const int64_t* rowptr, const int32_t* colind, const double* vals,
+                          const double* D, const double* Omega, const nsp_params* p,
+                          void* stream);
+
+/* Y = B X = A^T (A X) + eps D X for ncols >= 1 columns (Sec. 1.2).
+ *  X [n x ncols], ld ldx >= n; Y [n x ncols], ld ldy >= n; device, FP64.
+ *  Uses the FP64 values regardless of the precision mode.  X and Y must not
+ *  overlap.  Allowed in any state after init. */
+nsp_status apply_op(nsp_ctx* ctx, const double* X, int64_t ldx, double* Y, int64_t ldy,
+                    int32_t ncols);
+
+/* Run Algorithm 2 (Sec. 4.3) and, if p->refine, the FP64 refinement.
+ *  st  host, may be NULL.
+ * Returns NSP_OK, or NSP_ERR_NOCONV when the budget ran out (the basis of the
+ * last cycle is kept and extractable), NSP_ERR_BREAKDOWN, NSP_ERR_NONFINITE,
+ * NSP_ERR_HIP.  May be called again to re-solve (the state is reset). */
+nsp_status lanczos_run(nsp_ctx* ctx, nsp_stats* st);
+
+/* Nullity N found by the last lanczos_run (host out). */
+nsp_status nullspace_nullity(nsp_ctx* ctx, int32_t* nullity);
+
+/* Copy V (n x N, FP64, orthonormal columns) into V [ldv >= n], device.
+ * Errors: NSP_ERR_STATE before a successful (or NOCONV) lanczos_run. */
+nsp_status extract_basis(nsp_ctx* ctx, double* V, int64_t ldv);
+
+/* Ritz values of the last Rayleigh-Ritz extraction, ascending (host out).
+ *  theta  host buffer of capacity cap; *count receives the number written
+ *  (min(cap, dim K)).  Before refinement, i.e. eigenvalues of T_ell. */
+nsp_status nullspace_ritz_values(nsp_ctx* ctx, double* theta, int32_t cap, int32_t* count);
+
+/* Backward pass for a loss L(P), P = V V^T, with V from extract_basis.
+ *  GsV        [n x N], ld >= n, device: G_s V where G_s is the symmetric part
+ *             of dL/dP.  (For dL/dV of a loss that depends on V only through P,
+ *             G_s V = (dL/dV) / 2.)
+ *  grad_vals  [nnz], device, out: dL/d vals in A's CSR order,
+ *             grad_p = -2 <(A W)_i, V_j> for the stored entry p = (i, j), where
+ *             W = (A^T A)^+ (I - V V^T) G_s V is computed by CG on A^T A
+ *             restricted to range(A^T).
+ *  tol        relative CG residual target per column (e.g. 1e-12).
+ *  max_iter   CG iteration cap; the call returns NSP_ERR_NOCONV if reached.
+ *  iters      host out (nullable): CG iterations used. */
+nsp_status backward(nsp_ctx* ctx, const double* GsV, int64_t ld, double* grad_vals, double tol,
+                    int64_t max_iter, int64_t* iters);
+
+/* Release everything the context owns.  NULL is accepted. */
+void nullspace_destroy(nsp_ctx* ctx);
+
+/* Message describing the last error on the calling thread ("" if none). */
+const char* nullspace_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* NULLSPACE_H */

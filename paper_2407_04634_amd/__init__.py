@@ -1,0 +1,15 @@
+"""MI355X-native randomized small-block Lanczos null-space solver.
+
+The numerical work runs in ``libnullspace.so`` (hand-written HIP for gfx950,
+C ABI in ``include/nullspace.h``); this package only marshals arguments.
+"""
+from ._lib import (  # noqa: F401
+    Context,
+    NspError,
+    Params,
+    Stats,
+    default_params,
+    load,
+    PREC_FP64,
+    PREC_MIXED,
+)

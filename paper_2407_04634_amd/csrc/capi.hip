@@ -1,0 +1,190 @@
+// C ABI entry points (include/nullspace.h).  Validation, error codes, the
+// thread-local error message and context ownership live here; the numerical
+// work is in kernels_*.hip and solver.hip.
+#include <cmath>
+#include <cstring>
+
+#include "common.h"
+
+namespace {
+
+thread_local std::string g_last_error;
+
+template <typename F>
+nsp_status guarded(F&& f) {
+  try {
+    g_last_error.clear();
+    f();
+    return NSP_OK;
+  } catch (const nsp::Error& e) {
+    g_last_error = e.what();
+    return e.code;
+  } catch (const std::bad_alloc&) {
+    g_last_error = "host allocation failed";
+    return NSP_ERR_NOMEM;
+  } catch (const std::exception& e) {
+    g_last_error = e.what();
+    return NSP_ERR_HIP;
+  } catch (...) {
+    g_last_error = "unknown error";
+    return NSP_ERR_HIP;
+  }
+}
+
+void validate_params(const nsp_params* p, int64_t n) {
+  NSP_REQUIRE(p != nullptr, "params must not be NULL");
+  NSP_REQUIRE(std::isfinite(p->eps) && p->eps > 0.0, "eps must be finite and > 0");
+  NSP_REQUIRE(p->d == 1 || p->d == 2 || p->d == 4 || p->d == 8, "d must be 1, 2, 4 or 8");
+  NSP_REQUIRE(p->max_dim % p->d == 0, "max_dim must be a multiple of d");
+  NSP_REQUIRE(p->max_dim >= 3 * p->d, "max_dim must be at least 3d");
+  NSP_REQUIRE((int64_t)p->max_dim + p->d <= n, "max_dim + d must not exceed n");
+  NSP_REQUIRE(p->max_dim <= 8192, "max_dim must be at most 8192");
+  NSP_REQUIRE(p->max_matvec > 0, "max_matvec must be positive");
+  NSP_REQUIRE(p->prec == NSP_PREC_FP64 || p->prec == NSP_PREC_MIXED, "unknown precision mode");
+  NSP_REQUIRE(p->ro_tol >= 0.0 && p->ro_tol < 1.0, "ro_tol must be in [0, 1)");
+  NSP_REQUIRE(p->tol_rel_resid >= 0.0 && p->tol_abs_resid >= 0.0, "tolerances must be >= 0");
+  NSP_REQUIRE(p->max_cycles >= 0, "max_cycles must be >= 0");
+}
+
+}  // namespace
+
+extern "C" {
+
+void nsp_default_params(nsp_params* p) {
+  if (!p) return;
+  std::memset(p, 0, sizeof(*p));
+  p->eps = 1e-3;
+  p->d = 1;
+  p->max_dim = 64;
+  p->max_matvec = 10000000;
+  p->ro_tol = 0.0;
+  p->prec = NSP_PREC_FP64;
+  p->refine = 1;
+  p->tol_rel_resid = 1e-10;
+  p->tol_abs_resid = 0.0;
+  p->max_refine_iter = 1000000;
+  p->max_cycles = 0;
+  p->seed = 20240704ull;
+}
+
+nsp_status nullspace_init(nsp_ctx** out, int64_t m, int64_t n, int64_t nnz, const int64_t* rowptr,
+                          const int32_t* colind, const double* vals, const double* D,
+                          const double* Omega, const nsp_params* p, void* stream) {
+  if (out) *out = nullptr;
+  nsp_ctx* c = nullptr;
+  nsp_status st = guarded([&] {
+    NSP_REQUIRE(out != nullptr, "out must not be NULL");
+    NSP_REQUIRE(m >= 1 && n >= 1, "m and n must be >= 1");
+    NSP_REQUIRE(nnz >= 0 && nnz < 2147483647LL, "nnz must be in [0, 2^31)");
+    NSP_REQUIRE(m < 2147483647LL && n < 2147483647LL, "m and n must be < 2^31");
+    NSP_REQUIRE(rowptr != nullptr, "rowptr must not be NULL");
+    NSP_REQUIRE(nnz == 0 || (colind != nullptr && vals != nullptr), "colind/vals must not be NULL");
+    validate_params(p, n);
+    c = new nsp_ctx();
+    c->m = m;
+    c->n = n;
+    c->nnz = nnz;
+    c->prm = *p;
+    c->stream = static_cast<hipStream_t>(stream);
+    NSP_BLAS(rocblas_create_handle(&c->blas));
+    NSP_BLAS(rocblas_set_stream(c->blas, c->stream));
+    c->A.colind = colind;
+    c->A.val = vals;
+    // reduction scratch (shared by all kernels of the context; stream-ordered)
+    c->red_partials.alloc(sizeof(double) * nsp::kRedBlocks * 256);
+    c->red_counters.alloc(sizeof(unsigned) * 16);
+    NSP_HIP(hipMemsetAsync(c->red_counters.p, 0, sizeof(unsigned) * 16, c->stream));
+    c->red.partials = c->red_partials.as<double>();
+    c->red.counter = c->red_counters.as<unsigned>();
+    c->red.max_blocks = nsp::kRedBlocks;
+    c->red.max_values = 256;
+    nsp::build_transpose(c, rowptr);
+    nsp::init_random(c, D, Omega);
+    nsp::matrix_norms(c);
+    NSP_HIP(hipStreamSynchronize(c->stream));
+  });
+  if (st != NSP_OK) {
+    if (c) nullspace_destroy(c);
+    return st;
+  }
+  *out = c;
+  return NSP_OK;
+}
+
+nsp_status apply_op(nsp_ctx* ctx, const double* X, int64_t ldx, double* Y, int64_t ldy,
+                    int32_t ncols) {
+  return guarded([&] {
+    NSP_REQUIRE(ctx != nullptr, "ctx must not be NULL");
+    NSP_REQUIRE(ncols >= 1, "ncols must be >= 1");
+    NSP_REQUIRE(X != nullptr && Y != nullptr, "X and Y must not be NULL");
+    NSP_REQUIRE(ldx >= ctx->n && ldy >= ctx->n, "leading dimensions must be >= n");
+    nsp::apply_b_colmajor(ctx, X, ldx, Y, ldy, ncols);
+  });
+}
+
+nsp_status lanczos_run(nsp_ctx* ctx, nsp_stats* st) {
+  nsp_status s = guarded([&] {
+    NSP_REQUIRE(ctx != nullptr, "ctx must not be NULL");
+    nsp::solve(ctx);
+  });
+  if (ctx && st) *st = ctx->stats;
+  if (s == NSP_OK && ctx && !ctx->stats.converged) {
+    g_last_error = "matvec budget or cycle limit reached before the stopping rule fired";
+    return NSP_ERR_NOCONV;
+  }
+  return s;
+}
+
+nsp_status nullspace_nullity(nsp_ctx* ctx, int32_t* nullity) {
+  return guarded([&] {
+    NSP_REQUIRE(ctx != nullptr && nullity != nullptr, "arguments must not be NULL");
+    NSP_REQUIRE(ctx->state >= 1, "no basis yet: call lanczos_run first");
+    *nullity = ctx->nullity;
+  });
+}
+
+nsp_status extract_basis(nsp_ctx* ctx, double* V, int64_t ldv) {
+  return guarded([&] {
+    NSP_REQUIRE(ctx != nullptr, "ctx must not be NULL");
+    if (ctx->state < 1) throw nsp::Error(NSP_ERR_STATE, "no basis yet: call lanczos_run first");
+    if (ctx->nullity == 0) return;
+    NSP_REQUIRE(V != nullptr && ldv >= ctx->n, "V must be non-NULL with ldv >= n");
+    NSP_HIP(hipMemcpy2DAsync(V, sizeof(double) * ldv, ctx->V.p, sizeof(double) * ctx->n,
+                             sizeof(double) * ctx->n, ctx->nullity, hipMemcpyDeviceToDevice,
+                             ctx->stream));
+    NSP_HIP(hipStreamSynchronize(ctx->stream));
+  });
+}
+
+nsp_status nullspace_ritz_values(nsp_ctx* ctx, double* theta, int32_t cap, int32_t* count) {
+  return guarded([&] {
+    NSP_REQUIRE(ctx != nullptr && count != nullptr, "arguments must not be NULL");
+    NSP_REQUIRE(cap >= 0 && (cap == 0 || theta != nullptr), "theta must hold cap values");
+    const int32_t k = (int32_t)std::min<size_t>((size_t)cap, ctx->ritz.size());
+    for (int32_t i = 0; i < k; ++i) theta[i] = ctx->ritz[i];
+    *count = k;
+  });
+}
+
+nsp_status backward(nsp_ctx* ctx, const double* GsV, int64_t ld, double* grad_vals, double tol,
+                    int64_t max_iter, int64_t* iters) {
+  return guarded([&] {
+    NSP_REQUIRE(ctx != nullptr, "ctx must not be NULL");
+    if (ctx->state < 1) throw nsp::Error(NSP_ERR_STATE, "no basis yet: call lanczos_run first");
+    NSP_REQUIRE(grad_vals != nullptr || ctx->nnz == 0, "grad_vals must not be NULL");
+    NSP_REQUIRE(ctx->nullity == 0 || (GsV != nullptr && ld >= ctx->n), "GsV must be n x N, ld >= n");
+    NSP_REQUIRE(tol > 0.0 && max_iter > 0, "tol and max_iter must be positive");
+    nsp::run_backward(ctx, GsV, ld, grad_vals, tol, max_iter, iters);
+  });
+}
+
+void nullspace_destroy(nsp_ctx* ctx) {
+  if (!ctx) return;
+  if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
+  if (ctx->blas) (void)rocblas_destroy_handle(ctx->blas);
+  delete ctx;
+}
+
+const char* nullspace_last_error(void) { return g_last_error.c_str(); }
+
+}  // extern "C"

@@ -1,0 +1,163 @@
+// Internal declarations shared by the library's translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <rocblas/rocblas.h>
+#include <rocsolver/rocsolver.h>
+
+#include <cstdint>
+#include <cstdio>
+#include <stdexcept>
+#include <string>
+#include <vector>
+
+#include "nullspace.h"
+
+namespace nsp {
+
+// ---------------------------------------------------------------------------
+// error handling: internal code throws nsp::Error, the C ABI converts it
+// ---------------------------------------------------------------------------
+struct Error : std::runtime_error {
+  nsp_status code;
+  Error(nsp_status c, const std::string& m) : std::runtime_error(m), code(c) {}
+};
+
+#define NSP_HIP(call)                                                                     \
+  do {                                                                                    \
+    hipError_t e_ = (call);                                                               \
+    if (e_ != hipSuccess)                                                                 \
+      throw ::nsp::Error(e_ == hipErrorOutOfMemory ? NSP_ERR_NOMEM : NSP_ERR_HIP,         \
+                         std::string(#call) + ": " + hipGetErrorString(e_));              \
+  } while (0)
+
+#define NSP_BLAS(call)                                                                    \
+  do {                                                                                    \
+    rocblas_status s_ = (call);                                                           \
+    if (s_ != rocblas_status_success)                                                     \
+      throw ::nsp::Error(NSP_ERR_HIP, std::string(#call) + ": rocblas status " +          \
+                                          std::to_string((int)s_));                       \
+  } while (0)
+
+#define NSP_REQUIRE(cond, msg)                                                            \
+  do {                                                                                    \
+    if (!(cond)) throw ::nsp::Error(NSP_ERR_ARG, msg);                                    \
+  } while (0)
+
+// ---------------------------------------------------------------------------
+// device buffer owned by the context
+// ---------------------------------------------------------------------------
+struct DBuf {
+  void* p = nullptr;
+  size_t bytes = 0;
+  DBuf() = default;
+  DBuf(const DBuf&) = delete;
+  DBuf& operator=(const DBuf&) = delete;
+  ~DBuf() { release(); }
+  void alloc(size_t b) {
+    if (b <= bytes && p) return;
+    release();
+    if (b == 0) return;
+    NSP_HIP(hipMalloc(&p, b));
+    bytes = b;
+  }
+  void release() {
+    if (p) (void)hipFree(p);
+    p = nullptr;
+    bytes = 0;
+  }
+  template <typename T> T* as() const { return static_cast<T*>(p); }
+};
+
+// Reduction scratch for the "last block finishes the reduction" pattern:
+// per-block partials plus an arrival counter that the last block resets.
+struct Reducer {
+  double* partials = nullptr;  // capacity: max_blocks * max_values doubles
+  unsigned* counter = nullptr; // one counter per concurrent use site
+  int max_blocks = 0;
+  int max_values = 0;
+};
+
+constexpr int kMaxD = 8;            // largest supported block size
+constexpr int kRedBlocks = 512;     // grid cap of kernels that reduce
+constexpr int kThreads = 256;       // threads per block of streaming kernels
+
+// ---------------------------------------------------------------------------
+// the context
+// ---------------------------------------------------------------------------
+struct Csr {
+  int64_t rows = 0, cols = 0, nnz = 0;
+  const int32_t* rowptr = nullptr;  // int32 offsets (device)
+  const int32_t* colind = nullptr;
+  const double* val = nullptr;
+  const float* val32 = nullptr;
+  int lpr = 1;                      // lanes per row chosen from the mean row length
+};
+
+}  // namespace nsp
+
+struct nsp_ctx {
+  int64_t m = 0, n = 0, nnz = 0;
+  nsp_params prm{};
+  hipStream_t stream = nullptr;
+  rocblas_handle blas = nullptr;
+
+  // A (caller's colind/vals; own int32 row offsets) and its stored transpose
+  nsp::Csr A, AT;
+  nsp::DBuf rowptr32, rowptrT, colindT, valsT, permT, vals32, valsT32;
+  double normA_fro = 0.0;
+  double normA1_inf = 0.0;  // ||A||_1 * ||A||_inf
+
+  // perturbation diagonal and start block
+  nsp::DBuf Dv, omega;
+
+  // Lanczos state (working precision: 8 or 4 bytes per element)
+  int esize = 8;
+  int64_t ldz = 0;          // leading dimension of the basis (>= n, padded)
+  nsp::DBuf Z, Z2;          // basis, n x (K + d), column-major; Z2 for the restart
+  nsp::DBuf ring;           // 3 row-interleaved copies of consecutive blocks (d > 1)
+  nsp::DBuf Y;              // m x d, row-interleaved, working precision
+  nsp::DBuf P;              // n x d, row-interleaved, working precision
+  nsp::DBuf C;              // n x 2d row-interleaved scratch (reorthogonalisation)
+  nsp::DBuf H;              // k x 2d coefficients (FP64)
+  nsp::DBuf xi, gam;        // (L+2) blocks of d x d (FP64), column-major
+  nsp::DBuf rinv;           // d x d (and 2d x 2d) inverse triangular factors
+  nsp::DBuf wmat;           // (L+3)^2 W-recurrence bounds
+  nsp::DBuf theta_kept;     // K Ritz values kept at the last restart
+  nsp::DBuf fmat;           // d x K coupling block F
+  nsp::DBuf tmat, evals, ework; // T (K x K), eigenvalues, rocSOLVER E workspace
+  nsp::DBuf flags;          // device ints: [0] reorth flag, [1] breakdown, [2] nonfinite,
+                            // [3] reorth event counter
+  nsp::DBuf red_partials, red_counters;
+  nsp::Reducer red;
+  int* dinfo = nullptr;
+
+  // result
+  nsp::DBuf V;              // n x N column-major FP64 (final basis)
+  int32_t nullity = 0;
+  int state = 0;            // 0 = initialised, 1 = basis available
+  std::vector<double> ritz; // last Ritz values (host)
+  nsp_stats stats{};
+};
+
+namespace nsp {
+
+// launchers implemented in kernels_*.hip -----------------------------------
+void build_transpose(nsp_ctx* c, const int64_t* rowptr64);
+void init_random(nsp_ctx* c, const double* D, const double* Omega);
+double matrix_norms(nsp_ctx* c);
+
+// y(m x d) = A x ; generic strides: element (i, j) of x at x[i*xrs + j*xcs]
+template <typename VT>
+void spmm(nsp_ctx* c, const Csr& a, int d, const VT* x, int64_t xrs, int64_t xcs, VT* y,
+          int64_t yrs, int64_t ycs);
+
+// apply_op helper: Y = B X (FP64, column-major, ld)
+void apply_b_colmajor(nsp_ctx* c, const double* X, int64_t ldx, double* Y, int64_t ldy, int ncols);
+
+// Lanczos solve (solver.hip)
+void solve(nsp_ctx* c);
+void run_backward(nsp_ctx* c, const double* GsV, int64_t ld, double* grad, double tol,
+                  int64_t max_iter, int64_t* iters);
+
+}  // namespace nsp

@@ -1,0 +1,532 @@
+// Sparse kernels: CSR SpMM (y = A x), the fused transposed product of one
+// Lanczos step (z = A^T y + eps D x - X_prev Gamma^T, with the Xi dots),
+// wide SpMM for many right-hand sides, SDDMM, and the set-up work of
+// nullspace_init (stored transpose, random draws, norms).
+//
+// The operator B = A^T A + eps D is applied matrix-free exactly as in Sec. 1.2
+// of the paper: one CSR product with A, one with the stored CSR of A^T.
+// Row-interleaved blocks: a block of d columns is stored n x d row-major so a
+// gather of row c of the block reads d contiguous values.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <numeric>
+
+#include "common.h"
+#include "device_util.h"
+#include "kernels.h"
+
+namespace nsp {
+
+// ---------------------------------------------------------------------------
+// y(rows x D) = A x, narrow blocks (D <= 8); LPR lanes cooperate on one row.
+// ---------------------------------------------------------------------------
+template <typename VT, int D, int LPR>
+__global__ __launch_bounds__(kThreads) void k_spmm(int64_t nrows, const int32_t* __restrict__ rp,
+                                                   const int32_t* __restrict__ ci,
+                                                   const VT* __restrict__ av,
+                                                   const VT* __restrict__ x, VT* __restrict__ y) {
+  const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t row = g / LPR;
+  const int lane = threadIdx.x % LPR;
+  VT acc[D];
+#pragma unroll
+  for (int j = 0; j < D; ++j) acc[j] = VT(0);
+  if (row < nrows) {
+    const int beg = rp[row], end = rp[row + 1];
+    for (int p = beg + lane; p < end; p += LPR) {
+      const VT a = av[p];
+      const VT* xr = x + (int64_t)ci[p] * D;
+#pragma unroll
+      for (int j = 0; j < D; ++j) acc[j] = fma(a, xr[j], acc[j]);
+    }
+  }
+#pragma unroll
+  for (int j = 0; j < D; ++j) acc[j] = group_sum<VT, LPR>(acc[j]);
+  if (row < nrows && lane == 0) {
+#pragma unroll
+    for (int j = 0; j < D; ++j) y[row * D + j] = acc[j];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// One Lanczos step's second product, fused (Alg. 2 inner loop):
+//   P = A^T Y + eps D X  [- Xp Gamma_prev^T]            (three-term recurrence)
+//   Xi = X^T P  (D x D, reduced over the grid, symmetrised)  when XI is set
+// Y (m x D), X, Xp, P (n x D) row-interleaved.  Gamma_prev is D x D column-major.
+// ---------------------------------------------------------------------------
+template <typename VT, int D, int LPR, bool PREV, bool XI>
+__global__ __launch_bounds__(kThreads) void k_spmmT_step(
+    int64_t nrows, const int32_t* __restrict__ rp, const int32_t* __restrict__ ci,
+    const VT* __restrict__ av, const VT* __restrict__ y, const VT* __restrict__ x,
+    const double* __restrict__ dv, double eps, const VT* __restrict__ xp,
+    const double* __restrict__ gprev, VT* __restrict__ out, double* partials, unsigned* counter,
+    double* xi_out, double* xi_nrm) {
+  __shared__ double smem[kThreads > D * D * (kThreads / kWave) ? kThreads : D * D * (kThreads / kWave)];
+  __shared__ double gp[D * D];
+  if (PREV) {
+    if (threadIdx.x < D * D) gp[threadIdx.x] = gprev[threadIdx.x];
+    __syncthreads();
+  }
+  constexpr int NV = XI ? D * D : 1;
+  double dots[NV];
+#pragma unroll
+  for (int i = 0; i < NV; ++i) dots[i] = 0.0;
+  const int lane = threadIdx.x % LPR;
+  const int64_t rows_per_grid = (int64_t)gridDim.x * (blockDim.x / LPR);
+  // grid-stride over rows; the LPR lanes of a group always share ``row``
+  for (int64_t row = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / LPR; row < nrows;
+       row += rows_per_grid) {
+    VT acc[D];
+#pragma unroll
+    for (int j = 0; j < D; ++j) acc[j] = VT(0);
+    const int beg = rp[row], end = rp[row + 1];
+    for (int p = beg + lane; p < end; p += LPR) {
+      const VT a = av[p];
+      const VT* yr = y + (int64_t)ci[p] * D;
+#pragma unroll
+      for (int j = 0; j < D; ++j) acc[j] = fma(a, yr[j], acc[j]);
+    }
+#pragma unroll
+    for (int j = 0; j < D; ++j) acc[j] = group_sum<VT, LPR>(acc[j]);
+    if (lane == 0) {
+      const VT sd = VT(eps * dv[row]);
+      VT xr[D];
+#pragma unroll
+      for (int j = 0; j < D; ++j) xr[j] = x[row * D + j];
+#pragma unroll
+      for (int j = 0; j < D; ++j) acc[j] = fma(sd, xr[j], acc[j]);
+      if (PREV) {
+        VT pr[D];
+#pragma unroll
+        for (int j = 0; j < D; ++j) pr[j] = xp[row * D + j];
+#pragma unroll
+        for (int a = 0; a < D; ++a) {
+          VT s = acc[a];
+#pragma unroll
+          for (int b = 0; b < D; ++b) s = fma(-pr[b], VT(gp[a + b * D]), s);
+          acc[a] = s;
+        }
+      }
+#pragma unroll
+      for (int j = 0; j < D; ++j) out[row * D + j] = acc[j];
+      if constexpr (XI) {
+#pragma unroll
+        for (int a = 0; a < D; ++a)
+#pragma unroll
+          for (int b = 0; b < D; ++b) dots[a * D + b] += (double)xr[a] * (double)acc[b];
+      }
+    }
+  }
+  if constexpr (XI) {
+    block_sum<NV>(dots, smem);
+    __shared__ double res[NV];
+    if (grid_sum_last<NV>(dots, partials, counter, res, smem)) {
+      if (threadIdx.x == 0) {
+        double f2 = 0.0;
+        for (int i = 0; i < NV; ++i) {
+          const int a = i % D, b = i / D;
+          const double v = 0.5 * (res[a * D + b] + res[b * D + a]);
+          xi_out[i] = v;
+          f2 += v * v;
+        }
+        if (xi_nrm) *xi_nrm = sqrt(f2);
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// wide SpMM: y(rows x k) = A x(n x k), row-major, one wavefront per row,
+// lanes over the k columns.  Used by the refinement and the backward pass.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(kThreads) void k_spmm_wide(int64_t nrows, int k,
+                                                        const int32_t* __restrict__ rp,
+                                                        const int32_t* __restrict__ ci,
+                                                        const double* __restrict__ av,
+                                                        const double* __restrict__ x,
+                                                        double* __restrict__ y) {
+  const int64_t row = (int64_t)blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave;
+  const int lane = threadIdx.x % kWave;
+  if (row >= nrows) return;
+  const int beg = rp[row], end = rp[row + 1];
+  for (int c0 = 0; c0 < k; c0 += kWave) {
+    const int c = c0 + lane;
+    double acc = 0.0;
+    if (c < k) {
+      for (int p = beg; p < end; ++p) acc = fma(av[p], x[(int64_t)ci[p] * k + c], acc);
+      y[row * k + c] = acc;
+    }
+  }
+}
+
+// SDDMM on A's pattern: grad[p] = -2 <U_i, V_j> for p = (i, j); U (m x k), V (n x k) row-major.
+__global__ __launch_bounds__(kThreads) void k_sddmm(int64_t nrows, int k, const int32_t* __restrict__ rp,
+                                                    const int32_t* __restrict__ ci,
+                                                    const double* __restrict__ u,
+                                                    const double* __restrict__ v,
+                                                    double* __restrict__ grad) {
+  const int64_t row = (int64_t)blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave;
+  const int lane = threadIdx.x % kWave;
+  if (row >= nrows) return;
+  const int beg = rp[row], end = rp[row + 1];
+  for (int p = beg; p < end; ++p) {
+    const int64_t col = ci[p];
+    double s = 0.0;
+    for (int c = lane; c < k; c += kWave) s = fma(u[row * k + c], v[col * k + c], s);
+    s = wave_sum(s);
+    if (lane == 0) grad[p] = -2.0 * s;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// set-up kernels
+// ---------------------------------------------------------------------------
+__global__ void k_gather_vals(int64_t nnz, const int32_t* __restrict__ perm,
+                              const double* __restrict__ src, double* __restrict__ dst) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < nnz) dst[i] = src[perm[i]];
+}
+
+__global__ void k_to_f32(int64_t n, const double* __restrict__ src, float* __restrict__ dst) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) dst[i] = (float)src[i];
+}
+
+// per-row sums of |a| and a^2; a non-finite value sets flag[0]
+__global__ void k_row_abs_sums(int64_t nrows, const int32_t* __restrict__ rp,
+                               const double* __restrict__ av, double* __restrict__ rabs,
+                               double* __restrict__ rsq, int* flag) {
+  const int64_t row = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (row >= nrows) return;
+  double s = 0.0, q = 0.0;
+  bool bad = false;
+  for (int p = rp[row]; p < rp[row + 1]; ++p) {
+    const double a = av[p];
+    bad |= !isfinite(a);
+    s += fabs(a);
+    q += a * a;
+  }
+  rabs[row] = s;
+  if (rsq) rsq[row] = q;
+  if (bad) atomicOr(flag, 1);
+}
+
+// Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11): counter (i, stream, 0, 0),
+// key (seed low, seed high).  uniform53 builds a double in [0,1) from 53 random
+// bits; the normal pair comes from the Box-Muller transform.
+struct Philox {
+  __device__ static void round(uint32_t (&c)[4], uint32_t k0, uint32_t k1) {
+    const uint32_t M0 = 0xD2511F53u, M1 = 0xCD9E8D57u;
+    const uint64_t p0 = (uint64_t)M0 * c[0], p1 = (uint64_t)M1 * c[2];
+    const uint32_t hi0 = (uint32_t)(p0 >> 32), lo0 = (uint32_t)p0;
+    const uint32_t hi1 = (uint32_t)(p1 >> 32), lo1 = (uint32_t)p1;
+    uint32_t r0 = hi1 ^ c[1] ^ k0, r1 = lo1, r2 = hi0 ^ c[3] ^ k1, r3 = lo0;
+    c[0] = r0; c[1] = r1; c[2] = r2; c[3] = r3;
+  }
+  __device__ static void gen(uint64_t seed, uint32_t c0, uint32_t c1, uint32_t (&out)[4]) {
+    uint32_t c[4] = {c0, c1, 0u, 0u};
+    uint32_t k0 = (uint32_t)seed, k1 = (uint32_t)(seed >> 32);
+    for (int r = 0; r < 10; ++r) {
+      round(c, k0, k1);
+      k0 += 0x9E3779B9u;
+      k1 += 0xBB67AE85u;
+    }
+    out[0] = c[0]; out[1] = c[1]; out[2] = c[2]; out[3] = c[3];
+  }
+  __device__ static double u53(uint32_t a, uint32_t b) {
+    return ((double)(a >> 5) * 67108864.0 + (double)(b >> 6)) * (1.0 / 9007199254740992.0);
+  }
+};
+
+// D[i] = uniform53(philox(i, stream=0)) ; Omega[i + j*n] from stream j+1 via Box-Muller
+__global__ void k_philox_uniform(int64_t n, uint64_t seed, uint32_t stream, double* __restrict__ out) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  uint32_t r[4];
+  Philox::gen(seed, (uint32_t)i, stream, r);
+  out[i] = Philox::u53(r[0], r[1]);
+}
+
+__global__ void k_philox_normal(int64_t n, uint64_t seed, uint32_t stream, double* __restrict__ out) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  uint32_t r[4];
+  Philox::gen(seed, (uint32_t)i, stream, r);
+  const double u1 = 1.0 - Philox::u53(r[0], r[1]);  // (0, 1]
+  const double u2 = Philox::u53(r[2], r[3]);
+  out[i] = sqrt(-2.0 * log(u1)) * cos(2.0 * M_PI * u2);
+}
+
+// row-major (rows x k) <-> column-major (ld) conversions
+__global__ void k_colmajor_to_rows(int64_t rows, int k, const double* __restrict__ src, int64_t ld,
+                                   double* __restrict__ dst) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= rows * k) return;
+  const int64_t r = i / k, c = i % k;
+  dst[i] = src[r + c * ld];
+}
+
+__global__ void k_rows_to_colmajor(int64_t rows, int k, const double* __restrict__ src,
+                                   double* __restrict__ dst, int64_t ld) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= rows * k) return;
+  const int64_t c = i / rows, r = i % rows;
+  dst[r + c * ld] = src[r * k + c];
+}
+
+static inline unsigned nblocks(int64_t work, int per) { return (unsigned)((work + per - 1) / per); }
+
+// ---------------------------------------------------------------------------
+// host-side launchers
+// ---------------------------------------------------------------------------
+template <typename VT, int D>
+static void spmm_d(nsp_ctx* c, const Csr& a, const VT* x, VT* y) {
+  const VT* av = nullptr;
+  if constexpr (sizeof(VT) == 8) av = a.val; else av = a.val32;
+  if (a.rows == 0) return;
+#define NSP_SPMM_CASE(L)                                                                       \
+  case L:                                                                                      \
+    k_spmm<VT, D, L><<<nblocks(a.rows * L, kThreads), kThreads, 0, c->stream>>>(              \
+        a.rows, a.rowptr, a.colind, av, x, y);                                                 \
+    break;
+  switch (a.lpr) {
+    NSP_SPMM_CASE(1) NSP_SPMM_CASE(2) NSP_SPMM_CASE(4) NSP_SPMM_CASE(8) NSP_SPMM_CASE(16)
+    NSP_SPMM_CASE(32)
+    default: throw Error(NSP_ERR_ARG, "unsupported lanes-per-row");
+  }
+#undef NSP_SPMM_CASE
+  NSP_HIP(hipGetLastError());
+}
+
+template <typename VT>
+void spmm_block(nsp_ctx* c, const Csr& a, int d, const VT* x, VT* y) {
+  switch (d) {
+    case 1: spmm_d<VT, 1>(c, a, x, y); break;
+    case 2: spmm_d<VT, 2>(c, a, x, y); break;
+    case 4: spmm_d<VT, 4>(c, a, x, y); break;
+    case 8: spmm_d<VT, 8>(c, a, x, y); break;
+    default: throw Error(NSP_ERR_ARG, "block size must be 1, 2, 4 or 8");
+  }
+}
+template void spmm_block<double>(nsp_ctx*, const Csr&, int, const double*, double*);
+template void spmm_block<float>(nsp_ctx*, const Csr&, int, const float*, float*);
+
+template <typename VT, int D, bool PREV, bool XI>
+static void spmmT_step_d(nsp_ctx* c, const VT* y, const VT* x, const VT* xp, const double* gprev,
+                         VT* out, double* xi_out, double* xi_nrm) {
+  const Csr& a = c->AT;
+  const VT* av = nullptr;
+  if constexpr (sizeof(VT) == 8) av = a.val; else av = a.val32;
+  const int64_t groups = (a.rows + 0);
+  unsigned grid = nblocks(groups * a.lpr, kThreads);
+  if (XI) grid = std::min<unsigned>(grid, (unsigned)kRedBlocks);
+#define NSP_T_CASE(L)                                                                          \
+  case L:                                                                                      \
+    k_spmmT_step<VT, D, L, PREV, XI><<<grid, kThreads, 0, c->stream>>>(                        \
+        a.rows, a.rowptr, a.colind, av, y, x, c->Dv.as<double>(), c->prm.eps, xp, gprev, out,  \
+        c->red.partials, c->red.counter, xi_out, xi_nrm);                                      \
+    break;
+  switch (a.lpr) {
+    NSP_T_CASE(1) NSP_T_CASE(2) NSP_T_CASE(4) NSP_T_CASE(8) NSP_T_CASE(16) NSP_T_CASE(32)
+    default: throw Error(NSP_ERR_ARG, "unsupported lanes-per-row");
+  }
+#undef NSP_T_CASE
+  NSP_HIP(hipGetLastError());
+}
+
+template <typename VT>
+void spmmT_step(nsp_ctx* c, int d, const VT* y, const VT* x, const VT* xp, const double* gprev,
+                VT* out, double* xi_out, double* xi_nrm) {
+  const bool prev = xp != nullptr, dots = xi_out != nullptr;
+#define NSP_DISPATCH(D)                                                                        \
+  if (prev && dots) spmmT_step_d<VT, D, true, true>(c, y, x, xp, gprev, out, xi_out, xi_nrm);          \
+  else if (prev) spmmT_step_d<VT, D, true, false>(c, y, x, xp, gprev, out, xi_out, xi_nrm);            \
+  else if (dots) spmmT_step_d<VT, D, false, true>(c, y, x, xp, gprev, out, xi_out, xi_nrm);            \
+  else spmmT_step_d<VT, D, false, false>(c, y, x, xp, gprev, out, xi_out, xi_nrm);
+  switch (d) {
+    case 1: { NSP_DISPATCH(1) break; }
+    case 2: { NSP_DISPATCH(2) break; }
+    case 4: { NSP_DISPATCH(4) break; }
+    case 8: { NSP_DISPATCH(8) break; }
+    default: throw Error(NSP_ERR_ARG, "block size must be 1, 2, 4 or 8");
+  }
+#undef NSP_DISPATCH
+}
+template void spmmT_step<double>(nsp_ctx*, int, const double*, const double*, const double*,
+                                 const double*, double*, double*, double*);
+template void spmmT_step<float>(nsp_ctx*, int, const float*, const float*, const float*,
+                                const double*, float*, double*, double*);
+
+void spmm_wide(nsp_ctx* c, const Csr& a, int k, const double* x, double* y) {
+  if (a.rows == 0 || k == 0) return;
+  const int rows_per_block = kThreads / kWave;
+  k_spmm_wide<<<nblocks(a.rows, rows_per_block), kThreads, 0, c->stream>>>(a.rows, k, a.rowptr,
+                                                                            a.colind, a.val, x, y);
+  NSP_HIP(hipGetLastError());
+}
+
+void sddmm(nsp_ctx* c, int k, const double* u, const double* v, double* grad) {
+  const Csr& a = c->A;
+  if (a.rows == 0) return;
+  const int rows_per_block = kThreads / kWave;
+  k_sddmm<<<nblocks(a.rows, rows_per_block), kThreads, 0, c->stream>>>(a.rows, k, a.rowptr,
+                                                                        a.colind, u, v, grad);
+  NSP_HIP(hipGetLastError());
+}
+
+void colmajor_to_rows(nsp_ctx* c, int64_t rows, int k, const double* src, int64_t ld, double* dst) {
+  if (rows * k == 0) return;
+  k_colmajor_to_rows<<<nblocks(rows * k, kThreads), kThreads, 0, c->stream>>>(rows, k, src, ld, dst);
+  NSP_HIP(hipGetLastError());
+}
+
+void rows_to_colmajor(nsp_ctx* c, int64_t rows, int k, const double* src, double* dst, int64_t ld) {
+  if (rows * k == 0) return;
+  k_rows_to_colmajor<<<nblocks(rows * k, kThreads), kThreads, 0, c->stream>>>(rows, k, src, dst, ld);
+  NSP_HIP(hipGetLastError());
+}
+
+// Lanes per row: the power of two nearest the mean row length, in [1, 32].
+static int choose_lpr(int64_t rows, int64_t nnz) {
+  const double mean = rows ? (double)nnz / (double)rows : 1.0;
+  int l = 1;
+  while (l < 32 && (double)(l * 2) <= mean * 1.41421356) l *= 2;
+  return l;
+}
+
+// Stored transpose: counting sort of A's entries by column on the host (once,
+// at init; the only place host work touches the matrix), then the values are
+// gathered on the device through the permutation.
+void build_transpose(nsp_ctx* c, const int64_t* rowptr64) {
+  const int64_t m = c->m, n = c->n, nnz = c->nnz;
+  std::vector<int64_t> hrp(m + 1);
+  std::vector<int32_t> hci(nnz);
+  NSP_HIP(hipMemcpy(hrp.data(), rowptr64, sizeof(int64_t) * (m + 1), hipMemcpyDeviceToHost));
+  if (nnz) NSP_HIP(hipMemcpy(hci.data(), c->A.colind, sizeof(int32_t) * nnz, hipMemcpyDeviceToHost));
+  NSP_REQUIRE(hrp[0] == 0 && hrp[m] == nnz, "rowptr[0] must be 0 and rowptr[m] must equal nnz");
+  for (int64_t i = 0; i < m; ++i) NSP_REQUIRE(hrp[i + 1] >= hrp[i], "rowptr must be non-decreasing");
+  std::vector<int32_t> rp32(m + 1), rpt(n + 1, 0), cit(nnz), perm(nnz);
+  for (int64_t i = 0; i <= m; ++i) rp32[i] = (int32_t)hrp[i];
+  for (int64_t p = 0; p < nnz; ++p) {
+    const int32_t j = hci[p];
+    NSP_REQUIRE(j >= 0 && j < n, "colind out of range");
+    rpt[j + 1]++;
+  }
+  for (int64_t j = 0; j < n; ++j) rpt[j + 1] += rpt[j];
+  std::vector<int32_t> next(rpt.begin(), rpt.end() - 1);
+  for (int64_t i = 0; i < m; ++i)
+    for (int64_t p = hrp[i]; p < hrp[i + 1]; ++p) {
+      const int32_t q = next[hci[p]]++;
+      cit[q] = (int32_t)i;
+      perm[q] = (int32_t)p;
+    }
+  c->rowptr32.alloc(sizeof(int32_t) * (m + 1));
+  c->rowptrT.alloc(sizeof(int32_t) * (n + 1));
+  c->colindT.alloc(sizeof(int32_t) * std::max<int64_t>(nnz, 1));
+  c->permT.alloc(sizeof(int32_t) * std::max<int64_t>(nnz, 1));
+  c->valsT.alloc(sizeof(double) * std::max<int64_t>(nnz, 1));
+  NSP_HIP(hipMemcpy(c->rowptr32.p, rp32.data(), sizeof(int32_t) * (m + 1), hipMemcpyHostToDevice));
+  NSP_HIP(hipMemcpy(c->rowptrT.p, rpt.data(), sizeof(int32_t) * (n + 1), hipMemcpyHostToDevice));
+  if (nnz) {
+    NSP_HIP(hipMemcpy(c->colindT.p, cit.data(), sizeof(int32_t) * nnz, hipMemcpyHostToDevice));
+    NSP_HIP(hipMemcpy(c->permT.p, perm.data(), sizeof(int32_t) * nnz, hipMemcpyHostToDevice));
+    k_gather_vals<<<nblocks(nnz, kThreads), kThreads, 0, c->stream>>>(
+        nnz, c->permT.as<int32_t>(), c->A.val, c->valsT.as<double>());
+    NSP_HIP(hipGetLastError());
+  }
+  c->A.rows = m; c->A.cols = n; c->A.nnz = nnz;
+  c->A.rowptr = c->rowptr32.as<int32_t>();
+  c->A.lpr = choose_lpr(m, nnz);
+  c->AT.rows = n; c->AT.cols = m; c->AT.nnz = nnz;
+  c->AT.rowptr = c->rowptrT.as<int32_t>();
+  c->AT.colind = c->colindT.as<int32_t>();
+  c->AT.val = c->valsT.as<double>();
+  c->AT.lpr = choose_lpr(n, nnz);
+  if (c->prm.prec == NSP_PREC_MIXED && nnz) {
+    c->vals32.alloc(sizeof(float) * nnz);
+    c->valsT32.alloc(sizeof(float) * nnz);
+    k_to_f32<<<nblocks(nnz, kThreads), kThreads, 0, c->stream>>>(nnz, c->A.val, c->vals32.as<float>());
+    k_to_f32<<<nblocks(nnz, kThreads), kThreads, 0, c->stream>>>(nnz, c->AT.val, c->valsT32.as<float>());
+    NSP_HIP(hipGetLastError());
+    c->A.val32 = c->vals32.as<float>();
+    c->AT.val32 = c->valsT32.as<float>();
+  }
+}
+
+void init_random(nsp_ctx* c, const double* D, const double* Omega) {
+  const int64_t n = c->n;
+  const int d = c->prm.d;
+  c->Dv.alloc(sizeof(double) * n);
+  c->omega.alloc(sizeof(double) * n * d);
+  if (D) {
+    NSP_HIP(hipMemcpyAsync(c->Dv.p, D, sizeof(double) * n, hipMemcpyDeviceToDevice, c->stream));
+  } else {
+    k_philox_uniform<<<nblocks(n, kThreads), kThreads, 0, c->stream>>>(n, c->prm.seed, 0u,
+                                                                        c->Dv.as<double>());
+  }
+  if (Omega) {
+    NSP_HIP(hipMemcpyAsync(c->omega.p, Omega, sizeof(double) * n * d, hipMemcpyDeviceToDevice,
+                           c->stream));
+  } else {
+    for (int j = 0; j < d; ++j)
+      k_philox_normal<<<nblocks(n, kThreads), kThreads, 0, c->stream>>>(
+          n, c->prm.seed, (uint32_t)(j + 1), c->omega.as<double>() + (int64_t)j * n);
+  }
+  NSP_HIP(hipGetLastError());
+}
+
+// ||A||_F, ||A||_1 ||A||_inf; also rejects non-finite values
+double matrix_norms(nsp_ctx* c) {
+  const int64_t m = c->m, n = c->n;
+  DBuf rabs, rsq, cabs, flag;
+  rabs.alloc(sizeof(double) * m);
+  rsq.alloc(sizeof(double) * m);
+  cabs.alloc(sizeof(double) * n);
+  flag.alloc(sizeof(int));
+  NSP_HIP(hipMemsetAsync(flag.p, 0, sizeof(int), c->stream));
+  k_row_abs_sums<<<nblocks(m, kThreads), kThreads, 0, c->stream>>>(m, c->A.rowptr, c->A.val,
+                                                                    rabs.as<double>(), rsq.as<double>(),
+                                                                    flag.as<int>());
+  k_row_abs_sums<<<nblocks(n, kThreads), kThreads, 0, c->stream>>>(n, c->AT.rowptr, c->AT.val,
+                                                                    cabs.as<double>(), nullptr,
+                                                                    flag.as<int>());
+  NSP_HIP(hipGetLastError());
+  std::vector<double> hr(m), hq(m), hc(n);
+  int hflag = 0;
+  NSP_HIP(hipMemcpyAsync(hr.data(), rabs.p, sizeof(double) * m, hipMemcpyDeviceToHost, c->stream));
+  NSP_HIP(hipMemcpyAsync(hq.data(), rsq.p, sizeof(double) * m, hipMemcpyDeviceToHost, c->stream));
+  NSP_HIP(hipMemcpyAsync(hc.data(), cabs.p, sizeof(double) * n, hipMemcpyDeviceToHost, c->stream));
+  NSP_HIP(hipMemcpyAsync(&hflag, flag.p, sizeof(int), hipMemcpyDeviceToHost, c->stream));
+  NSP_HIP(hipStreamSynchronize(c->stream));
+  if (hflag) throw Error(NSP_ERR_NONFINITE, "A contains a non-finite value");
+  double fro = 0.0, ninf = 0.0, n1 = 0.0;
+  for (int64_t i = 0; i < m; ++i) { fro += hq[i]; ninf = std::max(ninf, hr[i]); }
+  for (int64_t j = 0; j < n; ++j) n1 = std::max(n1, hc[j]);
+  c->normA_fro = std::sqrt(fro);
+  c->normA1_inf = n1 * ninf;
+  return c->normA_fro;
+}
+
+// Y = B X for column-major FP64 X, Y (apply_op).  Columns go through the
+// row-interleaved path in chunks of at most 8.
+void apply_b_colmajor(nsp_ctx* c, const double* X, int64_t ldx, double* Y, int64_t ldy, int ncols) {
+  const int64_t m = c->m, n = c->n;
+  DBuf xr, yr, zr;
+  xr.alloc(sizeof(double) * n * kMaxD);
+  yr.alloc(sizeof(double) * m * kMaxD);
+  zr.alloc(sizeof(double) * n * kMaxD);
+  for (int j0 = 0; j0 < ncols;) {
+    const int left = ncols - j0;
+    const int w = left >= 8 ? 8 : left >= 4 ? 4 : left >= 2 ? 2 : 1;
+    colmajor_to_rows(c, n, w, X + (int64_t)j0 * ldx, ldx, xr.as<double>());
+    spmm_block<double>(c, c->A, w, xr.as<double>(), yr.as<double>());
+    spmmT_step<double>(c, w, yr.as<double>(), xr.as<double>(), nullptr, nullptr, zr.as<double>(),
+                       nullptr);
+    rows_to_colmajor(c, n, w, zr.as<double>(), Y + (int64_t)j0 * ldy, ldy);
+    j0 += w;
+  }
+  NSP_HIP(hipStreamSynchronize(c->stream));
+}
+
+}  // namespace nsp
