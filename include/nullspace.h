@@ -69,9 +69,14 @@ typedef struct {
   double ro_tol;         /* reorthogonalisation threshold u_RO; 0 -> sqrt(u)          */
   int32_t prec;          /* nsp_precision                                            */
   int32_t refine;        /* 1: run the FP64 refinement after the Lanczos iteration   */
-  double tol_rel_resid;  /* refinement stops a column once ||A v|| <= this * ||A||_F  */
-  double tol_abs_resid;  /* ... or once ||A v|| <= this (absolute); the larger
-                            threshold of the two applies; 0 disables a criterion      */
+  double tol_rel_resid;  /* refinement target ||A V||_F <= this * ||A||_F; a column is
+                            done once ||A v|| <= this * ||A||_F / sqrt(N)              */
+  double tol_abs_resid;  /* absolute per-column target ||A v|| <= this                */
+  double tol_angle;      /* target sine of the largest principal angle to null(A): a
+                            column is done once ||A v|| <= this * s / (2 sqrt(N)),
+                            s^2 = theta_next - eps max(D) estimating sigma_min(A)^2
+                            from the smallest Ritz value above 3 eps.  The smallest
+                            threshold of the enabled (non-zero) criteria applies.   */
   int64_t max_refine_iter; /* CGLS iteration cap of the refinement                   */
   int32_t max_cycles;    /* stop after this many restart cycles (0 = no limit)       */
   uint64_t seed;         /* seed of the built-in Philox4x32-10 draws of D and Omega,
@@ -100,7 +105,8 @@ typedef struct {
 
 /* Fill *p with defaults: eps = 1e-3 (Sec. 5.3), d = 1, max_dim = 64,
    max_matvec = 10^7, ro_tol = 0, prec = FP64, refine = 1, tol_rel_resid = 1e-10,
-   tol_abs_resid = 0, max_refine_iter = 10^6, max_cycles = 0, seed = 20240704. */
+   tol_abs_resid = 0, tol_angle = 1e-9, max_refine_iter = 10^6, max_cycles = 0,
+   seed = 20240704. */
 void nsp_default_params(nsp_params* p);
 
 /* Create a solver context for A (m x n, nnz stored entries, CSR).

@@ -36,15 +36,16 @@ listed with its justification in the design notes):
   R9  block norms in the W-recurrence are Frobenius norms (upper bounds of
       the spectral norms, so W stays an upper bound); |G_l^-1| is the
       Frobenius norm of the inverse triangular factor.
-  R10 stopping rule: at each restart record (matvecs, N_ell); each increase
-      of N_ell after the first gives a speed sample (matvecs since the
-      previous increase) * d / (increase); s = 2 * max sample; stop once at
-      least one sample exists and more than s matvecs passed since the last
-      increase.  The interval before the first increase is not a sample: the
-      first Ritz value only has to separate the perturbed-zero cluster from
-      the rest of the spectrum, the later ones must also resolve the cluster,
-      so it under-estimates s.  With a single increase the run continues to
-      the matvec budget.
+  R10 stopping rule (s = matvecs needed for d newly converged Ritz values):
+      at each restart record (matvecs, N_ell).  Starting at the first
+      increase of N_ell, an interval closes at the first later restart where
+      N_ell has grown by at least d; it gives the sample
+      (matvecs spent) * d / (growth).  s = 2 * max sample; stop once a sample
+      exists and more than s matvecs passed since the last increase.  The
+      stretch before the first increase is not a sample: the first Ritz
+      value only has to separate the perturbed-zero cluster from the rest of
+      the spectrum, the later ones must also resolve the cluster, so it
+      under-estimates s.  Without a sample the run goes to the matvec budget.
   R11 the restart's coupling block is F = R Gamma_ell V_Z(last d rows, 1:k_keep),
       where R (~ I) is the triangular factor of re-orthonormalising Q_{ell+1}
       against the new Z_{ell_0}; the printed "[O, Gamma_{ell_0}] V_Z" drops
@@ -186,21 +187,23 @@ def restart_size(n_ell: int, dim_k: int, d: int) -> int:
 
 def speed_rule(history, d: int):
     """Reading R10: returns (stop, s) from the restart history [(matvecs, N_ell), ...]."""
-    events = [(0, 0)]
+    events = []
     best = 0
     for mv, nl in history:
         if nl > best:
             events.append((mv, nl))
             best = nl
-    if best == 0:
-        return False, math.inf
-    samples = [(events[i][0] - events[i - 1][0]) * d / (events[i][1] - events[i - 1][1])
-               for i in range(2, len(events))]
+    samples = []
+    if events:
+        start = events[0]
+        for mv, nl in events[1:]:
+            if nl - start[1] >= d:
+                samples.append((mv - start[0]) * d / (nl - start[1]))
+                start = (mv, nl)
     if not samples:
         return False, math.inf
     s = 2.0 * max(samples)
-    last_mv = events[-1][0]
-    return (history[-1][0] - last_mv) > s, s
+    return (history[-1][0] - events[-1][0]) > s, s
 
 
 def algorithm2(a, eps: float, dvec: np.ndarray, omega: np.ndarray, dim_k: int,

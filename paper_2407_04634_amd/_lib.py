@@ -40,6 +40,7 @@ class Params(ctypes.Structure):
         ("refine", ctypes.c_int32),
         ("tol_rel_resid", ctypes.c_double),
         ("tol_abs_resid", ctypes.c_double),
+        ("tol_angle", ctypes.c_double),
         ("max_refine_iter", ctypes.c_int64),
         ("max_cycles", ctypes.c_int32),
         ("seed", ctypes.c_uint64),

@@ -42,7 +42,8 @@ void validate_params(const nsp_params* p, int64_t n) {
   NSP_REQUIRE(p->max_matvec > 0, "max_matvec must be positive");
   NSP_REQUIRE(p->prec == NSP_PREC_FP64 || p->prec == NSP_PREC_MIXED, "unknown precision mode");
   NSP_REQUIRE(p->ro_tol >= 0.0 && p->ro_tol < 1.0, "ro_tol must be in [0, 1)");
-  NSP_REQUIRE(p->tol_rel_resid >= 0.0 && p->tol_abs_resid >= 0.0, "tolerances must be >= 0");
+  NSP_REQUIRE(p->tol_rel_resid >= 0.0 && p->tol_abs_resid >= 0.0 && p->tol_angle >= 0.0,
+              "tolerances must be >= 0");
   NSP_REQUIRE(p->max_cycles >= 0, "max_cycles must be >= 0");
 }
 
@@ -62,6 +63,7 @@ void nsp_default_params(nsp_params* p) {
   p->refine = 1;
   p->tol_rel_resid = 1e-10;
   p->tol_abs_resid = 0.0;
+  p->tol_angle = 1e-9;
   p->max_refine_iter = 1000000;
   p->max_cycles = 0;
   p->seed = 20240704ull;

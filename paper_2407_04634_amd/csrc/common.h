@@ -107,6 +107,7 @@ struct nsp_ctx {
   nsp::DBuf rowptr32, rowptrT, colindT, valsT, permT, vals32, valsT32;
   double normA_fro = 0.0;
   double normA1_inf = 0.0;  // ||A||_1 * ||A||_inf
+  double maxD = 1.0;        // max of the perturbation diagonal
 
   // perturbation diagonal and start block
   nsp::DBuf Dv, omega;

@@ -474,6 +474,15 @@ void init_random(nsp_ctx* c, const double* D, const double* Omega) {
           n, c->prm.seed, (uint32_t)(j + 1), c->omega.as<double>() + (int64_t)j * n);
   }
   NSP_HIP(hipGetLastError());
+  std::vector<double> hd(n);
+  NSP_HIP(hipMemcpyAsync(hd.data(), c->Dv.p, sizeof(double) * n, hipMemcpyDeviceToHost, c->stream));
+  NSP_HIP(hipStreamSynchronize(c->stream));
+  double mx = 0.0;
+  for (double v : hd) {
+    NSP_REQUIRE(std::isfinite(v) && v >= 0.0, "D must be finite and non-negative");
+    mx = std::max(mx, v);
+  }
+  c->maxD = mx;
 }
 
 // ||A||_F, ||A||_1 ||A||_inf; also rejects non-finite values

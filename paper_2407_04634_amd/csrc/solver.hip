@@ -1,8 +1,616 @@
-// placeholder; replaced by the Lanczos driver
+// Host driver of Algorithm 2 (Sec. 4.3) with device-resident state, the FP64
+// refinement, and the backward pass.
+//
+// Readings of the paper used here (same as the design notes):
+//  R1  restart keeps k_keep = d * floor((N_ell + K) / (2d)) vectors, clamped to
+//      [d, K - 2d];
+//  R2  the recurrence subtracts Q_{ell-1} Gamma_{ell-1}^T;
+//  R3/R4 the W-recurrence cases (see k_wrec);
+//  R5  reorthogonalisation = classical Gram-Schmidt twice;
+//  R6  QR = Cholesky QR (twice for d > 1), positive diagonal;
+//  R7  ||B|| = ||A||_1 ||A||_inf + eps max(D) in the first cycle, then the
+//      largest Ritz value;
+//  R8  u = 2^-52 (FP64) or 2^-23 (FP32 working precision), u_RO = sqrt(u);
+//  R9  Frobenius norms of the blocks in the W-recurrence;
+//  R10 convergence-speed stop;
+//  R11 F = R Gamma_ell V_Z(last d rows, 1:k_keep).
+#include <algorithm>
+#include <chrono>
+#include <cstdlib>
+#include <cmath>
+#include <limits>
+
 #include "common.h"
+#include "kernels.h"
+
 namespace nsp {
-void solve(nsp_ctx*) { throw Error(NSP_ERR_STATE, "solver not built yet"); }
-void run_backward(nsp_ctx*, const double*, int64_t, double*, double, int64_t, int64_t*) {
-  throw Error(NSP_ERR_STATE, "backward not built yet");
+
+namespace {
+
+double now_s() {
+  return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
 }
+
+int restart_size(int n_ell, int K, int d) {
+  int kk = d * ((n_ell + K) / (2 * d));
+  return std::min(std::max(kk, d), K - 2 * d);
+}
+
+// Reading R10: speed s = matvecs per d newly converged Ritz values, sampled
+// over intervals (starting at the first increase of N_ell) that close once
+// N_ell has grown by at least d; stop when more than 2 max(samples) matvecs
+// passed since the last increase.
+bool speed_rule(const std::vector<std::pair<int64_t, int>>& hist, int d) {
+  std::vector<std::pair<int64_t, int>> ev;
+  int best = 0;
+  for (auto& h : hist)
+    if (h.second > best) { ev.push_back(h); best = h.second; }
+  if (ev.empty()) return false;
+  double s = 0.0;
+  bool have = false;
+  auto start = ev[0];
+  for (size_t i = 1; i < ev.size(); ++i)
+    if (ev[i].second - start.second >= d) {
+      s = std::max(s, (double)(ev[i].first - start.first) * d / (ev[i].second - start.second));
+      start = ev[i];
+      have = true;
+    }
+  if (!have) return false;
+  return (double)(hist.back().first - ev.back().first) > 2.0 * s;
+}
+
+template <typename T> T* alloc_as(DBuf& b, size_t count) {
+  b.alloc(sizeof(T) * std::max<size_t>(count, 1));
+  return b.as<T>();
+}
+
+// dense small GEMM helpers on column-major FP64 (rocBLAS)
+void dgemm(nsp_ctx* c, rocblas_operation ta, rocblas_operation tb, int64_t m, int64_t n, int64_t k,
+           double alpha, const double* a, int64_t lda, const double* b, int64_t ldb, double beta,
+           double* out, int64_t ldc) {
+  NSP_BLAS(rocblas_dgemm(c->blas, ta, tb, (rocblas_int)m, (rocblas_int)n, (rocblas_int)k, &alpha, a,
+                         (rocblas_int)lda, b, (rocblas_int)ldb, &beta, out, (rocblas_int)ldc));
+}
+void sgemm(nsp_ctx* c, rocblas_operation ta, rocblas_operation tb, int64_t m, int64_t n, int64_t k,
+           float alpha, const float* a, int64_t lda, const float* b, int64_t ldb, float beta,
+           float* out, int64_t ldc) {
+  NSP_BLAS(rocblas_sgemm(c->blas, ta, tb, (rocblas_int)m, (rocblas_int)n, (rocblas_int)k, &alpha, a,
+                         (rocblas_int)lda, b, (rocblas_int)ldb, &beta, out, (rocblas_int)ldc));
+}
+
+// symmetric eigen-decomposition on the device (FP64): A (k x k) is replaced by
+// its eigenvectors, w receives the eigenvalues ascending.
+void syevd(nsp_ctx* c, int k, double* a, double* w, DBuf& ework, DBuf& info) {
+  double* e = alloc_as<double>(ework, k);
+  rocblas_int* inf = alloc_as<rocblas_int>(info, 1);
+  NSP_BLAS(rocsolver_dsyevd(c->blas, rocblas_evect_original, rocblas_fill_lower, k, a, k, w, e, inf));
+  rocblas_int h = 0;
+  NSP_HIP(hipMemcpyAsync(&h, inf, sizeof(h), hipMemcpyDeviceToHost, c->stream));
+  NSP_HIP(hipStreamSynchronize(c->stream));
+  if (h != 0) throw Error(NSP_ERR_HIP, "rocsolver_dsyevd did not converge (info " + std::to_string(h) + ")");
+}
+
+// ---------------------------------------------------------------------------
+template <typename VT>
+struct Lanczos {
+  nsp_ctx* c;
+  int64_t n, m, ldz;
+  int d, K, L;
+  VT *Z, *Z2, *ring[3], *Y, *P;
+  double *xi, *gam, *rinv, *rinv2, *rinvc, *nrm_xi, *nrm_gam, *nrm_ginv, *nrm_theta, *nrm_f;
+  double *W, *theta_kept, *fmat, *T, *evals, *H, *hpart;
+  int ldw;
+  int* flags;
+  DBuf b_xi, b_gam, b_rinv, b_rinv2, b_rinvc, b_nxi, b_ngam, b_nginv, b_ntheta, b_nf, b_W, b_hpart,
+      b_H, b_info, b_vzf, b_tmpv;
+
+  explicit Lanczos(nsp_ctx* ctx) : c(ctx) {
+    n = c->n; m = c->m; d = c->prm.d; K = c->prm.max_dim; L = K / d;
+    ldz = (n + 63) / 64 * 64;
+    Z = alloc_as<VT>(c->Z, (size_t)ldz * (K + d));
+    Z2 = alloc_as<VT>(c->Z2, (size_t)ldz * (K + d));
+    if (d > 1) {
+      VT* r = alloc_as<VT>(c->ring, (size_t)3 * n * d);
+      for (int i = 0; i < 3; ++i) ring[i] = r + (size_t)i * n * d;
+    }
+    Y = alloc_as<VT>(c->Y, (size_t)m * d);
+    P = alloc_as<VT>(c->P, (size_t)n * d);
+    const int nb = L + 3;
+    xi = alloc_as<double>(b_xi, (size_t)nb * d * d);
+    gam = alloc_as<double>(b_gam, (size_t)nb * d * d);
+    rinv = alloc_as<double>(b_rinv, (size_t)d * d);
+    rinv2 = alloc_as<double>(b_rinv2, (size_t)d * d);
+    rinvc = alloc_as<double>(b_rinvc, (size_t)2 * 4 * d * d);
+    nrm_xi = alloc_as<double>(b_nxi, nb);
+    nrm_gam = alloc_as<double>(b_ngam, nb);
+    nrm_ginv = alloc_as<double>(b_nginv, nb);
+    nrm_theta = alloc_as<double>(b_ntheta, nb);
+    nrm_f = alloc_as<double>(b_nf, nb);
+    ldw = L + 3;
+    W = alloc_as<double>(b_W, (size_t)ldw * ldw);
+    theta_kept = alloc_as<double>(c->theta_kept, K);
+    fmat = alloc_as<double>(c->fmat, (size_t)d * K);
+    T = alloc_as<double>(c->tmat, (size_t)K * K);
+    evals = alloc_as<double>(c->evals, K);
+    H = alloc_as<double>(b_H, (size_t)(K + d) * 2 * d);
+    const int64_t chunk = ts_chunk_rows(n, 1, 2 * d);
+    const int64_t maxchunks = (n + chunk - 1) / chunk;
+    hpart = alloc_as<double>(b_hpart, (size_t)maxchunks * (K + d) * 2 * d);
+    flags = alloc_as<int>(c->flags, 8);
+    NSP_HIP(hipMemsetAsync(flags, 0, sizeof(int) * 8, c->stream));
+    NSP_HIP(hipMemsetAsync(W, 0, sizeof(double) * ldw * ldw, c->stream));
+    NSP_HIP(hipMemsetAsync(nrm_theta, 0, sizeof(double) * nb, c->stream));
+    NSP_HIP(hipMemsetAsync(nrm_f, 0, sizeof(double) * nb, c->stream));
+  }
+
+  // row-interleaved copy of Lanczos block ``blk`` (1-based); for d = 1 it is
+  // the basis column itself
+  VT* slot(int blk) const { return d == 1 ? Z + (int64_t)(blk - 1) * ldz : ring[blk % 3]; }
+  VT* zcol(int blk) const { return d == 1 ? nullptr : Z + (int64_t)(blk - 1) * d * ldz; }
+
+  // Q = orth(X) for the block in slot ``blk``: Cholesky QR (twice for d > 1)
+  void orthonormalize_slot(int blk, double* gam_out) {
+    VT* x = slot(blk);
+    sub_gram<VT>(c, d, n, x, nullptr, nullptr, gam_out, rinv, nullptr, nullptr);
+    scale_block<VT>(c, d, n, x, rinv, x, zcol(blk), ldz, d > 1, gam_out, rinv2, nullptr, nullptr);
+    if (d > 1) scale_block<VT>(c, d, n, x, rinv2, x, zcol(blk), ldz, false, nullptr, nullptr, nullptr, nullptr);
+  }
+
+  // the QR of P into slot ``blk`` (Gamma_{blk-1} stored), with or without the Xi subtraction
+  void qr_step(int blk_from, int blk_to, bool subtract) {
+    double* g = gam + (size_t)blk_from * d * d;
+    sub_gram<VT>(c, d, n, P, subtract ? slot(blk_from) : nullptr,
+                 subtract ? xi + (size_t)blk_from * d * d : nullptr, g, rinv, nrm_gam + blk_from,
+                 nrm_ginv + blk_from);
+    scale_block<VT>(c, d, n, P, rinv, slot(blk_to), zcol(blk_to), ldz, d > 1, g, rinv2,
+                    nrm_gam + blk_from, nrm_ginv + blk_from);
+    if (d > 1)
+      scale_block<VT>(c, d, n, slot(blk_to), rinv2, slot(blk_to), zcol(blk_to), ldz, false, nullptr,
+                      nullptr, nullptr, nullptr);
+  }
+
+  void cgs2_full(VT* a, int k, bool final_gram, double* rinv_out) {
+    ts_project<VT>(c, nullptr, d, 1, n, Z, ldz, k, a, nullptr, H, hpart, false, nullptr);
+    ts_project<VT>(c, nullptr, d, 1, n, Z, ldz, k, a, nullptr, H, hpart, final_gram, rinv_out);
+  }
+
+  void run() {
+    nsp_params& p = c->prm;
+    nsp_stats& st = c->stats;
+    st = nsp_stats{};
+    const double t0 = now_s();
+    const double u = sizeof(VT) == 8 ? std::ldexp(1.0, -52) : std::ldexp(1.0, -23);
+    const double u_ro = p.ro_tol > 0 ? p.ro_tol : std::sqrt(u);
+    double norm_b = c->normA1_inf + p.eps * c->maxD;
+    double u_d = d * std::sqrt((double)n) * u * norm_b;
+
+    // Q_1 = orth(Omega)
+    cm_to_ri<double, VT>(c, n, d, c->omega.as<double>(), n, slot(1));
+    orthonormalize_slot(1, gam);
+
+    int l0 = 0;
+    int64_t matvecs = 0;
+    std::vector<std::pair<int64_t, int>> hist;
+    std::vector<double> hev(K);
+    int flags_h[8];
+    double t_lan = 0.0, t_rr = 0.0;
+    bool stop = false;
+    int n_ell = 0;
+    const char* ve = std::getenv("NSP_VERBOSE");
+    const bool verbose = ve && ve[0] == '1';
+    double last_print = now_s();
+    for (;;) {
+      const double tc0 = now_s();
+      const int kk = l0 * d;
+      // ---- first step of the cycle: Q' = B Q_{l0+1}, Xi, QR((I - Z Z^T) Q')
+      {
+        const int blk = l0 + 1;
+        spmm_block<VT>(c, c->A, d, slot(blk), Y);
+        spmmT_step<VT>(c, d, Y, slot(blk), nullptr, nullptr, P, xi + (size_t)blk * d * d,
+                       nrm_xi + blk);
+        cgs2_full(P, kk + d, false, nullptr);
+        qr_step(blk, blk + 1, false);
+        w_reset(c, l0 + 1, 2, u_d, W, ldw);
+        matvecs += d;
+      }
+      // ---- Lanczos steps ell = l0+2 .. L with partial reorthogonalisation
+      for (int ell = l0 + 2; ell <= L; ++ell) {
+        VT* x = slot(ell);
+        VT* xp = slot(ell - 1);
+        VT* xn = slot(ell + 1);
+        spmm_block<VT>(c, c->A, d, x, Y);
+        spmmT_step<VT>(c, d, Y, x, xp, gam + (size_t)(ell - 1) * d * d, P,
+                       xi + (size_t)ell * d * d, nrm_xi + ell);
+        qr_step(ell, ell + 1, true);
+        wrec(c, ell, l0, u_d, u_ro, nrm_xi, nrm_gam, nrm_ginv, nrm_theta, nrm_f, W, ldw);
+        const int kz = (ell - 1) * d;  // Z_{ell-1}
+        ts_project<VT>(c, flags, d, 2, n, Z, ldz, kz, x, xn, H, hpart, false, nullptr);
+        ts_project<VT>(c, flags, d, 2, n, Z, ldz, kz, x, xn, H, hpart, true, rinvc);
+        ts_scale<VT>(c, flags, d, 2, n, x, xn, rinvc, d > 1 ? zcol(ell) : nullptr, ldz);
+        matvecs += d;
+      }
+      NSP_HIP(hipStreamSynchronize(c->stream));
+      const double tc1 = now_s();
+      t_lan += tc1 - tc0;
+      // ---- Rayleigh-Ritz on T (Eq. "defT")
+      assemble_t(c, K, d, kk, theta_kept, fmat, xi, gam, T);
+      syevd(c, K, T, evals, c->ework, b_info);
+      NSP_HIP(hipMemcpyAsync(hev.data(), evals, sizeof(double) * K, hipMemcpyDeviceToHost, c->stream));
+      NSP_HIP(hipMemcpyAsync(flags_h, flags, sizeof(int) * 8, hipMemcpyDeviceToHost, c->stream));
+      NSP_HIP(hipStreamSynchronize(c->stream));
+      if (flags_h[1]) throw Error(NSP_ERR_BREAKDOWN, "a Lanczos block lost rank (Krylov breakdown)");
+      for (double v : hev)
+        if (!std::isfinite(v)) throw Error(NSP_ERR_NONFINITE, "non-finite Ritz value");
+      n_ell = (int)std::count_if(hev.begin(), hev.end(), [&](double v) { return v < 3.0 * p.eps; });
+      hist.emplace_back(matvecs, n_ell);
+      st.cycles++;
+      if (verbose && now_s() - last_print > 2.0) {
+        std::fprintf(stderr, "[nsp] cycle %d matvecs %lld N_ell %d lanczos %.2fs rr %.2fs\n",
+                     st.cycles, (long long)matvecs, n_ell, t_lan, t_rr);
+        std::fflush(stderr);
+        last_print = now_s();
+      }
+      stop = speed_rule(hist, d);
+      const bool budget = matvecs >= p.max_matvec || (p.max_cycles > 0 && st.cycles >= p.max_cycles);
+      c->ritz = hev;
+      if (stop || budget) {
+        extract(n_ell);
+        t_rr += now_s() - tc1;
+        break;
+      }
+      // ---- thick restart (Sec. 4.1)
+      const int kn = restart_size(n_ell, K, d);
+      if (n_ell > kn) throw Error(NSP_ERR_ARG, "max_dim too small for the detected nullity");
+      restart(kn, hev);
+      norm_b = hev[K - 1];  // reading R7
+      u_d = d * std::sqrt((double)n) * u * norm_b;
+      l0 = kn / d;
+      st.restarts++;
+      t_rr += now_s() - tc1;
+    }
+    NSP_HIP(hipMemcpyAsync(flags_h, flags, sizeof(int) * 8, hipMemcpyDeviceToHost, c->stream));
+    NSP_HIP(hipStreamSynchronize(c->stream));
+    st.nullity = n_ell;
+    st.converged = stop ? 1 : 0;
+    st.matvecs = matvecs;
+    st.reorths = flags_h[3];
+    st.norm_b = norm_b;
+    st.theta_last = n_ell > 0 ? hev[n_ell - 1] : 0.0;
+    st.theta_next = n_ell < K ? hev[n_ell] : 0.0;
+    st.t_lanczos_s = t_lan;
+    st.t_restart_s = t_rr;
+    c->nullity = n_ell;
+    c->state = 1;
+    (void)t0;
+  }
+
+  // Z_new = Z V_Z(:, 1:kn); Q_{l0+1} = orth((I - Z_new Z_new^T) Q_{L+1}); F
+  void restart(int kn, const std::vector<double>& hev) {
+    // basis update Z2(:, 0:kn) = Z(:, 0:K) V_Z(:, 0:kn)
+    if constexpr (sizeof(VT) == 8) {
+      dgemm(c, rocblas_operation_none, rocblas_operation_none, n, kn, K, 1.0, (const double*)Z, ldz,
+            T, K, 0.0, (double*)Z2, ldz);
+    } else {
+      float* vz = alloc_as<float>(b_vzf, (size_t)K * kn);
+      convert<double, float>(c, (int64_t)K * kn, T, vz);
+      sgemm(c, rocblas_operation_none, rocblas_operation_none, n, kn, K, 1.0f, (const float*)Z, ldz,
+            vz, K, 0.0f, (float*)Z2, ldz);
+    }
+    // carry Q_{L+1} (columns K..K+d of Z) to columns kn..kn+d of Z2
+    copy_panel<VT, VT>(c, n, d, Z + (int64_t)K * ldz, ldz, Z2 + (int64_t)kn * ldz, ldz);
+    std::swap(Z, Z2);
+    const int blk = kn / d + 1;
+    if (d > 1) cm_to_ri<VT, VT>(c, n, d, Z + (int64_t)kn * ldz, ldz, slot(blk));
+    // re-orthonormalise against the kept Ritz vectors: CGS2 with the Gram of the
+    // result, then scale by R^{-1} (R ~ I)
+    cgs2_full(slot(blk), kn, true, rinvc);
+    ts_scale<VT>(c, nullptr, d, 1, n, slot(blk), nullptr, rinvc, d > 1 ? zcol(blk) : nullptr, ldz);
+    // F = R Gamma_L V_Z(K-d:K, 0:kn)   (reading R11), on the host in FP64
+    std::vector<double> vlast((size_t)d * kn), gl((size_t)d * d), rr((size_t)2 * d * d);
+    NSP_HIP(hipMemcpy2DAsync(vlast.data(), sizeof(double) * d, T + (K - d), sizeof(double) * K,
+                             sizeof(double) * d, kn, hipMemcpyDeviceToHost, c->stream));
+    NSP_HIP(hipMemcpyAsync(gl.data(), gam + (size_t)L * d * d, sizeof(double) * d * d,
+                           hipMemcpyDeviceToHost, c->stream));
+    NSP_HIP(hipMemcpyAsync(rr.data(), rinvc, sizeof(double) * 2 * d * d, hipMemcpyDeviceToHost,
+                           c->stream));
+    NSP_HIP(hipStreamSynchronize(c->stream));
+    const double* rf = rr.data() + d * d;  // R follows R^{-1}
+    std::vector<double> rg((size_t)d * d, 0.0), f((size_t)d * kn, 0.0);
+    for (int i = 0; i < d; ++i)
+      for (int j = 0; j < d; ++j)
+        for (int l = 0; l < d; ++l) rg[i + j * d] += rf[i + l * d] * gl[l + j * d];
+    for (int j = 0; j < kn; ++j)
+      for (int i = 0; i < d; ++i) {
+        double s = 0.0;
+        for (int l = 0; l < d; ++l) s += rg[i + l * d] * vlast[l + (size_t)j * d];
+        f[i + (size_t)j * d] = s;
+      }
+    // block norms for the W-recurrence: ||Theta_k|| and ||F_k||_F, k = 1..kn/d
+    const int nb = kn / d;
+    std::vector<double> nth(L + 3, 0.0), nf(L + 3, 0.0);
+    for (int k = 1; k <= nb; ++k) {
+      double mx = 0.0, s2 = 0.0;
+      for (int j = (k - 1) * d; j < k * d; ++j) {
+        mx = std::max(mx, std::fabs(hev[j]));
+        for (int i = 0; i < d; ++i) s2 += f[i + (size_t)j * d] * f[i + (size_t)j * d];
+      }
+      nth[k] = mx;
+      nf[k] = std::sqrt(s2);
+    }
+    NSP_HIP(hipMemcpyAsync(fmat, f.data(), sizeof(double) * d * kn, hipMemcpyHostToDevice, c->stream));
+    NSP_HIP(hipMemcpyAsync(theta_kept, hev.data(), sizeof(double) * kn, hipMemcpyHostToDevice, c->stream));
+    NSP_HIP(hipMemcpyAsync(nrm_theta, nth.data(), sizeof(double) * (L + 3), hipMemcpyHostToDevice, c->stream));
+    NSP_HIP(hipMemcpyAsync(nrm_f, nf.data(), sizeof(double) * (L + 3), hipMemcpyHostToDevice, c->stream));
+    NSP_HIP(hipStreamSynchronize(c->stream));
+  }
+
+  // V = Z(:, 0:K) V_Z(:, 0:N) in FP64, column-major n x N
+  void extract(int nul) {
+    double* v = alloc_as<double>(c->V, (size_t)n * std::max(nul, 1));
+    if (nul == 0) return;
+    if constexpr (sizeof(VT) == 8) {
+      dgemm(c, rocblas_operation_none, rocblas_operation_none, n, nul, K, 1.0, (const double*)Z, ldz,
+            T, K, 0.0, v, n);
+    } else {
+      float* vz = alloc_as<float>(b_vzf, (size_t)K * nul);
+      convert<double, float>(c, (int64_t)K * nul, T, vz);
+      float* tmp = alloc_as<float>(b_tmpv, (size_t)n * nul);
+      sgemm(c, rocblas_operation_none, rocblas_operation_none, n, nul, K, 1.0f, (const float*)Z, ldz,
+            vz, K, 0.0f, tmp, n);
+      convert<float, double>(c, (int64_t)n * nul, tmp, v);
+    }
+  }
+};
+
+// ---------------------------------------------------------------------------
+// FP64 refinement: Rayleigh-Ritz with A^T A, CGLS projection onto null(A),
+// Cholesky QR twice, residual and orthogonality checks.
+// ---------------------------------------------------------------------------
+struct Refiner {
+  nsp_ctx* c;
+  int64_t n, m;
+  int k;
+  DBuf b_vr, b_u, b_x, b_s, b_r, b_p, b_q, b_small, b_small2, b_part, b_dots, b_act, b_info, b_e;
+
+  Refiner(nsp_ctx* ctx, int nul) : c(ctx), n(ctx->n), m(ctx->m), k(nul) {}
+
+  // row-major n x k  <->  column-major k x n view with ld k
+  void gram_rows(const double* a, int64_t rows, double* g) {
+    // G = A^T A for row-major A (rows x k): column-major view Acm (k x rows)
+    dgemm(c, rocblas_operation_none, rocblas_operation_transpose, k, k, rows, 1.0, a, k, a, k, 0.0, g, k);
+  }
+
+  void cholqr(double* vr) {
+    double* g = alloc_as<double>(b_small, (size_t)k * k);
+    rocblas_int* inf = alloc_as<rocblas_int>(b_info, 1);
+    gram_rows(vr, n, g);
+    NSP_BLAS(rocsolver_dpotrf(c->blas, rocblas_fill_upper, k, g, k, inf));
+    rocblas_int h = 0;
+    NSP_HIP(hipMemcpyAsync(&h, inf, sizeof(h), hipMemcpyDeviceToHost, c->stream));
+    NSP_HIP(hipStreamSynchronize(c->stream));
+    if (h != 0) throw Error(NSP_ERR_BREAKDOWN, "refined basis lost rank (Cholesky QR failed)");
+    // V <- V R^{-1}: in the column-major view Vcm = V^T: Vcm <- R^{-T} Vcm
+    const double one = 1.0;
+    NSP_BLAS(rocblas_dtrsm(c->blas, rocblas_side_left, rocblas_fill_upper, rocblas_operation_transpose,
+                           rocblas_diagonal_non_unit, k, (rocblas_int)n, &one, g, k, vr, k));
+  }
+
+  void run() {
+    nsp_params& p = c->prm;
+    nsp_stats& st = c->stats;
+    const double t0 = now_s();
+    double* vr = alloc_as<double>(b_vr, (size_t)n * k);
+    double* u = alloc_as<double>(b_u, (size_t)m * k);
+    colmajor_to_rows(c, n, k, c->V.as<double>(), n, vr);
+    // Step 1: Rayleigh-Ritz with the unperturbed A^T A on span(V)
+    spmm_wide(c, c->A, k, vr, u);
+    double* s = alloc_as<double>(b_small, (size_t)k * k);
+    gram_rows(u, m, s);
+    double* lam = alloc_as<double>(b_e, (size_t)2 * k);
+    syevd(c, k, s, lam, b_small2, b_info);
+    double* vnew = alloc_as<double>(b_x, (size_t)n * k);
+    // Vr_new^T = Y^T Vr^T  (column-major views)
+    dgemm(c, rocblas_operation_transpose, rocblas_operation_none, k, n, k, 1.0, s, k, vr, k, 0.0, vnew, k);
+    NSP_HIP(hipMemcpyAsync(vr, vnew, sizeof(double) * n * k, hipMemcpyDeviceToDevice, c->stream));
+    // Step 2: CGLS for x = A^+ A v per column, x_0 = 0; s = A v - A x = A (v - x)
+    double* x = alloc_as<double>(b_x, (size_t)n * k);
+    double* sv = alloc_as<double>(b_s, (size_t)m * k);
+    double* r = alloc_as<double>(b_r, (size_t)n * k);
+    double* pp = alloc_as<double>(b_p, (size_t)n * k);
+    double* q = alloc_as<double>(b_q, (size_t)m * k);
+    double* dots = alloc_as<double>(b_dots, (size_t)4 * k);  // gamma, qq, gnew, snorm2
+    double* part = alloc_as<double>(b_part, (size_t)coldots_parts(std::max(n, m)) * k);
+    int* act = alloc_as<int>(b_act, k);
+    double *gamma = dots, *qq = dots + k, *gnew = dots + 2 * k, *sn2 = dots + 3 * k;
+    NSP_HIP(hipMemsetAsync(x, 0, sizeof(double) * n * k, c->stream));
+    spmm_wide(c, c->A, k, vr, sv);
+    spmm_wide(c, c->AT, k, sv, r);
+    NSP_HIP(hipMemcpyAsync(pp, r, sizeof(double) * n * k, hipMemcpyDeviceToDevice, c->stream));
+    coldots(c, n, k, r, r, gamma, part);
+    coldots(c, m, k, sv, sv, sn2, part);
+    // per-column target: the smallest threshold of the enabled criteria
+    const double rk = std::sqrt((double)k);
+    double tau = std::numeric_limits<double>::infinity();
+    if (p.tol_rel_resid > 0) tau = std::min(tau, p.tol_rel_resid * c->normA_fro / rk);
+    if (p.tol_abs_resid > 0) tau = std::min(tau, p.tol_abs_resid);
+    if (p.tol_angle > 0) {
+      const double s2 = st.theta_next - p.eps * c->maxD;
+      if (s2 > 0) tau = std::min(tau, p.tol_angle * std::sqrt(s2) / (2.0 * rk));
+    }
+    if (!std::isfinite(tau)) tau = 1e-10 * c->normA_fro / rk;
+    std::vector<double> hs(k);
+    std::vector<int> ha(k);
+    auto update_active = [&]() -> bool {
+      NSP_HIP(hipMemcpyAsync(hs.data(), sn2, sizeof(double) * k, hipMemcpyDeviceToHost, c->stream));
+      NSP_HIP(hipStreamSynchronize(c->stream));
+      bool any = false;
+      for (int j = 0; j < k; ++j) {
+        if (!std::isfinite(hs[j])) throw Error(NSP_ERR_NONFINITE, "non-finite value in refinement");
+        ha[j] = std::sqrt(hs[j]) > tau ? 1 : 0;
+        any |= ha[j] != 0;
+      }
+      NSP_HIP(hipMemcpyAsync(act, ha.data(), sizeof(int) * k, hipMemcpyHostToDevice, c->stream));
+      return any;
+    };
+    int64_t it = 0;
+    bool any = update_active();
+    const char* ve = std::getenv("NSP_VERBOSE");
+    const bool verbose = ve && ve[0] == '1';
+    double last_print = now_s();
+    while (any && it < p.max_refine_iter) {
+      spmm_wide(c, c->A, k, pp, q);
+      coldots(c, m, k, q, q, qq, part);
+      cgls_xs(c, n, m, k, gamma, qq, act, x, pp, sv, q);
+      spmm_wide(c, c->AT, k, sv, r);
+      coldots(c, n, k, r, r, gnew, part);
+      cgls_p(c, n, k, gnew, gamma, act, r, pp);
+      // gamma <- gnew for active columns (inactive ones keep alpha = 0 anyway)
+      NSP_HIP(hipMemcpyAsync(gamma, gnew, sizeof(double) * k, hipMemcpyDeviceToDevice, c->stream));
+      ++it;
+      if (it % 16 == 0) {
+        coldots(c, m, k, sv, sv, sn2, part);
+        any = update_active();
+        if (verbose && now_s() - last_print > 2.0) {
+          int na = 0;
+          double mx = 0.0;
+          for (int j = 0; j < k; ++j) { na += ha[j]; mx = std::max(mx, std::sqrt(hs[j])); }
+          std::fprintf(stderr, "[nsp] refine it %lld active %d max|Av| %.3e target %.3e\n",
+                       (long long)it, na, mx, tau);
+          std::fflush(stderr);
+          last_print = now_s();
+        }
+      }
+    }
+    st.refine_iters = it;
+    sub_inplace(c, n * k, vr, x);
+    // Step 3: orthonormalise (Cholesky QR twice), residual and orthogonality
+    cholqr(vr);
+    cholqr(vr);
+    spmm_wide(c, c->A, k, vr, u);
+    coldots(c, m, k, u, u, sn2, part);
+    double* g = alloc_as<double>(b_small, (size_t)k * k);
+    gram_rows(vr, n, g);
+    std::vector<double> hg((size_t)k * k);
+    NSP_HIP(hipMemcpyAsync(hs.data(), sn2, sizeof(double) * k, hipMemcpyDeviceToHost, c->stream));
+    NSP_HIP(hipMemcpyAsync(hg.data(), g, sizeof(double) * k * k, hipMemcpyDeviceToHost, c->stream));
+    NSP_HIP(hipStreamSynchronize(c->stream));
+    double res2 = 0.0, oe = 0.0;
+    for (double v : hs) res2 += v;
+    for (int i = 0; i < k; ++i)
+      for (int j = 0; j < k; ++j) {
+        const double e = hg[i + (size_t)j * k] - (i == j ? 1.0 : 0.0);
+        oe += e * e;
+      }
+    st.rel_resid_fro = c->normA_fro > 0 ? std::sqrt(res2) / c->normA_fro : std::sqrt(res2);
+    st.orth_err_fro = std::sqrt(oe);
+    rows_to_colmajor(c, n, k, vr, c->V.as<double>(), n);
+    NSP_HIP(hipStreamSynchronize(c->stream));
+    st.t_refine_s = now_s() - t0;
+  }
+};
+
+}  // namespace
+
+void solve(nsp_ctx* c) {
+  const double t0 = now_s();
+  c->state = 0;
+  c->nullity = 0;
+  if (c->prm.prec == NSP_PREC_MIXED) {
+    Lanczos<float> lz(c);
+    lz.run();
+  } else {
+    Lanczos<double> lz(c);
+    lz.run();
+  }
+  if (c->prm.refine && c->nullity > 0) {
+    Refiner rf(c, c->nullity);
+    rf.run();
+  } else if (c->nullity > 0) {
+    // orthonormality / residual of the unrefined basis are still reported
+    c->stats.rel_resid_fro = -1.0;
+    c->stats.orth_err_fro = -1.0;
+  }
+  c->stats.t_total_s = now_s() - t0;
+}
+
+// ---------------------------------------------------------------------------
+// backward: W = (A^T A)^+ (I - V V^T) G_s V by CG on range(A^T); grad = SDDMM
+// ---------------------------------------------------------------------------
+void run_backward(nsp_ctx* c, const double* GsV, int64_t ld, double* grad, double tol,
+                  int64_t max_iter, int64_t* iters) {
+  const int64_t n = c->n, m = c->m;
+  const int k = c->nullity;
+  if (iters) *iters = 0;
+  if (k == 0) {
+    if (c->nnz) NSP_HIP(hipMemsetAsync(grad, 0, sizeof(double) * c->nnz, c->stream));
+    NSP_HIP(hipStreamSynchronize(c->stream));
+    return;
+  }
+  DBuf b_v, b_g, b_w, b_r, b_p, b_q, b_y, b_mm, b_dots, b_part, b_act;
+  double* vr = alloc_as<double>(b_v, (size_t)n * k);
+  double* r = alloc_as<double>(b_r, (size_t)n * k);
+  colmajor_to_rows(c, n, k, c->V.as<double>(), n, vr);
+  colmajor_to_rows(c, n, k, GsV, ld, r);
+  // R = G - V (V^T G)
+  double* mm = alloc_as<double>(b_mm, (size_t)k * k);
+  dgemm(c, rocblas_operation_none, rocblas_operation_transpose, k, k, n, 1.0, vr, k, r, k, 0.0, mm, k);
+  dgemm(c, rocblas_operation_transpose, rocblas_operation_none, k, n, k, -1.0, mm, k, vr, k, 1.0, r, k);
+  double* w = alloc_as<double>(b_w, (size_t)n * k);
+  double* pp = alloc_as<double>(b_p, (size_t)n * k);
+  double* q = alloc_as<double>(b_q, (size_t)n * k);
+  double* y = alloc_as<double>(b_y, (size_t)m * k);
+  double* dots = alloc_as<double>(b_dots, (size_t)3 * k);
+  double* part = alloc_as<double>(b_part, (size_t)coldots_parts(std::max(n, m)) * k);
+  int* act = alloc_as<int>(b_act, k);
+  double *rr = dots, *pq = dots + k, *rnew = dots + 2 * k;
+  NSP_HIP(hipMemsetAsync(w, 0, sizeof(double) * n * k, c->stream));
+  NSP_HIP(hipMemcpyAsync(pp, r, sizeof(double) * n * k, hipMemcpyDeviceToDevice, c->stream));
+  coldots(c, n, k, r, r, rr, part);
+  std::vector<double> r0(k), hr(k);
+  std::vector<int> ha(k);
+  NSP_HIP(hipMemcpyAsync(r0.data(), rr, sizeof(double) * k, hipMemcpyDeviceToHost, c->stream));
+  NSP_HIP(hipStreamSynchronize(c->stream));
+  bool any = false;
+  for (int j = 0; j < k; ++j) {
+    r0[j] = std::sqrt(r0[j]);
+    ha[j] = r0[j] > 0.0 ? 1 : 0;
+    any |= ha[j] != 0;
+  }
+  NSP_HIP(hipMemcpyAsync(act, ha.data(), sizeof(int) * k, hipMemcpyHostToDevice, c->stream));
+  int64_t it = 0;
+  while (any && it < max_iter) {
+    spmm_wide(c, c->A, k, pp, y);
+    spmm_wide(c, c->AT, k, y, q);
+    coldots(c, n, k, pp, q, pq, part);
+    cg_wr(c, n, k, rr, pq, act, w, pp, r, q);
+    coldots(c, n, k, r, r, rnew, part);
+    cgls_p(c, n, k, rnew, rr, act, r, pp);
+    NSP_HIP(hipMemcpyAsync(rr, rnew, sizeof(double) * k, hipMemcpyDeviceToDevice, c->stream));
+    ++it;
+    if (it % 16 == 0) {
+      // re-project the residual onto range(A^T): V is a null basis only to
+      // rounding accuracy, and A^T A cannot reduce a residual component in
+      // null(A) (a no-op in exact arithmetic, where r stays in the range)
+      dgemm(c, rocblas_operation_none, rocblas_operation_transpose, k, k, n, 1.0, vr, k, r, k, 0.0, mm, k);
+      dgemm(c, rocblas_operation_transpose, rocblas_operation_none, k, n, k, -1.0, mm, k, vr, k, 1.0, r, k);
+      coldots(c, n, k, r, r, rr, part);
+      NSP_HIP(hipMemcpyAsync(hr.data(), rr, sizeof(double) * k, hipMemcpyDeviceToHost, c->stream));
+      NSP_HIP(hipStreamSynchronize(c->stream));
+      any = false;
+      for (int j = 0; j < k; ++j) {
+        if (!std::isfinite(hr[j])) throw Error(NSP_ERR_NONFINITE, "non-finite value in backward CG");
+        ha[j] = std::sqrt(hr[j]) > tol * r0[j] ? 1 : 0;
+        any |= ha[j] != 0;
+      }
+      NSP_HIP(hipMemcpyAsync(act, ha.data(), sizeof(int) * k, hipMemcpyHostToDevice, c->stream));
+    }
+  }
+  // U = A W, grad_p = -2 <U_i, V_j>
+  spmm_wide(c, c->A, k, w, y);
+  sddmm(c, k, y, vr, grad);
+  NSP_HIP(hipStreamSynchronize(c->stream));
+  if (iters) *iters = it;
+  if (any) throw Error(NSP_ERR_NOCONV, "backward CG reached max_iter");
+}
+
 }  // namespace nsp

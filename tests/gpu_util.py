@@ -10,7 +10,7 @@ def to_dev(c):
             torch.from_numpy(c.vals).cuda())
 
 
-def context(c, eps, d=1, max_dim=64, seed=1, **kw):
+def context(c, eps, d=1, max_dim=64, seed=1, max_matvec=300000, **kw):
     from paper_2407_04634_amd import Context
 
     rp, ci, va = to_dev(c)
@@ -18,5 +18,5 @@ def context(c, eps, d=1, max_dim=64, seed=1, **kw):
     om = G.gaussian_start_block(c.n, d, seed)
     ctx = Context(rp, ci, va, c.m, c.n, D=torch.from_numpy(dv).cuda(),
                   Omega=torch.from_numpy(np.ascontiguousarray(om)).cuda(), eps=eps, d=d,
-                  max_dim=max_dim, **kw)
+                  max_dim=max_dim, max_matvec=max_matvec, **kw)
     return ctx, dv, om

@@ -1,0 +1,114 @@
+"""Algorithm 2 on the GPU (through the C ABI) vs the oracle and the closed forms."""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import exact, lanczos, refine
+from workloads import generators as G
+
+pytestmark = pytest.mark.gpu
+
+LAM2_ER20 = 0.36330958416634257  # smallest nonzero Laplacian eigenvalue of the seeded er20 instance
+EPS_ER20 = 0.1 * LAM2_ER20 ** 2
+
+
+def _basis(ctx):
+    return ctx.extract_basis().cpu().numpy()
+
+
+def test_first_cycle_ritz_values_match_oracle():
+    from tests.gpu_util import context
+
+    c = G.config("er20")
+    print("[solver] er20 first cycle", flush=True)
+    ctx, dv, om = context(c, EPS_ER20, d=1, max_dim=64, refine=0, max_cycles=1)
+    ctx.lanczos_run(allow_noconv=True)
+    th = np.array(ctx.ritz_values())
+    r = lanczos.algorithm2(c.to_scipy(), EPS_ER20, dv, om, 64, max_cycles=1)
+    nb = 4 * 16.67 ** 2  # ||B|| scale of this instance
+    assert th.shape == r["theta"].shape
+    assert np.max(np.abs(th - r["theta"])) < 1e-9 * nb
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_er20_nullity_and_subspace(prec):
+    from tests.gpu_util import context
+
+    c = G.config("er20")
+    print(f"[solver] er20 d=1 prec={prec}", flush=True)
+    ctx, dv, om = context(c, EPS_ER20, d=1, max_dim=64, prec=prec)
+    st = ctx.lanczos_run()
+    v0 = exact.indicator_basis(c.meta["labels"])
+    a = c.to_scipy()
+    r = lanczos.algorithm2(a, EPS_ER20, dv, om, 64)
+    assert st["nullity"] == r["N"] == 20
+    v = _basis(ctx)
+    assert v.shape == (c.n, 20)
+    assert exact.max_angle_sine(v, v0) <= 1e-8
+    afro = np.sqrt(np.sum(c.vals ** 2))
+    assert np.linalg.norm(a @ v) <= 1e-8 * afro
+    assert st["rel_resid_fro"] <= 1e-8
+    assert exact.orth_error_fro(v) <= c.n * 20 * exact.U64
+    vr, _ = refine.refine(a, r["V"], 1e-10)
+    assert exact.max_angle_sine(v, vr) <= 1e-8
+
+
+@pytest.mark.parametrize("d", [1, 2, 4, 8])
+def test_planted_small_block_sizes(d):
+    from tests.gpu_util import context
+
+    c = G.planted_nullity(1000, 1000, 10, seed=5)
+    a = c.to_scipy()
+    s = np.linalg.svd(a.toarray(), compute_uv=False)
+    smin = s[-11]
+    eps = 0.1 * smin ** 2
+    print(f"[solver] planted 1000 N=10 d={d}", flush=True)
+    ctx, dv, om = context(c, eps, d=d, max_dim=128, tol_abs_resid=1e-10 * smin, tol_rel_resid=0.0)
+    st = ctx.lanczos_run()
+    assert st["nullity"] == 10
+    v = _basis(ctx)
+    v0 = exact.planted_basis(c.meta["R"])
+    assert exact.max_angle_sine(v, v0) <= 1e-8
+    assert st["rel_resid_fro"] <= 1e-8
+
+
+def test_restart_state_planted_vs_oracle_nullity():
+    """Same D and Omega: the oracle's Algorithm 2 and the GPU agree on the nullity."""
+    from tests.gpu_util import context
+
+    c = G.planted_nullity(600, 600, 6, seed=9)
+    a = c.to_scipy()
+    s = np.linalg.svd(a.toarray(), compute_uv=False)
+    eps = 0.1 * s[-7] ** 2
+    print("[solver] planted 600 vs oracle", flush=True)
+    for d in (1, 4):
+        ctx, dv, om = context(c, eps, d=d, max_dim=96, seed=2)
+        st = ctx.lanczos_run()
+        r = lanczos.algorithm2(a, eps, dv, om, 96)
+        assert st["nullity"] == r["N"] == 6
+
+
+def test_fd_instance_backward_matches_dense_gradient():
+    import torch
+    from oracle import backward as bw
+    from tests.gpu_util import context
+
+    c = G.fd_instance()
+    a = c.to_scipy()
+    ad = a.toarray()
+    s = np.linalg.svd(ad, compute_uv=False)
+    smin = s[-9]
+    print("[solver] fd300 backward", flush=True)
+    ctx, dv, om = context(c, 0.1 * smin ** 2, d=1, max_dim=64, tol_abs_resid=1e-12 * smin,
+                          tol_rel_resid=0.0)
+    st = ctx.lanczos_run()
+    assert st["nullity"] == 8
+    v = _basis(ctx)
+    x = G.gaussian_matrix(c.n, 8, seed=5)
+    gsv = bw.gsv_pxf(v, x)
+    grad, it = ctx.backward(torch.from_numpy(gsv).cuda(), tol=1e-13)
+    grad = grad.cpu().numpy()
+    rows = np.repeat(np.arange(c.m), np.diff(c.rowptr))
+    ref = bw.dense_grad(ad, 8, bw.gs_pxf(x), rows, c.colind)
+    assert np.linalg.norm(grad - ref) <= 1e-6 * np.linalg.norm(ref)

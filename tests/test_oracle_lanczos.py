@@ -107,6 +107,11 @@ def test_restart_size_and_speed_rule():
     stop, _ = lanczos.speed_rule(hist + [(700, 3)], 1)
     assert stop
     assert lanczos.speed_rule([(100, 1), (900, 1)], 1) == (False, math.inf)  # one increase only
+    # d = 2: an interval closes only after >= 2 new values
+    hist2 = [(100, 1), (150, 2), (600, 3), (700, 3)]
+    stop, s = lanczos.speed_rule(hist2, 2)
+    assert s == 2 * (600 - 100) * 2 / 2 and not stop
+    assert lanczos.speed_rule([(100, 1), (150, 2), (400, 2)], 2) == (False, math.inf)
 
 
 def test_algorithm2_first_cycle_matches_algorithm1():
