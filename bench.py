@@ -128,6 +128,10 @@ def main():
     ap.add_argument("--prec", default="fp64", choices=["fp64", "mixed"])
     ap.add_argument("--max-dim", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--max-cycles", type=int, default=0,
+                    help="stop after this many restart cycles (profiling runs; the result is not valid)")
+    ap.add_argument("--no-refine", action="store_true", help="skip the FP64 refinement (profiling runs)")
+    ap.add_argument("--profile", type=int, default=1, help="HIP-event timing of the SpMV pair")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only; --gpus {args.gpus} is not supported "
@@ -151,15 +155,17 @@ def main():
     om = torch.from_numpy(np.ascontiguousarray(G.gaussian_start_block(c.n, args.d, 1))).cuda()
     ctx = Context(rp, ci, va, c.m, c.n, D=dv, Omega=om, eps=eps, d=args.d, max_dim=max_dim,
                   prec=PREC_MIXED if args.prec == "mixed" else PREC_FP64, tol_angle=1e-9,
-                  tol_rel_resid=1e-10, max_matvec=20_000_000)
+                  tol_rel_resid=1e-10, max_matvec=20_000_000, max_cycles=args.max_cycles,
+                  refine=0 if args.no_refine else 1, profile=args.profile)
+    partial = args.max_cycles > 0 or args.no_refine
     for w in range(args.warmup):
-        st = ctx.lanczos_run()
+        st = ctx.lanczos_run(allow_noconv=partial)
         print(f"[bench] warmup {w}: {json.dumps(st)}", file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     stats = []
     for s in range(args.steps):
-        stats.append(ctx.lanczos_run())
+        stats.append(ctx.lanczos_run(allow_noconv=partial))
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     st = stats[-1]

@@ -79,6 +79,8 @@ typedef struct {
                             threshold of the enabled (non-zero) criteria applies.   */
   int64_t max_refine_iter; /* CGLS iteration cap of the refinement                   */
   int32_t max_cycles;    /* stop after this many restart cycles (0 = no limit)       */
+  int32_t profile;       /* 1: time the SpMV pair with HIP events on the context's
+                            stream at every 16th Lanczos step (nsp_stats.t_spmv_*)   */
   uint64_t seed;         /* seed of the built-in Philox4x32-10 draws of D and Omega,
                             used only when the caller passes D or Omega as NULL       */
 } nsp_params;
@@ -101,12 +103,15 @@ typedef struct {
   double t_lanczos_s;      /* time in the Lanczos steps (device events)                 */
   double t_restart_s;      /* time in Rayleigh-Ritz + restarts                          */
   double t_refine_s;       /* time in the refinement                                    */
+  double t_spmv_a_us;      /* profile: mean duration of one y = A x launch (us)         */
+  double t_spmv_at_us;     /* profile: mean duration of one fused A^T launch (us)       */
+  int64_t spmv_samples;    /* profile: number of timed launch pairs                     */
 } nsp_stats;
 
 /* Fill *p with defaults: eps = 1e-3 (Sec. 5.3), d = 1, max_dim = 64,
    max_matvec = 10^7, ro_tol = 0, prec = FP64, refine = 1, tol_rel_resid = 1e-10,
    tol_abs_resid = 0, tol_angle = 1e-9, max_refine_iter = 10^6, max_cycles = 0,
-   seed = 20240704. */
+   profile = 0, seed = 20240704. */
 void nsp_default_params(nsp_params* p);
 
 /* Create a solver context for A (m x n, nnz stored entries, CSR).

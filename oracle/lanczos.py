@@ -27,7 +27,12 @@ listed with its justification in the design notes):
       explicit subtraction of Q_l Xi_l); for k = l-1 the pair
       w_{k+1,l}|G_k| + w_{k,l-1}|G_{l-1}| cancels exactly in the derivation
       (the Q_{l-1} coupling is subtracted explicitly) and is dropped.
-  R5  "reorthogonalize" = classical Gram-Schmidt applied twice (CGS2).
+  R5  "reorthogonalize" in the partial reorthogonalisation events = one
+      pass of classical Gram-Schmidt: the vectors are semi-orthogonal there
+      (bounds just above u_RO = sqrt(u)), so one projection leaves a component
+      of order u and a second pass would only matter under cancellation.  The
+      first step of a cycle and the restart (components of order ||B|| or 1)
+      use classical Gram-Schmidt twice (CGS2).
   R6  QR = orthonormal factor with positive-diagonal triangular factor (the
       unique thin QR of a full-rank block); d = 1 is normalisation.
   R7  ||B|| in u_d: ||A||_1 ||A||_inf + eps in the first cycle, then the
@@ -68,6 +73,13 @@ def block_qr(p: np.ndarray):
     s = np.sign(np.diag(r)).copy()
     s[s == 0] = 1.0
     return q * s[None, :], r * s[:, None]
+
+
+def cgs1(z: np.ndarray, p: np.ndarray) -> np.ndarray:
+    """(I - Z Z^T) P by one pass of classical Gram-Schmidt (reading R5)."""
+    if z.shape[1] == 0:
+        return p
+    return p - z @ (z.T @ p)
 
 
 def cgs2(z: np.ndarray, p: np.ndarray) -> np.ndarray:
@@ -277,9 +289,9 @@ def algorithm2(a, eps: float, dvec: np.ndarray, omega: np.ndarray, dim_k: int,
                 orth_trace.append((ell, wmax, true))
             if not full_reorth and wmax > u_ro:
                 # reorthogonalise Q_ell and Q_{ell+1} against Z_{ell-1} (Sec. 4.2)
-                blk = cgs2(zb[:, :c], zb[:, c:c + 2 * d])
+                blk = cgs1(zb[:, :c], zb[:, c:c + 2 * d])
                 qlr, _ = block_qr(blk[:, :d])
-                qnr, _ = block_qr(cgs2(qlr, blk[:, d:]))
+                qnr, _ = block_qr(cgs1(qlr, blk[:, d:]))
                 zb[:, c:c + d] = qlr
                 zb[:, c + d:c + 2 * d] = qnr
                 wrec.reset_column(ell, u_d)

@@ -43,6 +43,7 @@ class Params(ctypes.Structure):
         ("tol_angle", ctypes.c_double),
         ("max_refine_iter", ctypes.c_int64),
         ("max_cycles", ctypes.c_int32),
+        ("profile", ctypes.c_int32),
         ("seed", ctypes.c_uint64),
     ]
 
@@ -65,6 +66,9 @@ class Stats(ctypes.Structure):
         ("t_lanczos_s", ctypes.c_double),
         ("t_restart_s", ctypes.c_double),
         ("t_refine_s", ctypes.c_double),
+        ("t_spmv_a_us", ctypes.c_double),
+        ("t_spmv_at_us", ctypes.c_double),
+        ("spmv_samples", ctypes.c_int64),
     ]
 
     def as_dict(self) -> dict:

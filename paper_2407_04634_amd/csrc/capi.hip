@@ -31,6 +31,17 @@ nsp_status guarded(F&& f) {
   }
 }
 
+// Order the library's stream after the caller's stream (call entry) and the
+// caller's stream after the library's (call exit).
+void enter(nsp_ctx* c) {
+  NSP_HIP(hipEventRecord(c->ev_in, c->user_stream));
+  NSP_HIP(hipStreamWaitEvent(c->stream, c->ev_in, 0));
+}
+void leave(nsp_ctx* c) {
+  NSP_HIP(hipEventRecord(c->ev_out, c->stream));
+  NSP_HIP(hipStreamWaitEvent(c->user_stream, c->ev_out, 0));
+}
+
 void validate_params(const nsp_params* p, int64_t n) {
   NSP_REQUIRE(p != nullptr, "params must not be NULL");
   NSP_REQUIRE(std::isfinite(p->eps) && p->eps > 0.0, "eps must be finite and > 0");
@@ -66,6 +77,7 @@ void nsp_default_params(nsp_params* p) {
   p->tol_angle = 1e-9;
   p->max_refine_iter = 1000000;
   p->max_cycles = 0;
+  p->profile = 0;
   p->seed = 20240704ull;
 }
 
@@ -87,19 +99,22 @@ nsp_status nullspace_init(nsp_ctx** out, int64_t m, int64_t n, int64_t nnz, cons
     c->n = n;
     c->nnz = nnz;
     c->prm = *p;
-    c->stream = static_cast<hipStream_t>(stream);
+    c->user_stream = static_cast<hipStream_t>(stream);
+    NSP_HIP(hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking));
+    NSP_HIP(hipEventCreateWithFlags(&c->ev_in, hipEventDisableTiming));
+    NSP_HIP(hipEventCreateWithFlags(&c->ev_out, hipEventDisableTiming));
+    c->pin_d = c->pind.ensure((size_t)p->max_dim + 16);
+    c->pin_i = c->pini.ensure(64);
+    // the caller's arrays may still be written on its stream
+    NSP_HIP(hipStreamSynchronize(c->user_stream));
     NSP_BLAS(rocblas_create_handle(&c->blas));
     NSP_BLAS(rocblas_set_stream(c->blas, c->stream));
     c->A.colind = colind;
     c->A.val = vals;
-    // reduction scratch (shared by all kernels of the context; stream-ordered)
-    c->red_partials.alloc(sizeof(double) * nsp::kRedBlocks * 256);
-    c->red_counters.alloc(sizeof(unsigned) * 16);
-    NSP_HIP(hipMemsetAsync(c->red_counters.p, 0, sizeof(unsigned) * 16, c->stream));
-    c->red.partials = c->red_partials.as<double>();
-    c->red.counter = c->red_counters.as<unsigned>();
-    c->red.max_blocks = nsp::kRedBlocks;
-    c->red.max_values = 256;
+    // per-block partials of the step reductions (stream-ordered reuse)
+    c->part_xi.alloc(sizeof(double) * nsp::kRedBlocks * nsp::kMaxD * nsp::kMaxD);
+    c->part_g.alloc(sizeof(double) * nsp::kRedBlocks * nsp::kMaxD * nsp::kMaxD);
+    c->part_g2.alloc(sizeof(double) * nsp::kRedBlocks * nsp::kMaxD * nsp::kMaxD);
     nsp::build_transpose(c, rowptr);
     nsp::init_random(c, D, Omega);
     nsp::matrix_norms(c);
@@ -120,14 +135,18 @@ nsp_status apply_op(nsp_ctx* ctx, const double* X, int64_t ldx, double* Y, int64
     NSP_REQUIRE(ncols >= 1, "ncols must be >= 1");
     NSP_REQUIRE(X != nullptr && Y != nullptr, "X and Y must not be NULL");
     NSP_REQUIRE(ldx >= ctx->n && ldy >= ctx->n, "leading dimensions must be >= n");
+    enter(ctx);
     nsp::apply_b_colmajor(ctx, X, ldx, Y, ldy, ncols);
+    leave(ctx);
   });
 }
 
 nsp_status lanczos_run(nsp_ctx* ctx, nsp_stats* st) {
   nsp_status s = guarded([&] {
     NSP_REQUIRE(ctx != nullptr, "ctx must not be NULL");
+    enter(ctx);
     nsp::solve(ctx);
+    leave(ctx);
   });
   if (ctx && st) *st = ctx->stats;
   if (s == NSP_OK && ctx && !ctx->stats.converged) {
@@ -151,6 +170,7 @@ nsp_status extract_basis(nsp_ctx* ctx, double* V, int64_t ldv) {
     if (ctx->state < 1) throw nsp::Error(NSP_ERR_STATE, "no basis yet: call lanczos_run first");
     if (ctx->nullity == 0) return;
     NSP_REQUIRE(V != nullptr && ldv >= ctx->n, "V must be non-NULL with ldv >= n");
+    enter(ctx);
     NSP_HIP(hipMemcpy2DAsync(V, sizeof(double) * ldv, ctx->V.p, sizeof(double) * ctx->n,
                              sizeof(double) * ctx->n, ctx->nullity, hipMemcpyDeviceToDevice,
                              ctx->stream));
@@ -176,7 +196,9 @@ nsp_status backward(nsp_ctx* ctx, const double* GsV, int64_t ld, double* grad_va
     NSP_REQUIRE(grad_vals != nullptr || ctx->nnz == 0, "grad_vals must not be NULL");
     NSP_REQUIRE(ctx->nullity == 0 || (GsV != nullptr && ld >= ctx->n), "GsV must be n x N, ld >= n");
     NSP_REQUIRE(tol > 0.0 && max_iter > 0, "tol and max_iter must be positive");
+    enter(ctx);
     nsp::run_backward(ctx, GsV, ld, grad_vals, tol, max_iter, iters);
+    leave(ctx);
   });
 }
 
@@ -184,7 +206,11 @@ void nullspace_destroy(nsp_ctx* ctx) {
   if (!ctx) return;
   if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
   if (ctx->blas) (void)rocblas_destroy_handle(ctx->blas);
-  delete ctx;
+  if (ctx->ev_in) (void)hipEventDestroy(ctx->ev_in);
+  if (ctx->ev_out) (void)hipEventDestroy(ctx->ev_out);
+  hipStream_t s = ctx->stream;
+  delete ctx;  // frees device buffers first
+  if (s) (void)hipStreamDestroy(s);
 }
 
 const char* nullspace_last_error(void) { return g_last_error.c_str(); }

@@ -69,17 +69,8 @@ struct DBuf {
   template <typename T> T* as() const { return static_cast<T*>(p); }
 };
 
-// Reduction scratch for the "last block finishes the reduction" pattern:
-// per-block partials plus an arrival counter that the last block resets.
-struct Reducer {
-  double* partials = nullptr;  // capacity: max_blocks * max_values doubles
-  unsigned* counter = nullptr; // one counter per concurrent use site
-  int max_blocks = 0;
-  int max_values = 0;
-};
-
 constexpr int kMaxD = 8;            // largest supported block size
-constexpr int kRedBlocks = 512;     // grid cap of kernels that reduce
+constexpr int kRedBlocks = 512;     // grid cap of kernels that write per-block partials
 constexpr int kThreads = 256;       // threads per block of streaming kernels
 
 // ---------------------------------------------------------------------------
@@ -94,13 +85,42 @@ struct Csr {
   int lpr = 1;                      // lanes per row chosen from the mean row length
 };
 
+// pinned host buffer for the small read-backs (hipHostMalloc, grown on demand)
+template <typename T>
+struct PinBuf {
+  T* p = nullptr;
+  size_t count = 0;
+  PinBuf() = default;
+  PinBuf(const PinBuf&) = delete;
+  PinBuf& operator=(const PinBuf&) = delete;
+  ~PinBuf() { release(); }
+  T* ensure(size_t n) {
+    if (n <= count && p) return p;
+    release();
+    NSP_HIP(hipHostMalloc((void**)&p, sizeof(T) * n, hipHostMallocDefault));
+    count = n;
+    return p;
+  }
+  void release() {
+    if (p) (void)hipHostFree(p);
+    p = nullptr;
+    count = 0;
+  }
+};
+
 }  // namespace nsp
 
 struct nsp_ctx {
   int64_t m = 0, n = 0, nnz = 0;
   nsp_params prm{};
-  hipStream_t stream = nullptr;
+  hipStream_t stream = nullptr;       // the library's own non-blocking stream (all work)
+  hipStream_t user_stream = nullptr;  // the caller's stream; ordered by events at each call
+  hipEvent_t ev_in = nullptr, ev_out = nullptr;
   rocblas_handle blas = nullptr;
+  nsp::PinBuf<double> pind;           // pinned read-back buffers
+  nsp::PinBuf<int> pini;
+  double* pin_d = nullptr;            // = pind.p, at least max_dim + 16 doubles
+  int* pin_i = nullptr;               // = pini.p, at least 64 ints
 
   // A (caller's colind/vals; own int32 row offsets) and its stored transpose
   nsp::Csr A, AT;
@@ -119,19 +139,12 @@ struct nsp_ctx {
   nsp::DBuf ring;           // 3 row-interleaved copies of consecutive blocks (d > 1)
   nsp::DBuf Y;              // m x d, row-interleaved, working precision
   nsp::DBuf P;              // n x d, row-interleaved, working precision
-  nsp::DBuf C;              // n x 2d row-interleaved scratch (reorthogonalisation)
-  nsp::DBuf H;              // k x 2d coefficients (FP64)
-  nsp::DBuf xi, gam;        // (L+2) blocks of d x d (FP64), column-major
-  nsp::DBuf rinv;           // d x d (and 2d x 2d) inverse triangular factors
-  nsp::DBuf wmat;           // (L+3)^2 W-recurrence bounds
   nsp::DBuf theta_kept;     // K Ritz values kept at the last restart
   nsp::DBuf fmat;           // d x K coupling block F
   nsp::DBuf tmat, evals, ework; // T (K x K), eigenvalues, rocSOLVER E workspace
   nsp::DBuf flags;          // device ints: [0] reorth flag, [1] breakdown, [2] nonfinite,
                             // [3] reorth event counter
-  nsp::DBuf red_partials, red_counters;
-  nsp::Reducer red;
-  int* dinfo = nullptr;
+  nsp::DBuf part_xi, part_g, part_g2, part_c;  // per-block partials of the step reductions
 
   // result
   nsp::DBuf V;              // n x N column-major FP64 (final basis)
@@ -147,11 +160,6 @@ namespace nsp {
 void build_transpose(nsp_ctx* c, const int64_t* rowptr64);
 void init_random(nsp_ctx* c, const double* D, const double* Omega);
 double matrix_norms(nsp_ctx* c);
-
-// y(m x d) = A x ; generic strides: element (i, j) of x at x[i*xrs + j*xcs]
-template <typename VT>
-void spmm(nsp_ctx* c, const Csr& a, int d, const VT* x, int64_t xrs, int64_t xcs, VT* y,
-          int64_t yrs, int64_t ycs);
 
 // apply_op helper: Y = B X (FP64, column-major, ld)
 void apply_b_colmajor(nsp_ctx* c, const double* X, int64_t ldx, double* Y, int64_t ldy, int ncols);

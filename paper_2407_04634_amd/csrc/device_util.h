@@ -45,47 +45,30 @@ __device__ __forceinline__ void block_sum(double (&v)[NV], double* smem) {
   __syncthreads();
 }
 
-// Grid reduction epilogue.  Every block calls this with its block sums in
-// thread 0 (after block_sum).  The block that arrives last sums the partials
-// of all blocks in block order (deterministic) into ``out`` (NV doubles),
-// resets the counter, and returns true in all its threads; the other blocks
-// return false.  Partials are written with device-scope release semantics and
-// read after an acquire, so the last block sees every block's partial even
-// when blocks ran on different XCDs.
+// Fixed-order sum of per-block partials, done cooperatively by one block:
+// res[v] = sum_b part[b * NV + v] for v < NV.  Every thread of the block must
+// call it; res (shared, NV doubles) is valid in all threads afterwards.  smem
+// must hold blockDim.x doubles.  The partials come from an earlier kernel on
+// the same stream, so no fence or atomic is involved.
 template <int NV>
-__device__ bool grid_sum_last(const double (&v)[NV], double* partials, unsigned* counter,
-                              double* out, double* smem) {
-  static_assert(NV <= 256, "grid_sum_last handles at most 256 values");
-  __shared__ int am_last;
-  if (threadIdx.x == 0) {
-#pragma unroll
-    for (int i = 0; i < NV; ++i) partials[(size_t)blockIdx.x * NV + i] = v[i];
-    __threadfence();
-    unsigned prev = __hip_atomic_fetch_add(counter, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
-    am_last = (prev == gridDim.x - 1);
-  }
-  __syncthreads();
-  if (!am_last) return false;
-  __threadfence();
-  // thread t sums value (t % NV) over blocks b = t / NV, t / NV + G, ... (G = groups)
-  const int groups = blockDim.x / NV > 0 ? blockDim.x / NV : 1;
+__device__ __forceinline__ void reduce_partials(const double* __restrict__ part, int nparts,
+                                                double* res, double* smem) {
+  static_assert(NV <= 256, "at most 256 values");
   const int t = threadIdx.x;
+  const int groups = (int)blockDim.x / NV > 0 ? (int)blockDim.x / NV : 1;
   double s = 0.0;
   if (t < groups * NV) {
-    const int i = t % NV, g = t / NV;
-    for (unsigned b = g; b < gridDim.x; b += groups)
-      s += partials[(size_t)b * NV + i];
+    const int v = t % NV, g = t / NV;
+    for (int b = g; b < nparts; b += groups) s += part[(size_t)b * NV + v];
   }
   smem[t] = s;
   __syncthreads();
   if (t < NV) {
     double r = 0.0;
     for (int g = 0; g < groups; ++g) r += smem[g * NV + t];
-    out[t] = r;
+    res[t] = r;
   }
-  if (t == 0) __hip_atomic_store(counter, 0u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
   __syncthreads();
-  return true;
 }
 
 }  // namespace nsp

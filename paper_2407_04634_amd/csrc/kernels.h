@@ -8,39 +8,57 @@ namespace nsp {
 // sparse
 template <typename VT>
 void spmm_block(nsp_ctx* c, const Csr& a, int d, const VT* x, VT* y);
+// returns the number of per-block Xi partials written to part_xi (the grid size)
 template <typename VT>
-void spmmT_step(nsp_ctx* c, int d, const VT* y, const VT* x, const VT* xp, const double* gprev,
-                VT* out, double* xi_out, double* xi_nrm = nullptr);
+int spmmT_step(nsp_ctx* c, int d, const VT* y, const VT* x, const VT* xp, const double* gprev,
+               VT* out, double* part_xi);
 void spmm_wide(nsp_ctx* c, const Csr& a, int k, const double* x, double* y);
 void sddmm(nsp_ctx* c, int k, const double* u, const double* v, double* grad);
 void colmajor_to_rows(nsp_ctx* c, int64_t rows, int k, const double* src, int64_t ld, double* dst);
 void rows_to_colmajor(nsp_ctx* c, int64_t rows, int k, const double* src, double* dst, int64_t ld);
 
-// dense: Lanczos step
+// arguments of the W-recurrence (Sec. 4.2), evaluated inside the final QR kernel
+struct WArgs {
+  int ell, l0, ldw;
+  double u_d, u_ro;
+  const double *n_xi, *n_gam, *n_theta, *n_f;
+  double* w;
+  int* flags;
+};
+
+// dense: Lanczos step.  Each returns its grid size = number of partials written.
 template <typename VT>
-void sub_gram(nsp_ctx* c, int d, int64_t n, VT* p, const VT* x, const double* xi, double* gam_out,
-              double* rinv, double* nrm_gam, double* nrm_ginv);
+int sub_gram(nsp_ctx* c, int d, int64_t n, VT* p, const VT* x, const double* part_xi, int nparts_xi,
+             double* xi_out, double* nrm_xi, double* part_g);
 template <typename VT>
-void scale_block(nsp_ctx* c, int d, int64_t n, const VT* p, const double* rinv, VT* xn, VT* zcol,
-                 int64_t ldz, bool gram, double* gam, double* rinv2, double* nrm_gam,
-                 double* nrm_ginv);
-void wrec(nsp_ctx* c, int ell, int l0, double u_d, double u_ro, const double* n_xi,
-          const double* n_gam, const double* n_ginv, const double* n_theta, const double* n_f,
-          double* w, int ldw);
+int scale_block(nsp_ctx* c, int d, int64_t n, const VT* p, const double* part_g, int nparts,
+                VT* xn, VT* zcol, int64_t ldz, double* gam_out, double* nrm_gam, double* nrm_ginv,
+                double* part_g2, const WArgs* wa = nullptr);
+template <typename VT>
+void scale_block2(nsp_ctx* c, int d, int64_t n, const double* part_g2, int nparts, VT* xn, VT* zcol,
+                  int64_t ldz, double* gam, double* nrm_gam, double* nrm_ginv,
+                  const WArgs* wa = nullptr);
 void w_reset(nsp_ctx* c, int col0, int ncols, double u_d, double* w, int ldw);
 
-// dense: tall-skinny projection pair (CGS pass) and final scaling
+// dense: tall-skinny projection pair (one CGS pass) and final scaling
 int64_t ts_chunk_rows(int64_t n, int k, int nc);
+int64_t ts_part_c_len(int64_t n, int nc);
 template <typename VT>
 void ts_project(nsp_ctx* c, const int* cond, int d, int na, int64_t n, const VT* z, int64_t ldz,
-                int k, VT* a0, VT* a1, double* h, double* hpart, bool gram, double* rinv);
+                int k, VT* a0, VT* a1, double* h, double* hpart, bool gram, double* part_c,
+                double* rinv);
+// C = C R^{-1}; R from the Gram partials of the preceding ts_project(gram) (R^{-1}, R -> rinv)
 template <typename VT>
 void ts_scale(nsp_ctx* c, const int* cond, int d, int na, int64_t n, VT* a0, VT* a1,
-              const double* rinv, VT* z0, int64_t ldz);
+              const double* part_c, double* rinv, VT* z0, int64_t ldz);
 
 // dense: restart / extraction
 void assemble_t(nsp_ctx* c, int K, int d, int kk, const double* theta, const double* f,
                 const double* xi, const double* gam, double* t);
+// F = R Gamma_L V_Z(K-d:K, 0:kn), theta_kept = evals[0:kn], kept-block norms
+void restart_coupling(nsp_ctx* c, int K, int d, int kn, const double* vz, const double* gam_l,
+                      const double* rinvc, const double* evals, double* f, double* theta_kept,
+                      double* n_theta, double* n_f);
 template <typename SRC, typename DST>
 void cm_to_ri(nsp_ctx* c, int64_t n, int d, const SRC* s, int64_t ld, DST* o);
 template <typename SRC, typename DST>

@@ -66,24 +66,97 @@ __device__ double fro(int k, const double* a) {
 }
 
 // ---------------------------------------------------------------------------
-// Lanczos step, QR part.
-// k_sub_gram:  P -= X Xi (if SUB) ; G = P^T P reduced ; last block: Cholesky
-//              G = R^T R, stores R (gam_out), R^{-1} (rinv), ||R||_F, ||R^-1||_F.
+// W-recurrence (Sec. 4.2): column ell+1 of the bounds w_{k,j} >= ||Q_k^T Q_j||,
+// blocks numbered from 1, W (ldw x ldw) column-major.  Executed by one block.
+// Sets flags[0] = 1 (and counts the event in flags[3]) when a bound exceeds
+// u_RO; the reorthogonalisation kernels that follow then run, and columns ell
+// and ell+1 are reset to u_d here.
 // ---------------------------------------------------------------------------
-template <typename VT, int D, bool SUB>
+__device__ void wrec_block(const WArgs& a, double gi, double* red) {
+  const int t = threadIdx.x, ell = a.ell, l0 = a.l0;
+  double* w = a.w;
+  const int ldw = a.ldw;
+  auto W = [&](int k, int j) -> double& { return w[k + (int64_t)j * ldw]; };
+  double s = 0.0;
+  for (int i = 1 + t; i <= l0; i += blockDim.x) s += W(i, ell) * a.n_f[i];
+  red[t] = s;
+  __syncthreads();
+  for (int off = blockDim.x / 2; off > 0; off >>= 1) {
+    if (t < off) red[t] += red[t + off];
+    __syncthreads();
+  }
+  const double sum_f = red[0];
+  __syncthreads();
+  double mx = 0.0;
+  for (int k = 1 + t; k <= ell; k += blockDim.x) {
+    double v;
+    if (k == ell) {
+      v = a.u_d;
+    } else if (k <= l0) {
+      v = gi * (W(k, ell) * (a.n_theta[k] + a.n_xi[ell]) + W(l0 + 1, ell) * a.n_f[k] +
+                W(k, ell - 1) * a.n_gam[ell - 1] + 2.0 * a.u_d);
+    } else if (k == l0 + 1) {
+      double acc = W(k, ell) * (a.n_xi[k] + a.n_xi[ell]) + sum_f + 2.0 * a.u_d;
+      if (k < ell - 1) acc += W(k + 1, ell) * a.n_gam[k] + W(k, ell - 1) * a.n_gam[ell - 1];
+      v = gi * acc;
+    } else {
+      double acc = W(k, ell) * (a.n_xi[k] + a.n_xi[ell]) + W(k - 1, ell) * a.n_gam[k - 1] + 2.0 * a.u_d;
+      if (k < ell - 1) acc += W(k + 1, ell) * a.n_gam[k] + W(k, ell - 1) * a.n_gam[ell - 1];
+      v = gi * acc;
+    }
+    W(k, ell + 1) = v;
+    if (k < ell) mx = fmax(mx, v);
+  }
+  red[t] = mx;
+  __syncthreads();
+  for (int off = blockDim.x / 2; off > 0; off >>= 1) {
+    if (t < off) red[t] = fmax(red[t], red[t + off]);
+    __syncthreads();
+  }
+  const bool need = red[0] > a.u_ro || !(red[0] == red[0]);
+  __syncthreads();
+  if (need) {
+    for (int k = 1 + t; k < ell; k += blockDim.x) W(k, ell) = a.u_d;
+    for (int k = 1 + t; k <= ell; k += blockDim.x) W(k, ell + 1) = a.u_d;
+  }
+  if (t == 0) {
+    a.flags[0] = need ? 1 : 0;
+    if (need) a.flags[3] += 1;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Lanczos step, QR part (no grid-wide synchronisation inside a kernel: each
+// kernel reduces the per-block partials the previous kernel wrote, in block
+// order, so results are deterministic and need no atomics or fences).
+//
+// k_sub_gram: [XI: Xi = sum of the Xi partials, symmetrised; block 0 stores Xi
+//             and ||Xi||_F]; [SUB: P -= X Xi]; writes per-block partials of P^T P.
+// ---------------------------------------------------------------------------
+constexpr int kSmem = kThreads * 4;  // shared scratch doubles for block sums of <= 256 values
+
+template <typename VT, int D, bool XI, bool SUB>
 __global__ __launch_bounds__(kThreads) void k_sub_gram(int64_t n, VT* __restrict__ p,
                                                        const VT* __restrict__ x,
-                                                       const double* __restrict__ xi,
-                                                       double* partials, unsigned* counter,
-                                                       double* gam_out, double* rinv,
-                                                       double* nrm_gam, double* nrm_ginv,
-                                                       int* flags) {
+                                                       const double* __restrict__ part_xi,
+                                                       int nparts_xi, double* xi_out,
+                                                       double* nrm_xi, double* __restrict__ part_g) {
   constexpr int NV = D * D;
-  __shared__ double smem[kThreads > NV * (kThreads / kWave) ? kThreads : NV * (kThreads / kWave)];
+  __shared__ double smem[kSmem];
+  __shared__ double res[NV];
   __shared__ double xs[NV];
-  if (SUB) {
-    if (threadIdx.x < NV) xs[threadIdx.x] = xi[threadIdx.x];
+  if constexpr (XI) {
+    reduce_partials<NV>(part_xi, nparts_xi, res, smem);
+    if (threadIdx.x < NV) {
+      const int a = threadIdx.x % D, b = threadIdx.x / D;
+      xs[threadIdx.x] = 0.5 * (res[a + b * D] + res[b + a * D]);
+    }
     __syncthreads();
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+      double f2 = 0.0;
+      for (int i = 0; i < NV; ++i) { xi_out[i] = xs[i]; f2 += xs[i] * xs[i]; }
+      if (nrm_xi) *nrm_xi = sqrt(f2);
+    }
   }
   double g[NV];
 #pragma unroll
@@ -93,7 +166,7 @@ __global__ __launch_bounds__(kThreads) void k_sub_gram(int64_t n, VT* __restrict
     VT v[D];
 #pragma unroll
     for (int j = 0; j < D; ++j) v[j] = p[r * D + j];
-    if (SUB) {
+    if constexpr (SUB) {
       VT xr[D];
 #pragma unroll
       for (int j = 0; j < D; ++j) xr[j] = x[r * D + j];
@@ -113,38 +186,52 @@ __global__ __launch_bounds__(kThreads) void k_sub_gram(int64_t n, VT* __restrict
       for (int b = 0; b < D; ++b) g[a + b * D] += (double)v[a] * (double)v[b];
   }
   block_sum<NV>(g, smem);
-  __shared__ double res[NV];
-  if (grid_sum_last<NV>(g, partials, counter, res, smem)) {
-    if (threadIdx.x == 0) {
-      double r[NV], ri[NV];
-      const bool ok = chol_upper_inv(D, res, r, ri);
-      if (!ok) atomicOr(flags + 1, 1);
-      for (int i = 0; i < NV; ++i) { gam_out[i] = r[i]; rinv[i] = ri[i]; }
-      if (nrm_gam) *nrm_gam = fro(D, r);
-      if (nrm_ginv) *nrm_ginv = fro(D, ri);
-    }
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int i = 0; i < NV; ++i) part_g[(size_t)blockIdx.x * NV + i] = g[i];
   }
 }
 
-// k_scale: Xn = P R^{-1}; written to the ring slot ``xn`` and, when zcol is not
-// null, to D columns of the column-major basis.  With GRAM, also reduces the
-// Gram matrix of Xn and (last block) refines: R2 from Cholesky, stores
-// R2^{-1} in rinv2 and Gamma <- R2 Gamma.
-template <typename VT, int D, bool GRAM>
-__global__ __launch_bounds__(kThreads) void k_scale(int64_t n, const VT* __restrict__ p,
-                                                    const double* __restrict__ rinv,
-                                                    VT* __restrict__ xn, VT* __restrict__ zcol,
-                                                    int64_t ldz, double* partials,
-                                                    unsigned* counter, double* gam, double* rinv2,
-                                                    double* nrm_gam, double* nrm_ginv, int* flags) {
-  constexpr int NV = GRAM ? D * D : 1;
-  __shared__ double smem[kThreads > NV * (kThreads / kWave) ? kThreads : NV * (kThreads / kWave)];
-  __shared__ double ri[D * D];
-  if (threadIdx.x < D * D) ri[threadIdx.x] = rinv[threadIdx.x];
+// k_scale: G = sum of the Gram partials; Cholesky G = R^T R (every block, one
+// thread); Xn = P R^{-1} written to the ring slot ``xn`` and, when zcol is not
+// null, to D basis columns.  Block 0 stores R (the new Gamma), ||R||_F and
+// ||R^{-1}||_F.  With GRAM it also writes the Gram partials of Xn for the
+// second Cholesky-QR pass (k_scale2).
+template <typename VT, int D, bool GRAM, bool WREC>
+__global__ __launch_bounds__(kThreads) void k_scale(int64_t n, const VT* p,
+                                                    const double* __restrict__ part_g, int nparts,
+                                                    VT* xn, VT* __restrict__ zcol, int64_t ldz,
+                                                    double* gam_out, double* nrm_gam,
+                                                    double* nrm_ginv, double* __restrict__ part_g2,
+                                                    int* flags, WArgs wa) {
+  constexpr int NV = D * D;
+  __shared__ double smem[kSmem];
+  __shared__ double res[NV];
+  __shared__ double ri[NV];
+  __shared__ double gi_s;
+  reduce_partials<NV>(part_g, nparts, res, smem);
+  if (threadIdx.x == 0) {
+    double r[NV], rv[NV];
+    const bool ok = chol_upper_inv(D, res, r, rv);
+    for (int i = 0; i < NV; ++i) ri[i] = rv[i];
+    gi_s = fro(D, rv);
+    if (blockIdx.x == 0) {
+      if (!ok) atomicOr(flags + 1, 1);
+      if (gam_out)
+        for (int i = 0; i < NV; ++i) gam_out[i] = r[i];
+      if (nrm_gam) *nrm_gam = fro(D, r);
+      if (nrm_ginv) *nrm_ginv = gi_s;
+    }
+  }
   __syncthreads();
-  double g[NV];
+  // the W-recurrence needs ||Gamma_ell^{-1}||; for d = 1 the QR is final here
+  if constexpr (WREC) {
+    if (blockIdx.x == 0) wrec_block(wa, gi_s, smem);
+  }
+  constexpr int NG = GRAM ? NV : 1;
+  double g[NG];
 #pragma unroll
-  for (int i = 0; i < NV; ++i) g[i] = 0.0;
+  for (int i = 0; i < NG; ++i) g[i] = 0.0;
   for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < n;
        r += (int64_t)gridDim.x * blockDim.x) {
     VT v[D], o[D];
@@ -171,98 +258,85 @@ __global__ __launch_bounds__(kThreads) void k_scale(int64_t n, const VT* __restr
     }
   }
   if constexpr (GRAM) {
-    block_sum<NV>(g, smem);
-    __shared__ double res[NV];
-    if (grid_sum_last<NV>(g, partials, counter, res, smem)) {
-      if (threadIdx.x == 0) {
-        double r2[NV], r2i[NV], gn[NV], rin[NV];
-        const bool ok = chol_upper_inv(D, res, r2, r2i);
-        if (!ok) atomicOr(flags + 1, 1);
-        // Gamma <- R2 Gamma ; (R2 Gamma)^{-1} = Gamma^{-1} R2^{-1}
-        for (int i = 0; i < D; ++i)
-          for (int j = 0; j < D; ++j) {
-            double s = 0.0, t = 0.0;
-            for (int l = 0; l < D; ++l) {
-              s += r2[i + l * D] * gam[l + j * D];
-              t += rinv[i + l * D] * r2i[l + j * D];
-            }
-            gn[i + j * D] = s;
-            rin[i + j * D] = t;
-          }
-        for (int i = 0; i < NV; ++i) { gam[i] = gn[i]; rinv2[i] = r2i[i]; }
-        if (nrm_gam) *nrm_gam = fro(D, gn);
-        if (nrm_ginv) *nrm_ginv = fro(D, rin);
-      }
+    block_sum<NG>(g, smem);
+    if (threadIdx.x == 0) {
+#pragma unroll
+      for (int i = 0; i < NG; ++i) part_g2[(size_t)blockIdx.x * NG + i] = g[i];
     }
   }
 }
 
-// ---------------------------------------------------------------------------
-// W-recurrence (Sec. 4.2): column ell+1 of the bounds w_{k,j} >= ||Q_k^T Q_j||.
-// One block.  W is (ldw x ldw) column-major, blocks numbered from 1.  Sets
-// flags[0] = 1 (and counts the event in flags[3]) when a bound exceeds u_RO,
-// in which case the caller's reorthogonalisation kernels run and the columns
-// ell and ell+1 are reset to u_d here.
-// ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_wrec(int ell, int l0, double u_d, double u_ro,
-                                              const double* __restrict__ n_xi,
-                                              const double* __restrict__ n_gam,
-                                              const double* __restrict__ n_ginv,
-                                              const double* __restrict__ n_theta,
-                                              const double* __restrict__ n_f, double* w, int ldw,
-                                              int* flags) {
-  __shared__ double red[256];
-  __shared__ double sum_f_s;
-  const int t = threadIdx.x;
-  auto W = [&](int k, int j) -> double& { return w[k + (int64_t)j * ldw]; };
-  // sum_{i <= l0} w_{i,ell} ||F_i||
-  double s = 0.0;
-  for (int i = 1 + t; i <= l0; i += blockDim.x) s += W(i, ell) * n_f[i];
-  red[t] = s;
-  __syncthreads();
-  for (int off = 128; off > 0; off >>= 1) {
-    if (t < off) red[t] += red[t + off];
-    __syncthreads();
-  }
-  if (t == 0) sum_f_s = red[0];
-  __syncthreads();
-  const double sum_f = sum_f_s;
-  const double gi = n_ginv[ell];
-  double mx = 0.0;
-  for (int k = 1 + t; k <= ell; k += blockDim.x) {
-    double v;
-    if (k == ell) {
-      v = u_d;
-    } else if (k <= l0) {
-      v = gi * (W(k, ell) * (n_theta[k] + n_xi[ell]) + W(l0 + 1, ell) * n_f[k] +
-                W(k, ell - 1) * n_gam[ell - 1] + 2.0 * u_d);
-    } else if (k == l0 + 1) {
-      double acc = W(k, ell) * (n_xi[k] + n_xi[ell]) + sum_f + 2.0 * u_d;
-      if (k < ell - 1) acc += W(k + 1, ell) * n_gam[k] + W(k, ell - 1) * n_gam[ell - 1];
-      v = gi * acc;
-    } else {
-      double acc = W(k, ell) * (n_xi[k] + n_xi[ell]) + W(k - 1, ell) * n_gam[k - 1] + 2.0 * u_d;
-      if (k < ell - 1) acc += W(k + 1, ell) * n_gam[k] + W(k, ell - 1) * n_gam[ell - 1];
-      v = gi * acc;
+// Second Cholesky-QR pass (d > 1): R2 from the Gram partials of Xn; Xn <- Xn R2^{-1};
+// block 0 updates Gamma <- R2 Gamma and its norms.
+template <typename VT, int D, bool WREC>
+__global__ __launch_bounds__(kThreads) void k_scale2(int64_t n, const double* __restrict__ part_g2,
+                                                     int nparts, VT* xn, VT* __restrict__ zcol,
+                                                     int64_t ldz, double* gam, double* nrm_gam,
+                                                     double* nrm_ginv, int* flags, WArgs wa) {
+  constexpr int NV = D * D;
+  __shared__ double smem[kSmem];
+  __shared__ double res[NV];
+  __shared__ double ri[NV];
+  __shared__ double gi_s;
+  reduce_partials<NV>(part_g2, nparts, res, smem);
+  if (threadIdx.x == 0) {
+    double r2[NV], r2i[NV];
+    const bool ok = chol_upper_inv(D, res, r2, r2i);
+    for (int i = 0; i < NV; ++i) ri[i] = r2i[i];
+    if (blockIdx.x == 0) {
+      if (!ok) atomicOr(flags + 1, 1);
+      if (gam) {
+        double g0[NV], g0i[NV], gn[NV], gni[NV];
+        for (int i = 0; i < NV; ++i) g0[i] = gam[i];
+        // inverse of the upper triangular old Gamma
+        for (int i = 0; i < NV; ++i) g0i[i] = 0.0;
+        for (int j = 0; j < D; ++j) {
+          g0i[j + j * D] = 1.0 / g0[j + j * D];
+          for (int i = j - 1; i >= 0; --i) {
+            double s = 0.0;
+            for (int l = i + 1; l <= j; ++l) s += g0[i + l * D] * g0i[l + j * D];
+            g0i[i + j * D] = -s / g0[i + i * D];
+          }
+        }
+        for (int i = 0; i < D; ++i)
+          for (int j = 0; j < D; ++j) {
+            double s = 0.0, t = 0.0;
+            for (int l = 0; l < D; ++l) {
+              s += r2[i + l * D] * g0[l + j * D];
+              t += g0i[i + l * D] * r2i[l + j * D];
+            }
+            gn[i + j * D] = s;
+            gni[i + j * D] = t;
+          }
+        for (int i = 0; i < NV; ++i) gam[i] = gn[i];
+        if (nrm_gam) *nrm_gam = fro(D, gn);
+        gi_s = fro(D, gni);
+        if (nrm_ginv) *nrm_ginv = gi_s;
+      }
     }
-    W(k, ell + 1) = v;
-    if (k < ell) mx = fmax(mx, v);
   }
-  red[t] = mx;
   __syncthreads();
-  for (int off = 128; off > 0; off >>= 1) {
-    if (t < off) red[t] = fmax(red[t], red[t + off]);
-    __syncthreads();
+  if constexpr (WREC) {
+    if (blockIdx.x == 0) wrec_block(wa, gi_s, smem);
   }
-  const bool need = red[0] > u_ro || !(red[0] == red[0]);
-  __syncthreads();
-  if (need) {
-    for (int k = 1 + t; k < ell; k += blockDim.x) W(k, ell) = u_d;
-    for (int k = 1 + t; k <= ell; k += blockDim.x) W(k, ell + 1) = u_d;
-  }
-  if (t == 0) {
-    flags[0] = need ? 1 : 0;
-    if (need) flags[3] += 1;
+  for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < n;
+       r += (int64_t)gridDim.x * blockDim.x) {
+    VT v[D], o[D];
+#pragma unroll
+    for (int j = 0; j < D; ++j) v[j] = xn[r * D + j];
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+      VT s = VT(0);
+#pragma unroll
+      for (int b = 0; b <= a; ++b) s = fma(v[b], VT(ri[b + a * D]), s);
+      o[a] = s;
+    }
+#pragma unroll
+    for (int j = 0; j < D; ++j) xn[r * D + j] = o[j];
+    if (zcol) {
+#pragma unroll
+      for (int j = 0; j < D; ++j) zcol[r + j * ldz] = o[j];
+    }
   }
 }
 
@@ -273,9 +347,10 @@ __global__ void k_w_reset(int col0, int ncols, double u_d, double* w, int ldw) {
 }
 
 // ---------------------------------------------------------------------------
-// Tall-skinny pair of the (partial) reorthogonalisation, CGS (Sec. 4.2):
-//   H = Z^T C       (k x NC, split over row chunks, partials then reduce)
-//   C = C - Z H
+// Tall-skinny pair of the (partial) reorthogonalisation, classical
+// Gram-Schmidt (Sec. 4.2):
+//   H = Z^T C   (k x NC)  k_ts_tn writes per-row-chunk partials, k_reduce_cols sums them
+//   C = C - Z H           k_ts_nn
 // C is NC columns held as NA row-interleaved arrays of DA columns each
 // (NC = NA * DA): for the reorthogonalisation of [Q_ell, Q_ell+1] NA = 2.
 // When ``cond`` is non-null the kernels do nothing unless *cond != 0.
@@ -292,149 +367,182 @@ struct CPair {
   }
 };
 
-constexpr int kTnRows = 256;  // rows per LDS sub-tile
+template <int NC> struct TsShape {
+  static constexpr int JW = NC >= 8 ? 1 : (NC >= 4 ? 2 : 4);  // basis columns per wave
+  static constexpr int JB = 4 * JW;                            // basis columns per block
+};
 
+// grid (row chunks, column groups); wave w of a block owns JW columns, lanes stride rows
 template <typename VT, int DA, int NA>
 __global__ __launch_bounds__(kThreads) void k_ts_tn(const int* cond, int64_t n, int64_t chunk,
                                                     const VT* __restrict__ z, int64_t ldz, int k,
                                                     CPair<VT, DA, NA> cc, double* __restrict__ hpart) {
   constexpr int NC = DA * NA;
-  constexpr int JW = NC >= 32 ? 1 : 32 / NC;  // columns per wave
+  constexpr int JW = TsShape<NC>::JW;
   if (cond && *cond == 0) return;
-  __shared__ VT cs[kTnRows * NC];
   const int lane = threadIdx.x % kWave, wid = threadIdx.x / kWave;
-  const int nw = blockDim.x / kWave;
   const int64_t r0 = (int64_t)blockIdx.x * chunk;
   const int64_t r1 = min(n, r0 + chunk);
-  const int jbase = blockIdx.y * (nw * JW) + wid * JW;
+  const int j0 = blockIdx.y * TsShape<NC>::JB + wid * JW;
+  const int jn = max(0, min(JW, k - j0));
   double acc[JW][NC];
 #pragma unroll
   for (int q = 0; q < JW; ++q)
 #pragma unroll
     for (int c = 0; c < NC; ++c) acc[q][c] = 0.0;
-  for (int64_t t0 = r0; t0 < r1; t0 += kTnRows) {
-    const int rows = (int)min((int64_t)kTnRows, r1 - t0);
-    __syncthreads();
-    for (int i = threadIdx.x; i < rows * NC; i += blockDim.x)
-      cs[i] = cc.get(t0 + i / NC, i % NC);
-    __syncthreads();
+  if (jn > 0) {
+    for (int64_t r = r0 + lane; r < r1; r += kWave) {
+      double cv[NC];
 #pragma unroll
-    for (int q = 0; q < JW; ++q) {
-      const int j = jbase + q;
-      if (j >= k) break;
-      const VT* zc = z + (int64_t)j * ldz + t0;
-      for (int i = lane; i < rows; i += kWave) {
-        const double zv = (double)zc[i];
+      for (int c = 0; c < NC; ++c) cv[c] = (double)cc.get(r, c);
 #pragma unroll
-        for (int c = 0; c < NC; ++c) acc[q][c] = fma(zv, (double)cs[i * NC + c], acc[q][c]);
+      for (int q = 0; q < JW; ++q) {
+        if (q < jn) {
+          const double zv = (double)z[r + (int64_t)(j0 + q) * ldz];
+#pragma unroll
+          for (int c = 0; c < NC; ++c) acc[q][c] = fma(zv, cv[c], acc[q][c]);
+        }
       }
     }
   }
 #pragma unroll
-  for (int q = 0; q < JW; ++q) {
-    const int j = jbase + q;
+  for (int q = 0; q < JW; ++q)
 #pragma unroll
     for (int c = 0; c < NC; ++c) {
       const double v = wave_sum(acc[q][c]);
-      if (lane == 0 && j < k) hpart[((int64_t)blockIdx.x * k + j) * NC + c] = v;
+      if (lane == 0 && q < jn) hpart[((int64_t)blockIdx.x * k + j0 + q) * NC + c] = v;
     }
+}
+
+// out[v] = sum_b part[b * nv + v]  (fixed order); 32 values x 8 part-groups per block
+__global__ __launch_bounds__(256) void k_reduce_cols(const int* cond, int nparts, int nv,
+                                                     const double* __restrict__ part,
+                                                     double* __restrict__ out) {
+  if (cond && *cond == 0) return;
+  __shared__ double sm[256];
+  const int vl = threadIdx.x % 32, g = threadIdx.x / 32;
+  const int v = blockIdx.x * 32 + vl;
+  double s = 0.0;
+  if (v < nv)
+    for (int b = g; b < nparts; b += 8) s += part[(size_t)b * nv + v];
+  sm[threadIdx.x] = s;
+  __syncthreads();
+  if (g == 0 && v < nv) {
+    double r = 0.0;
+    for (int q = 0; q < 8; ++q) r += sm[q * 32 + vl];
+    out[v] = r;
   }
 }
 
-// H[j][c] = sum over chunks of the partials (fixed order)
-__global__ void k_ts_reduce(const int* cond, int nchunks, int kc, const double* __restrict__ hpart,
-                            double* __restrict__ h) {
-  if (cond && *cond == 0) return;
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= kc) return;
-  double s = 0.0;
-  for (int b = 0; b < nchunks; ++b) s += hpart[(int64_t)b * kc + i];
-  h[i] = s;
-}
-
-// C -= Z H ; with GRAM also reduces C^T C and (last block) stores R^{-1} of its
-// Cholesky factor in rinv (NC x NC) for the final re-orthonormalisation.
-constexpr int kNnJ = 256;  // H rows staged in LDS per pass
-
+// C -= Z H.  A block handles 64 rows; its 4 waves split the k columns and the
+// partial sums are combined in LDS.  With GRAM the block also writes the
+// partial Gram matrix of the updated rows (for the final Cholesky QR).
 template <typename VT, int DA, int NA, bool GRAM>
 __global__ __launch_bounds__(kThreads) void k_ts_nn(const int* cond, int64_t n,
                                                     const VT* __restrict__ z, int64_t ldz, int k,
                                                     const double* __restrict__ h,
-                                                    CPair<VT, DA, NA> cc, double* partials,
-                                                    unsigned* counter, double* rinv, int* flags) {
+                                                    CPair<VT, DA, NA> cc,
+                                                    double* __restrict__ part_c) {
   constexpr int NC = DA * NA;
-  constexpr int NV = GRAM ? NC * NC : 1;
   if (cond && *cond == 0) return;
-  __shared__ double hs[kNnJ * NC];
-  __shared__ double smem[kThreads > NV * (kThreads / kWave) ? kThreads : NV * (kThreads / kWave)];
-  double g[NV];
+  __shared__ double red[4][kWave][NC];
+  const int lane = threadIdx.x % kWave, wid = threadIdx.x / kWave;
+  const int64_t r = (int64_t)blockIdx.x * kWave + lane;
+  const int per = (k + 3) / 4;
+  const int jb = wid * per, je = min(k, jb + per);
+  double acc[NC];
 #pragma unroll
-  for (int i = 0; i < NV; ++i) g[i] = 0.0;
-  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  const int64_t rbeg = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  // every thread of the block walks the same number of row iterations so the
-  // __syncthreads around the LDS staging stay uniform
-  const int64_t iters = (n + stride - 1) / stride;
-  for (int64_t it = 0; it < iters; ++it) {
-    const int64_t r = rbeg + it * stride;
-    const bool valid = r < n;
-    double acc[NC];
+  for (int c = 0; c < NC; ++c) acc[c] = 0.0;
+  if (r < n) {
+    const VT* zr = z + r;
+    for (int j = jb; j < je; ++j) {
+      const double zv = (double)zr[(int64_t)j * ldz];
 #pragma unroll
-    for (int c = 0; c < NC; ++c) acc[c] = 0.0;
-    for (int j0 = 0; j0 < k; j0 += kNnJ) {
-      const int jn = min(kNnJ, k - j0);
-      __syncthreads();
-      for (int i = threadIdx.x; i < jn * NC; i += blockDim.x) hs[i] = h[(int64_t)j0 * NC + i];
-      __syncthreads();
-      if (valid) {
-        const VT* zr = z + r + (int64_t)j0 * ldz;
-        for (int j = 0; j < jn; ++j) {
-          const double zv = (double)zr[(int64_t)j * ldz];
-#pragma unroll
-          for (int c = 0; c < NC; ++c) acc[c] = fma(zv, hs[j * NC + c], acc[c]);
-        }
-      }
+      for (int c = 0; c < NC; ++c) acc[c] = fma(zv, h[(int64_t)j * NC + c], acc[c]);
     }
-    if (valid) {
-      VT o[NC];
+  }
+#pragma unroll
+  for (int c = 0; c < NC; ++c) red[wid][lane][c] = acc[c];
+  __syncthreads();
+  if (wid == 0) {
+    constexpr int NG = GRAM ? NC * NC : 1;
+    double g[NG];
+#pragma unroll
+    for (int i = 0; i < NG; ++i) g[i] = 0.0;
+    if (r < n) {
+      double o[NC];
 #pragma unroll
       for (int c = 0; c < NC; ++c) {
-        o[c] = VT((double)cc.get(r, c) - acc[c]);
-        cc.set(r, c, o[c]);
+        const double s = red[0][lane][c] + red[1][lane][c] + red[2][lane][c] + red[3][lane][c];
+        o[c] = (double)VT((double)cc.get(r, c) - s);
+        cc.set(r, c, VT(o[c]));
       }
       if constexpr (GRAM) {
 #pragma unroll
         for (int a = 0; a < NC; ++a)
 #pragma unroll
-          for (int b = 0; b < NC; ++b) g[a + b * NC] += (double)o[a] * (double)o[b];
+          for (int b = 0; b < NC; ++b) g[a + b * NC] += o[a] * o[b];
       }
     }
-  }
-  if constexpr (GRAM) {
-    block_sum<NV>(g, smem);
-    __shared__ double res[NV];
-    if (grid_sum_last<NV>(g, partials, counter, res, smem)) {
-      if (threadIdx.x == 0) {
-        double r[NV], ri[NV];
-        if (!chol_upper_inv(NC, res, r, ri)) atomicOr(flags + 1, 1);
-        // rinv holds R^{-1} followed by R
-        for (int i = 0; i < NV; ++i) { rinv[i] = ri[i]; rinv[NV + i] = r[i]; }
+    if constexpr (GRAM) {
+#pragma unroll
+      for (int i = 0; i < NG; ++i) {
+        const double v = wave_sum(g[i]);
+        if (lane == 0) part_c[(size_t)blockIdx.x * NG + i] = v;
       }
     }
   }
 }
 
+// One block: Gram of C from the partials, Cholesky; writes R^{-1} then R (NC x NC each).
+template <int NC>
+__global__ __launch_bounds__(256) void k_ts_gramfin(const int* cond, int nparts,
+                                                    const double* __restrict__ part_c,
+                                                    double* rinv, int* flags) {
+  constexpr int NV = NC * NC;
+  if (cond && *cond == 0) return;
+  __shared__ double smem[256];
+  __shared__ double res[NV];
+  reduce_partials<NV>(part_c, nparts, res, smem);
+  if (threadIdx.x == 0) {
+    double r[NV], ri[NV];
+    if (!chol_upper_inv(NC, res, r, ri)) atomicOr(flags + 1, 1);
+    for (int i = 0; i < NV; ++i) { rinv[i] = ri[i]; rinv[NV + i] = r[i]; }
+  }
+}
+
 // C = C R^{-1} (NC columns), written back to the arrays and, if z0 is given,
-// to NC consecutive basis columns starting at z0.
-template <typename VT, int DA, int NA>
+// to NC consecutive basis columns starting at z0.  With FUSED the block first
+// reduces the Gram partials of k_ts_nn itself and factors them (NC <= 4);
+// block 0 then stores R^{-1} and R in rinv.  Otherwise rinv comes from
+// k_ts_gramfin.
+template <typename VT, int DA, int NA, bool FUSED>
 __global__ __launch_bounds__(kThreads) void k_ts_scale(const int* cond, int64_t n,
                                                        CPair<VT, DA, NA> cc,
-                                                       const double* __restrict__ rinv,
-                                                       VT* __restrict__ z0, int64_t ldz) {
+                                                       const double* __restrict__ part_c,
+                                                       int nparts, double* rinv,
+                                                       VT* __restrict__ z0, int64_t ldz,
+                                                       int* flags) {
   constexpr int NC = DA * NA;
+  constexpr int NV = NC * NC;
   if (cond && *cond == 0) return;
-  __shared__ double ri[NC * NC];
-  if (threadIdx.x < NC * NC) ri[threadIdx.x] = rinv[threadIdx.x];
+  __shared__ double ri[NV];
+  if constexpr (FUSED) {
+    __shared__ double smem[kThreads];
+    __shared__ double res[NV];
+    reduce_partials<NV>(part_c, nparts, res, smem);
+    if (threadIdx.x == 0) {
+      double r[NV], rv[NV];
+      const bool ok = chol_upper_inv(NC, res, r, rv);
+      for (int i = 0; i < NV; ++i) ri[i] = rv[i];
+      if (blockIdx.x == 0) {
+        if (!ok) atomicOr(flags + 1, 1);
+        for (int i = 0; i < NV; ++i) { rinv[i] = rv[i]; rinv[NV + i] = r[i]; }
+      }
+    }
+  } else {
+    if (threadIdx.x < NV) ri[threadIdx.x] = rinv[threadIdx.x];
+  }
   __syncthreads();
   for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < n;
        r += (int64_t)gridDim.x * blockDim.x) {
@@ -479,6 +587,42 @@ __global__ void k_assemble_t(int K, int d, int kk, const double* __restrict__ th
     else if (blk_j == blk_i + 1) v = gam[(int64_t)blk_i * d * d + jj + ii * d];
   }
   t[idx] = v;
+}
+
+// Restart coupling block (reading R11): F = R Gamma_L V_Z(K-d:K, 0:kn), d x kn
+// column-major, with R the triangular factor that re-orthonormalised Q_{L+1}
+// (stored after R^{-1} in rinvc) and V_Z the eigenvectors of T (K x K).
+__global__ void k_restart_f(int K, int d, int kn, const double* __restrict__ vz,
+                            const double* __restrict__ gam_l, const double* __restrict__ rinvc,
+                            double* __restrict__ f) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= kn) return;
+  const double* r = rinvc + d * d;
+  for (int i = 0; i < d; ++i) {
+    double s = 0.0;
+    for (int l = 0; l < d; ++l) {
+      double rg = 0.0;  // (R Gamma_L)[i, l]
+      for (int q = 0; q < d; ++q) rg += r[i + q * d] * gam_l[q + l * d];
+      s += rg * vz[(K - d + l) + (int64_t)j * K];
+    }
+    f[i + (int64_t)j * d] = s;
+  }
+}
+
+// Block norms for the W-recurrence of the kept part: ||Theta_k|| (max |theta|)
+// and ||F_k||_F for the blocks k = 1..nb of d kept Ritz vectors each.
+__global__ void k_kept_norms(int nb, int d, const double* __restrict__ theta,
+                             const double* __restrict__ f, double* __restrict__ n_theta,
+                             double* __restrict__ n_f) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x + 1;
+  if (k > nb) return;
+  double mx = 0.0, s2 = 0.0;
+  for (int j = (k - 1) * d; j < k * d; ++j) {
+    mx = fmax(mx, fabs(theta[j]));
+    for (int i = 0; i < d; ++i) s2 += f[i + (int64_t)j * d] * f[i + (int64_t)j * d];
+  }
+  n_theta[k] = mx;
+  n_f[k] = sqrt(s2);
 }
 
 // column-major (ld) -> row-interleaved, with type conversion
@@ -584,145 +728,191 @@ __global__ void k_sub(int64_t cnt, double* __restrict__ x, const double* __restr
 // host launchers
 // ===========================================================================
 template <typename VT>
-void sub_gram(nsp_ctx* c, int d, int64_t n, VT* p, const VT* x, const double* xi, double* gam_out,
-              double* rinv, double* nrm_gam, double* nrm_ginv) {
+int sub_gram(nsp_ctx* c, int d, int64_t n, VT* p, const VT* x, const double* part_xi, int nparts_xi,
+             double* xi_out, double* nrm_xi, double* part_g) {
   const unsigned grid = cap_grid(n, kThreads, kRedBlocks);
-  int* flags = c->flags.as<int>();
 #define NSP_SG(D)                                                                              \
   case D:                                                                                      \
-    if (xi)                                                                                    \
-      k_sub_gram<VT, D, true><<<grid, kThreads, 0, c->stream>>>(n, p, x, xi, c->red.partials,  \
-          c->red.counter, gam_out, rinv, nrm_gam, nrm_ginv, flags);                            \
+    if (part_xi && x)                                                                          \
+      k_sub_gram<VT, D, true, true><<<grid, kThreads, 0, c->stream>>>(                         \
+          n, p, x, part_xi, nparts_xi, xi_out, nrm_xi, part_g);                                \
+    else if (part_xi)                                                                          \
+      k_sub_gram<VT, D, true, false><<<grid, kThreads, 0, c->stream>>>(                        \
+          n, p, x, part_xi, nparts_xi, xi_out, nrm_xi, part_g);                                \
     else                                                                                       \
-      k_sub_gram<VT, D, false><<<grid, kThreads, 0, c->stream>>>(n, p, x, xi, c->red.partials, \
-          c->red.counter, gam_out, rinv, nrm_gam, nrm_ginv, flags);                            \
+      k_sub_gram<VT, D, false, false><<<grid, kThreads, 0, c->stream>>>(                       \
+          n, p, x, part_xi, nparts_xi, xi_out, nrm_xi, part_g);                                \
     break;
   switch (d) { NSP_SG(1) NSP_SG(2) NSP_SG(4) NSP_SG(8) default: throw Error(NSP_ERR_ARG, "d"); }
 #undef NSP_SG
   NSP_HIP(hipGetLastError());
+  return (int)grid;
 }
-template void sub_gram<double>(nsp_ctx*, int, int64_t, double*, const double*, const double*,
-                               double*, double*, double*, double*);
-template void sub_gram<float>(nsp_ctx*, int, int64_t, float*, const float*, const double*, double*,
+template int sub_gram<double>(nsp_ctx*, int, int64_t, double*, const double*, const double*, int,
                               double*, double*, double*);
+template int sub_gram<float>(nsp_ctx*, int, int64_t, float*, const float*, const double*, int,
+                             double*, double*, double*);
 
 template <typename VT>
-void scale_block(nsp_ctx* c, int d, int64_t n, const VT* p, const double* rinv, VT* xn, VT* zcol,
-                 int64_t ldz, bool gram, double* gam, double* rinv2, double* nrm_gam,
-                 double* nrm_ginv) {
+int scale_block(nsp_ctx* c, int d, int64_t n, const VT* p, const double* part_g, int nparts,
+                VT* xn, VT* zcol, int64_t ldz, double* gam_out, double* nrm_gam, double* nrm_ginv,
+                double* part_g2, const WArgs* wa) {
   const unsigned grid = cap_grid(n, kThreads, kRedBlocks);
   int* flags = c->flags.as<int>();
+  WArgs w{};
+  if (wa) w = *wa;
 #define NSP_SC(D)                                                                              \
   case D:                                                                                      \
-    if (gram)                                                                                  \
-      k_scale<VT, D, true><<<grid, kThreads, 0, c->stream>>>(n, p, rinv, xn, zcol, ldz,        \
-          c->red.partials, c->red.counter, gam, rinv2, nrm_gam, nrm_ginv, flags);              \
+    if (part_g2)                                                                               \
+      k_scale<VT, D, true, false><<<grid, kThreads, 0, c->stream>>>(n, p, part_g, nparts, xn,  \
+          zcol, ldz, gam_out, nrm_gam, nrm_ginv, part_g2, flags, w);                           \
+    else if (wa)                                                                               \
+      k_scale<VT, D, false, true><<<grid, kThreads, 0, c->stream>>>(n, p, part_g, nparts, xn,  \
+          zcol, ldz, gam_out, nrm_gam, nrm_ginv, part_g2, flags, w);                           \
     else                                                                                       \
-      k_scale<VT, D, false><<<grid, kThreads, 0, c->stream>>>(n, p, rinv, xn, zcol, ldz,       \
-          c->red.partials, c->red.counter, gam, rinv2, nrm_gam, nrm_ginv, flags);              \
+      k_scale<VT, D, false, false><<<grid, kThreads, 0, c->stream>>>(n, p, part_g, nparts, xn, \
+          zcol, ldz, gam_out, nrm_gam, nrm_ginv, part_g2, flags, w);                           \
     break;
   switch (d) { NSP_SC(1) NSP_SC(2) NSP_SC(4) NSP_SC(8) default: throw Error(NSP_ERR_ARG, "d"); }
 #undef NSP_SC
   NSP_HIP(hipGetLastError());
+  return (int)grid;
 }
-template void scale_block<double>(nsp_ctx*, int, int64_t, const double*, const double*, double*,
-                                  double*, int64_t, bool, double*, double*, double*, double*);
-template void scale_block<float>(nsp_ctx*, int, int64_t, const float*, const double*, float*,
-                                 float*, int64_t, bool, double*, double*, double*, double*);
+template int scale_block<double>(nsp_ctx*, int, int64_t, const double*, const double*, int, double*,
+                                 double*, int64_t, double*, double*, double*, double*, const WArgs*);
+template int scale_block<float>(nsp_ctx*, int, int64_t, const float*, const double*, int, float*,
+                                float*, int64_t, double*, double*, double*, double*, const WArgs*);
 
-void wrec(nsp_ctx* c, int ell, int l0, double u_d, double u_ro, const double* n_xi,
-          const double* n_gam, const double* n_ginv, const double* n_theta, const double* n_f,
-          double* w, int ldw) {
-  k_wrec<<<1, 256, 0, c->stream>>>(ell, l0, u_d, u_ro, n_xi, n_gam, n_ginv, n_theta, n_f, w, ldw,
-                                   c->flags.as<int>());
+template <typename VT>
+void scale_block2(nsp_ctx* c, int d, int64_t n, const double* part_g2, int nparts, VT* xn, VT* zcol,
+                  int64_t ldz, double* gam, double* nrm_gam, double* nrm_ginv, const WArgs* wa) {
+  const unsigned grid = cap_grid(n, kThreads, kRedBlocks);
+  int* flags = c->flags.as<int>();
+  WArgs w{};
+  if (wa) w = *wa;
+#define NSP_SC2(D)                                                                             \
+  case D:                                                                                      \
+    if (wa)                                                                                    \
+      k_scale2<VT, D, true><<<grid, kThreads, 0, c->stream>>>(n, part_g2, nparts, xn, zcol,    \
+          ldz, gam, nrm_gam, nrm_ginv, flags, w);                                              \
+    else                                                                                       \
+      k_scale2<VT, D, false><<<grid, kThreads, 0, c->stream>>>(n, part_g2, nparts, xn, zcol,   \
+          ldz, gam, nrm_gam, nrm_ginv, flags, w);                                              \
+    break;
+  switch (d) { NSP_SC2(1) NSP_SC2(2) NSP_SC2(4) NSP_SC2(8) default: throw Error(NSP_ERR_ARG, "d"); }
+#undef NSP_SC2
   NSP_HIP(hipGetLastError());
 }
+template void scale_block2<double>(nsp_ctx*, int, int64_t, const double*, int, double*, double*,
+                                   int64_t, double*, double*, double*, const WArgs*);
+template void scale_block2<float>(nsp_ctx*, int, int64_t, const double*, int, float*, float*,
+                                  int64_t, double*, double*, double*, const WArgs*);
 
 void w_reset(nsp_ctx* c, int col0, int ncols, double u_d, double* w, int ldw) {
   k_w_reset<<<1, 256, 0, c->stream>>>(col0, ncols, u_d, w, ldw);
   NSP_HIP(hipGetLastError());
 }
 
-// Workspace need of the TN partials: nchunks * k * NC doubles.
+// Rows per chunk of the TN kernel: aim for ~1024 blocks in total with chunks of
+// at least 1024 rows (so each lane accumulates >= 16 rows before the wave sum).
 int64_t ts_chunk_rows(int64_t n, int k, int nc) {
-  const int jw = nc >= 32 ? 1 : 32 / nc;
-  const int64_t col_groups = (k + 4 * jw - 1) / (4 * jw);
-  // aim for ~2048 blocks in total, chunks of at least 256 rows
-  int64_t chunks = std::max<int64_t>(1, 2048 / std::max<int64_t>(1, col_groups));
+  const int jb = nc >= 8 ? 4 : (nc >= 4 ? 8 : 16);
+  const int64_t col_groups = std::max<int64_t>(1, (k + jb - 1) / jb);
+  const int64_t chunks = std::max<int64_t>(1, 1024 / col_groups);
   int64_t rows = (n + chunks - 1) / chunks;
-  rows = std::max<int64_t>(rows, kTnRows);
-  rows = (rows + kTnRows - 1) / kTnRows * kTnRows;
-  return rows;
+  rows = std::max<int64_t>(rows, 1024);
+  return (rows + 63) / 64 * 64;
 }
 
 template <typename VT, int DA, int NA>
 static void ts_proj_t(nsp_ctx* c, const int* cond, int64_t n, const VT* z, int64_t ldz, int k,
-                      VT* a0, VT* a1, double* h, double* hpart, bool gram, double* rinv) {
+                      VT* a0, VT* a1, double* h, double* hpart, bool gram, double* part_c,
+                      double* rinv) {
   constexpr int NC = DA * NA;
-  constexpr int JW = NC >= 32 ? 1 : 32 / NC;
   CPair<VT, DA, NA> cc{a0, a1};
-  const int64_t chunk = ts_chunk_rows(n, k, NC);
-  const unsigned nchunks = (unsigned)((n + chunk - 1) / chunk);
-  const unsigned gy = (unsigned)((k + 4 * JW - 1) / (4 * JW));
+  const unsigned nnblocks = (unsigned)((n + kWave - 1) / kWave);
   if (k > 0) {
-    dim3 grid(nchunks, gy);
-    k_ts_tn<VT, DA, NA><<<grid, kThreads, 0, c->stream>>>(cond, n, chunk, z, ldz, k, cc, hpart);
-    k_ts_reduce<<<nblk((int64_t)k * NC, 256), 256, 0, c->stream>>>(cond, (int)nchunks, k * NC, hpart, h);
+    const int64_t chunk = ts_chunk_rows(n, k, NC);
+    const unsigned nchunks = (unsigned)((n + chunk - 1) / chunk);
+    const unsigned gy = (unsigned)((k + TsShape<NC>::JB - 1) / TsShape<NC>::JB);
+    k_ts_tn<VT, DA, NA><<<dim3(nchunks, gy), kThreads, 0, c->stream>>>(cond, n, chunk, z, ldz, k, cc,
+                                                                        hpart);
+    k_reduce_cols<<<nblk((int64_t)k * NC, 32), 256, 0, c->stream>>>(cond, (int)nchunks, k * NC,
+                                                                    hpart, h);
   }
-  const unsigned g2 = cap_grid(n, kThreads, 2048);
-  if (gram)
-    k_ts_nn<VT, DA, NA, true><<<std::min<unsigned>(g2, kRedBlocks), kThreads, 0, c->stream>>>(
-        cond, n, z, ldz, k, h, cc, c->red.partials, c->red.counter, rinv, c->flags.as<int>());
-  else
-    k_ts_nn<VT, DA, NA, false><<<g2, kThreads, 0, c->stream>>>(cond, n, z, ldz, k, h, cc, nullptr,
-                                                               nullptr, nullptr, c->flags.as<int>());
+  if (gram) {
+    k_ts_nn<VT, DA, NA, true><<<nnblocks, kThreads, 0, c->stream>>>(cond, n, z, ldz, k, h, cc, part_c);
+    if (NC > 4)
+      k_ts_gramfin<NC><<<1, 256, 0, c->stream>>>(cond, (int)nnblocks, part_c, rinv, c->flags.as<int>());
+  } else if (k > 0) {
+    k_ts_nn<VT, DA, NA, false><<<nnblocks, kThreads, 0, c->stream>>>(cond, n, z, ldz, k, h, cc,
+                                                                     nullptr);
+  }
   NSP_HIP(hipGetLastError());
 }
+
+int64_t ts_part_c_len(int64_t n, int nc) { return ((n + kWave - 1) / kWave) * nc * nc; }
 
 template <typename VT, int DA, int NA>
-static void ts_scale_t(nsp_ctx* c, const int* cond, int64_t n, VT* a0, VT* a1, const double* rinv,
-                       VT* z0, int64_t ldz) {
+static void ts_scale_t(nsp_ctx* c, const int* cond, int64_t n, VT* a0, VT* a1, const double* part_c,
+                       double* rinv, VT* z0, int64_t ldz) {
+  constexpr int NC = DA * NA;
   CPair<VT, DA, NA> cc{a0, a1};
-  k_ts_scale<VT, DA, NA><<<cap_grid(n, kThreads, 2048), kThreads, 0, c->stream>>>(cond, n, cc, rinv,
-                                                                                  z0, ldz);
+  const int nparts = (int)((n + kWave - 1) / kWave);
+  const unsigned grid = cap_grid(n, kThreads, 2048);
+  if constexpr (NC <= 4)
+    k_ts_scale<VT, DA, NA, true><<<grid, kThreads, 0, c->stream>>>(cond, n, cc, part_c, nparts, rinv,
+                                                                   z0, ldz, c->flags.as<int>());
+  else
+    k_ts_scale<VT, DA, NA, false><<<grid, kThreads, 0, c->stream>>>(cond, n, cc, part_c, nparts, rinv,
+                                                                    z0, ldz, c->flags.as<int>());
   NSP_HIP(hipGetLastError());
 }
 
-// One CGS pass of C = [a0 (| a1)] against the first k basis columns.
+// One CGS pass of C = [a0 (| a1)] against the first k basis columns; with gram
+// also the Cholesky factor of the updated C's Gram matrix (R^{-1}, then R, in rinv).
 template <typename VT>
 void ts_project(nsp_ctx* c, const int* cond, int d, int na, int64_t n, const VT* z, int64_t ldz,
-                int k, VT* a0, VT* a1, double* h, double* hpart, bool gram, double* rinv) {
-  if (k <= 0) {
-    if (!gram) return;
-  }
+                int k, VT* a0, VT* a1, double* h, double* hpart, bool gram, double* part_c,
+                double* rinv) {
+  k = std::max(k, 0);
 #define NSP_TP(D)                                                                              \
   case D:                                                                                      \
-    if (na == 1) ts_proj_t<VT, D, 1>(c, cond, n, z, ldz, std::max(k, 0), a0, a1, h, hpart, gram, rinv); \
-    else ts_proj_t<VT, D, 2>(c, cond, n, z, ldz, std::max(k, 0), a0, a1, h, hpart, gram, rinv);          \
+    if (na == 1) ts_proj_t<VT, D, 1>(c, cond, n, z, ldz, k, a0, a1, h, hpart, gram, part_c, rinv); \
+    else ts_proj_t<VT, D, 2>(c, cond, n, z, ldz, k, a0, a1, h, hpart, gram, part_c, rinv);          \
     break;
   switch (d) { NSP_TP(1) NSP_TP(2) NSP_TP(4) NSP_TP(8) default: throw Error(NSP_ERR_ARG, "d"); }
 #undef NSP_TP
 }
 template void ts_project<double>(nsp_ctx*, const int*, int, int, int64_t, const double*, int64_t,
-                                 int, double*, double*, double*, double*, bool, double*);
+                                 int, double*, double*, double*, double*, bool, double*, double*);
 template void ts_project<float>(nsp_ctx*, const int*, int, int, int64_t, const float*, int64_t, int,
-                                float*, float*, double*, double*, bool, double*);
+                                float*, float*, double*, double*, bool, double*, double*);
 
 template <typename VT>
 void ts_scale(nsp_ctx* c, const int* cond, int d, int na, int64_t n, VT* a0, VT* a1,
-              const double* rinv, VT* z0, int64_t ldz) {
+              const double* part_c, double* rinv, VT* z0, int64_t ldz) {
 #define NSP_TS(D)                                                                              \
   case D:                                                                                      \
-    if (na == 1) ts_scale_t<VT, D, 1>(c, cond, n, a0, a1, rinv, z0, ldz);                      \
-    else ts_scale_t<VT, D, 2>(c, cond, n, a0, a1, rinv, z0, ldz);                              \
+    if (na == 1) ts_scale_t<VT, D, 1>(c, cond, n, a0, a1, part_c, rinv, z0, ldz);              \
+    else ts_scale_t<VT, D, 2>(c, cond, n, a0, a1, part_c, rinv, z0, ldz);                      \
     break;
   switch (d) { NSP_TS(1) NSP_TS(2) NSP_TS(4) NSP_TS(8) default: throw Error(NSP_ERR_ARG, "d"); }
 #undef NSP_TS
 }
 template void ts_scale<double>(nsp_ctx*, const int*, int, int, int64_t, double*, double*,
-                               const double*, double*, int64_t);
+                               const double*, double*, double*, int64_t);
 template void ts_scale<float>(nsp_ctx*, const int*, int, int, int64_t, float*, float*,
-                              const double*, float*, int64_t);
+                              const double*, double*, float*, int64_t);
+
+void restart_coupling(nsp_ctx* c, int K, int d, int kn, const double* vz, const double* gam_l,
+                      const double* rinvc, const double* evals, double* f, double* theta_kept,
+                      double* n_theta, double* n_f) {
+  k_restart_f<<<nblk(kn, 256), 256, 0, c->stream>>>(K, d, kn, vz, gam_l, rinvc, f);
+  NSP_HIP(hipMemcpyAsync(theta_kept, evals, sizeof(double) * kn, hipMemcpyDeviceToDevice, c->stream));
+  k_kept_norms<<<nblk(kn / d, 256), 256, 0, c->stream>>>(kn / d, d, evals, f, n_theta, n_f);
+  NSP_HIP(hipGetLastError());
+}
 
 void assemble_t(nsp_ctx* c, int K, int d, int kk, const double* theta, const double* f,
                 const double* xi, const double* gam, double* t) {

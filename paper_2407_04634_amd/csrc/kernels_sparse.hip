@@ -52,7 +52,8 @@ __global__ __launch_bounds__(kThreads) void k_spmm(int64_t nrows, const int32_t*
 // ---------------------------------------------------------------------------
 // One Lanczos step's second product, fused (Alg. 2 inner loop):
 //   P = A^T Y + eps D X  [- Xp Gamma_prev^T]            (three-term recurrence)
-//   Xi = X^T P  (D x D, reduced over the grid, symmetrised)  when XI is set
+//   per-block partials of Xi = X^T P (D x D) when XI is set; the QR kernel
+//   that follows reduces them in block order (deterministic)
 // Y (m x D), X, Xp, P (n x D) row-interleaved.  Gamma_prev is D x D column-major.
 // ---------------------------------------------------------------------------
 template <typename VT, int D, int LPR, bool PREV, bool XI>
@@ -60,8 +61,7 @@ __global__ __launch_bounds__(kThreads) void k_spmmT_step(
     int64_t nrows, const int32_t* __restrict__ rp, const int32_t* __restrict__ ci,
     const VT* __restrict__ av, const VT* __restrict__ y, const VT* __restrict__ x,
     const double* __restrict__ dv, double eps, const VT* __restrict__ xp,
-    const double* __restrict__ gprev, VT* __restrict__ out, double* partials, unsigned* counter,
-    double* xi_out, double* xi_nrm) {
+    const double* __restrict__ gprev, VT* __restrict__ out, double* __restrict__ part_xi) {
   __shared__ double smem[kThreads > D * D * (kThreads / kWave) ? kThreads : D * D * (kThreads / kWave)];
   __shared__ double gp[D * D];
   if (PREV) {
@@ -119,19 +119,11 @@ __global__ __launch_bounds__(kThreads) void k_spmmT_step(
     }
   }
   if constexpr (XI) {
+    // per-block partial of X^T P; the next kernel reduces the partials
     block_sum<NV>(dots, smem);
-    __shared__ double res[NV];
-    if (grid_sum_last<NV>(dots, partials, counter, res, smem)) {
-      if (threadIdx.x == 0) {
-        double f2 = 0.0;
-        for (int i = 0; i < NV; ++i) {
-          const int a = i % D, b = i / D;
-          const double v = 0.5 * (res[a * D + b] + res[b * D + a]);
-          xi_out[i] = v;
-          f2 += v * v;
-        }
-        if (xi_nrm) *xi_nrm = sqrt(f2);
-      }
+    if (threadIdx.x == 0) {
+#pragma unroll
+      for (int i = 0; i < NV; ++i) part_xi[(size_t)blockIdx.x * NV + i] = dots[i];
     }
   }
 }
@@ -313,8 +305,8 @@ template void spmm_block<double>(nsp_ctx*, const Csr&, int, const double*, doubl
 template void spmm_block<float>(nsp_ctx*, const Csr&, int, const float*, float*);
 
 template <typename VT, int D, bool PREV, bool XI>
-static void spmmT_step_d(nsp_ctx* c, const VT* y, const VT* x, const VT* xp, const double* gprev,
-                         VT* out, double* xi_out, double* xi_nrm) {
+static int spmmT_step_d(nsp_ctx* c, const VT* y, const VT* x, const VT* xp, const double* gprev,
+                        VT* out, double* part_xi) {
   const Csr& a = c->AT;
   const VT* av = nullptr;
   if constexpr (sizeof(VT) == 8) av = a.val; else av = a.val32;
@@ -325,7 +317,7 @@ static void spmmT_step_d(nsp_ctx* c, const VT* y, const VT* x, const VT* xp, con
   case L:                                                                                      \
     k_spmmT_step<VT, D, L, PREV, XI><<<grid, kThreads, 0, c->stream>>>(                        \
         a.rows, a.rowptr, a.colind, av, y, x, c->Dv.as<double>(), c->prm.eps, xp, gprev, out,  \
-        c->red.partials, c->red.counter, xi_out, xi_nrm);                                      \
+        part_xi);                                                                              \
     break;
   switch (a.lpr) {
     NSP_T_CASE(1) NSP_T_CASE(2) NSP_T_CASE(4) NSP_T_CASE(8) NSP_T_CASE(16) NSP_T_CASE(32)
@@ -333,17 +325,18 @@ static void spmmT_step_d(nsp_ctx* c, const VT* y, const VT* x, const VT* xp, con
   }
 #undef NSP_T_CASE
   NSP_HIP(hipGetLastError());
+  return (int)grid;
 }
 
 template <typename VT>
-void spmmT_step(nsp_ctx* c, int d, const VT* y, const VT* x, const VT* xp, const double* gprev,
-                VT* out, double* xi_out, double* xi_nrm) {
-  const bool prev = xp != nullptr, dots = xi_out != nullptr;
+int spmmT_step(nsp_ctx* c, int d, const VT* y, const VT* x, const VT* xp, const double* gprev,
+               VT* out, double* part_xi) {
+  const bool prev = xp != nullptr, dots = part_xi != nullptr;
 #define NSP_DISPATCH(D)                                                                        \
-  if (prev && dots) spmmT_step_d<VT, D, true, true>(c, y, x, xp, gprev, out, xi_out, xi_nrm);          \
-  else if (prev) spmmT_step_d<VT, D, true, false>(c, y, x, xp, gprev, out, xi_out, xi_nrm);            \
-  else if (dots) spmmT_step_d<VT, D, false, true>(c, y, x, xp, gprev, out, xi_out, xi_nrm);            \
-  else spmmT_step_d<VT, D, false, false>(c, y, x, xp, gprev, out, xi_out, xi_nrm);
+  if (prev && dots) return spmmT_step_d<VT, D, true, true>(c, y, x, xp, gprev, out, part_xi);   \
+  else if (prev) return spmmT_step_d<VT, D, true, false>(c, y, x, xp, gprev, out, part_xi);     \
+  else if (dots) return spmmT_step_d<VT, D, false, true>(c, y, x, xp, gprev, out, part_xi);     \
+  else return spmmT_step_d<VT, D, false, false>(c, y, x, xp, gprev, out, part_xi);
   switch (d) {
     case 1: { NSP_DISPATCH(1) break; }
     case 2: { NSP_DISPATCH(2) break; }
@@ -353,10 +346,10 @@ void spmmT_step(nsp_ctx* c, int d, const VT* y, const VT* x, const VT* xp, const
   }
 #undef NSP_DISPATCH
 }
-template void spmmT_step<double>(nsp_ctx*, int, const double*, const double*, const double*,
-                                 const double*, double*, double*, double*);
-template void spmmT_step<float>(nsp_ctx*, int, const float*, const float*, const float*,
-                                const double*, float*, double*, double*);
+template int spmmT_step<double>(nsp_ctx*, int, const double*, const double*, const double*,
+                                const double*, double*, double*);
+template int spmmT_step<float>(nsp_ctx*, int, const float*, const float*, const float*,
+                               const double*, float*, double*);
 
 void spmm_wide(nsp_ctx* c, const Csr& a, int k, const double* x, double* y) {
   if (a.rows == 0 || k == 0) return;

@@ -6,7 +6,8 @@
 //      [d, K - 2d];
 //  R2  the recurrence subtracts Q_{ell-1} Gamma_{ell-1}^T;
 //  R3/R4 the W-recurrence cases (see k_wrec);
-//  R5  reorthogonalisation = classical Gram-Schmidt twice;
+//  R5  partial reorthogonalisation = one classical Gram-Schmidt pass (the vectors
+//      are semi-orthogonal); the cycle's first step and the restart use two;
 //  R6  QR = Cholesky QR (twice for d > 1), positive diagonal;
 //  R7  ||B|| = ||A||_1 ||A||_inf + eps max(D) in the first cycle, then the
 //      largest Ritz value;
@@ -84,9 +85,9 @@ void syevd(nsp_ctx* c, int k, double* a, double* w, DBuf& ework, DBuf& info) {
   double* e = alloc_as<double>(ework, k);
   rocblas_int* inf = alloc_as<rocblas_int>(info, 1);
   NSP_BLAS(rocsolver_dsyevd(c->blas, rocblas_evect_original, rocblas_fill_lower, k, a, k, w, e, inf));
-  rocblas_int h = 0;
-  NSP_HIP(hipMemcpyAsync(&h, inf, sizeof(h), hipMemcpyDeviceToHost, c->stream));
+  NSP_HIP(hipMemcpyAsync(c->pin_i + 8, inf, sizeof(rocblas_int), hipMemcpyDeviceToHost, c->stream));
   NSP_HIP(hipStreamSynchronize(c->stream));
+  const int h = c->pin_i[8];
   if (h != 0) throw Error(NSP_ERR_HIP, "rocsolver_dsyevd did not converge (info " + std::to_string(h) + ")");
 }
 
@@ -97,12 +98,43 @@ struct Lanczos {
   int64_t n, m, ldz;
   int d, K, L;
   VT *Z, *Z2, *ring[3], *Y, *P;
-  double *xi, *gam, *rinv, *rinv2, *rinvc, *nrm_xi, *nrm_gam, *nrm_ginv, *nrm_theta, *nrm_f;
+  double *xi, *gam, *rinvc, *nrm_xi, *nrm_gam, *nrm_ginv, *nrm_theta, *nrm_f;
+  double *part_xi, *part_g, *part_g2, *part_c;
   double *W, *theta_kept, *fmat, *T, *evals, *H, *hpart;
   int ldw;
   int* flags;
-  DBuf b_xi, b_gam, b_rinv, b_rinv2, b_rinvc, b_nxi, b_ngam, b_nginv, b_ntheta, b_nf, b_W, b_hpart,
+  DBuf b_xi, b_gam, b_rinvc, b_nxi, b_ngam, b_nginv, b_ntheta, b_nf, b_W, b_hpart,
       b_H, b_info, b_vzf, b_tmpv;
+
+  // HIP-event timing of the SpMV pair at sampled steps (profile mode)
+  struct Prof {
+    static constexpr int kSlots = 64;
+    bool on = false;
+    int used = 0;
+    int64_t samples = 0;
+    double sum_a = 0.0, sum_at = 0.0;  // milliseconds
+    hipEvent_t ev[3 * kSlots];
+    void init(bool enable) {
+      on = enable;
+      if (on)
+        for (auto& e : ev) NSP_HIP(hipEventCreate(&e));
+    }
+    void collect() {
+      for (int i = 0; i < used; ++i) {
+        float a = 0.f, b = 0.f;
+        NSP_HIP(hipEventElapsedTime(&a, ev[3 * i], ev[3 * i + 1]));
+        NSP_HIP(hipEventElapsedTime(&b, ev[3 * i + 1], ev[3 * i + 2]));
+        sum_a += a;
+        sum_at += b;
+        ++samples;
+      }
+      used = 0;
+    }
+    ~Prof() {
+      if (on)
+        for (auto& e : ev) (void)hipEventDestroy(e);
+    }
+  } prof;
 
   explicit Lanczos(nsp_ctx* ctx) : c(ctx) {
     n = c->n; m = c->m; d = c->prm.d; K = c->prm.max_dim; L = K / d;
@@ -118,9 +150,11 @@ struct Lanczos {
     const int nb = L + 3;
     xi = alloc_as<double>(b_xi, (size_t)nb * d * d);
     gam = alloc_as<double>(b_gam, (size_t)nb * d * d);
-    rinv = alloc_as<double>(b_rinv, (size_t)d * d);
-    rinv2 = alloc_as<double>(b_rinv2, (size_t)d * d);
     rinvc = alloc_as<double>(b_rinvc, (size_t)2 * 4 * d * d);
+    part_xi = c->part_xi.as<double>();
+    part_g = c->part_g.as<double>();
+    part_g2 = c->part_g2.as<double>();
+    part_c = alloc_as<double>(c->part_c, (size_t)ts_part_c_len(n, 2 * d));
     nrm_xi = alloc_as<double>(b_nxi, nb);
     nrm_gam = alloc_as<double>(b_ngam, nb);
     nrm_ginv = alloc_as<double>(b_nginv, nb);
@@ -133,14 +167,18 @@ struct Lanczos {
     T = alloc_as<double>(c->tmat, (size_t)K * K);
     evals = alloc_as<double>(c->evals, K);
     H = alloc_as<double>(b_H, (size_t)(K + d) * 2 * d);
-    const int64_t chunk = ts_chunk_rows(n, 1, 2 * d);
-    const int64_t maxchunks = (n + chunk - 1) / chunk;
+    int64_t maxchunks = 1;
+    for (int nc : {d, 2 * d}) {
+      const int64_t chunk = ts_chunk_rows(n, 1, nc);
+      maxchunks = std::max(maxchunks, (n + chunk - 1) / chunk);
+    }
     hpart = alloc_as<double>(b_hpart, (size_t)maxchunks * (K + d) * 2 * d);
     flags = alloc_as<int>(c->flags, 8);
     NSP_HIP(hipMemsetAsync(flags, 0, sizeof(int) * 8, c->stream));
     NSP_HIP(hipMemsetAsync(W, 0, sizeof(double) * ldw * ldw, c->stream));
     NSP_HIP(hipMemsetAsync(nrm_theta, 0, sizeof(double) * nb, c->stream));
     NSP_HIP(hipMemsetAsync(nrm_f, 0, sizeof(double) * nb, c->stream));
+    prof.init(c->prm.profile != 0);
   }
 
   // row-interleaved copy of Lanczos block ``blk`` (1-based); for d = 1 it is
@@ -151,27 +189,30 @@ struct Lanczos {
   // Q = orth(X) for the block in slot ``blk``: Cholesky QR (twice for d > 1)
   void orthonormalize_slot(int blk, double* gam_out) {
     VT* x = slot(blk);
-    sub_gram<VT>(c, d, n, x, nullptr, nullptr, gam_out, rinv, nullptr, nullptr);
-    scale_block<VT>(c, d, n, x, rinv, x, zcol(blk), ldz, d > 1, gam_out, rinv2, nullptr, nullptr);
-    if (d > 1) scale_block<VT>(c, d, n, x, rinv2, x, zcol(blk), ldz, false, nullptr, nullptr, nullptr, nullptr);
+    int np = sub_gram<VT>(c, d, n, x, nullptr, nullptr, 0, nullptr, nullptr, part_g);
+    np = scale_block<VT>(c, d, n, x, part_g, np, x, zcol(blk), ldz, gam_out, nullptr, nullptr,
+                         d > 1 ? part_g2 : nullptr);
+    if (d > 1) scale_block2<VT>(c, d, n, part_g2, np, x, zcol(blk), ldz, gam_out, nullptr, nullptr);
   }
 
-  // the QR of P into slot ``blk`` (Gamma_{blk-1} stored), with or without the Xi subtraction
-  void qr_step(int blk_from, int blk_to, bool subtract) {
+  // Xi_{blk_from} from the SpMV partials and the QR of P into slot ``blk_to``
+  // (Gamma_{blk_from} stored), with or without the subtraction of X Xi
+  void qr_step(int blk_from, int blk_to, bool subtract, int nparts_xi, const WArgs* wa = nullptr) {
     double* g = gam + (size_t)blk_from * d * d;
-    sub_gram<VT>(c, d, n, P, subtract ? slot(blk_from) : nullptr,
-                 subtract ? xi + (size_t)blk_from * d * d : nullptr, g, rinv, nrm_gam + blk_from,
-                 nrm_ginv + blk_from);
-    scale_block<VT>(c, d, n, P, rinv, slot(blk_to), zcol(blk_to), ldz, d > 1, g, rinv2,
-                    nrm_gam + blk_from, nrm_ginv + blk_from);
+    int np = sub_gram<VT>(c, d, n, P, subtract ? slot(blk_from) : nullptr, part_xi, nparts_xi,
+                          xi + (size_t)blk_from * d * d, nrm_xi + blk_from, part_g);
+    np = scale_block<VT>(c, d, n, P, part_g, np, slot(blk_to), zcol(blk_to), ldz, g,
+                         nrm_gam + blk_from, nrm_ginv + blk_from, d > 1 ? part_g2 : nullptr,
+                         d > 1 ? nullptr : wa);
     if (d > 1)
-      scale_block<VT>(c, d, n, slot(blk_to), rinv2, slot(blk_to), zcol(blk_to), ldz, false, nullptr,
-                      nullptr, nullptr, nullptr);
+      scale_block2<VT>(c, d, n, part_g2, np, slot(blk_to), zcol(blk_to), ldz, g, nrm_gam + blk_from,
+                       nrm_ginv + blk_from, wa);
   }
 
   void cgs2_full(VT* a, int k, bool final_gram, double* rinv_out) {
-    ts_project<VT>(c, nullptr, d, 1, n, Z, ldz, k, a, nullptr, H, hpart, false, nullptr);
-    ts_project<VT>(c, nullptr, d, 1, n, Z, ldz, k, a, nullptr, H, hpart, final_gram, rinv_out);
+    ts_project<VT>(c, nullptr, d, 1, n, Z, ldz, k, a, nullptr, H, hpart, false, nullptr, nullptr);
+    ts_project<VT>(c, nullptr, d, 1, n, Z, ldz, k, a, nullptr, H, hpart, final_gram, part_c,
+                   rinv_out);
   }
 
   void run() {
@@ -197,7 +238,8 @@ struct Lanczos {
     bool stop = false;
     int n_ell = 0;
     const char* ve = std::getenv("NSP_VERBOSE");
-    const bool verbose = ve && ve[0] == '1';
+    const bool verbose = ve && (ve[0] == '1' || ve[0] == '2');
+    const bool verbose_all = ve && ve[0] == '2';
     double last_print = now_s();
     for (;;) {
       const double tc0 = now_s();
@@ -206,10 +248,9 @@ struct Lanczos {
       {
         const int blk = l0 + 1;
         spmm_block<VT>(c, c->A, d, slot(blk), Y);
-        spmmT_step<VT>(c, d, Y, slot(blk), nullptr, nullptr, P, xi + (size_t)blk * d * d,
-                       nrm_xi + blk);
+        const int npx = spmmT_step<VT>(c, d, Y, slot(blk), nullptr, nullptr, P, part_xi);
         cgs2_full(P, kk + d, false, nullptr);
-        qr_step(blk, blk + 1, false);
+        qr_step(blk, blk + 1, false, npx);
         w_reset(c, l0 + 1, 2, u_d, W, ldw);
         matvecs += d;
       }
@@ -218,35 +259,42 @@ struct Lanczos {
         VT* x = slot(ell);
         VT* xp = slot(ell - 1);
         VT* xn = slot(ell + 1);
+        const bool timed = prof.on && (ell % 16 == 0) && prof.used < Prof::kSlots;
+        if (timed) NSP_HIP(hipEventRecord(prof.ev[3 * prof.used], c->stream));
         spmm_block<VT>(c, c->A, d, x, Y);
-        spmmT_step<VT>(c, d, Y, x, xp, gam + (size_t)(ell - 1) * d * d, P,
-                       xi + (size_t)ell * d * d, nrm_xi + ell);
-        qr_step(ell, ell + 1, true);
-        wrec(c, ell, l0, u_d, u_ro, nrm_xi, nrm_gam, nrm_ginv, nrm_theta, nrm_f, W, ldw);
-        const int kz = (ell - 1) * d;  // Z_{ell-1}
-        ts_project<VT>(c, flags, d, 2, n, Z, ldz, kz, x, xn, H, hpart, false, nullptr);
-        ts_project<VT>(c, flags, d, 2, n, Z, ldz, kz, x, xn, H, hpart, true, rinvc);
-        ts_scale<VT>(c, flags, d, 2, n, x, xn, rinvc, d > 1 ? zcol(ell) : nullptr, ldz);
+        if (timed) NSP_HIP(hipEventRecord(prof.ev[3 * prof.used + 1], c->stream));
+        const int npx = spmmT_step<VT>(c, d, Y, x, xp, gam + (size_t)(ell - 1) * d * d, P, part_xi);
+        if (timed) NSP_HIP(hipEventRecord(prof.ev[3 * prof.used++ + 2], c->stream));
+        const WArgs wa{ell, l0, ldw, u_d, u_ro, nrm_xi, nrm_gam, nrm_theta, nrm_f, W, flags};
+        qr_step(ell, ell + 1, true, npx, &wa);
+        // partial reorthogonalisation of [Q_ell, Q_ell+1] against Z_{ell-1} when the
+        // W-recurrence raised the flag: one CGS pass (reading R5), then Cholesky QR
+        const int kz = (ell - 1) * d;
+        ts_project<VT>(c, flags, d, 2, n, Z, ldz, kz, x, xn, H, hpart, true, part_c, rinvc);
+        ts_scale<VT>(c, flags, d, 2, n, x, xn, part_c, rinvc, d > 1 ? zcol(ell) : nullptr, ldz);
         matvecs += d;
       }
       NSP_HIP(hipStreamSynchronize(c->stream));
       const double tc1 = now_s();
       t_lan += tc1 - tc0;
+      prof.collect();
       // ---- Rayleigh-Ritz on T (Eq. "defT")
       assemble_t(c, K, d, kk, theta_kept, fmat, xi, gam, T);
       syevd(c, K, T, evals, c->ework, b_info);
-      NSP_HIP(hipMemcpyAsync(hev.data(), evals, sizeof(double) * K, hipMemcpyDeviceToHost, c->stream));
-      NSP_HIP(hipMemcpyAsync(flags_h, flags, sizeof(int) * 8, hipMemcpyDeviceToHost, c->stream));
+      NSP_HIP(hipMemcpyAsync(c->pin_d, evals, sizeof(double) * K, hipMemcpyDeviceToHost, c->stream));
+      NSP_HIP(hipMemcpyAsync(c->pin_i, flags, sizeof(int) * 8, hipMemcpyDeviceToHost, c->stream));
       NSP_HIP(hipStreamSynchronize(c->stream));
+      std::copy(c->pin_d, c->pin_d + K, hev.begin());
+      std::copy(c->pin_i, c->pin_i + 8, flags_h);
       if (flags_h[1]) throw Error(NSP_ERR_BREAKDOWN, "a Lanczos block lost rank (Krylov breakdown)");
       for (double v : hev)
         if (!std::isfinite(v)) throw Error(NSP_ERR_NONFINITE, "non-finite Ritz value");
       n_ell = (int)std::count_if(hev.begin(), hev.end(), [&](double v) { return v < 3.0 * p.eps; });
       hist.emplace_back(matvecs, n_ell);
       st.cycles++;
-      if (verbose && now_s() - last_print > 2.0) {
-        std::fprintf(stderr, "[nsp] cycle %d matvecs %lld N_ell %d lanczos %.2fs rr %.2fs\n",
-                     st.cycles, (long long)matvecs, n_ell, t_lan, t_rr);
+      if ((verbose && now_s() - last_print > 2.0) || verbose_all) {
+        std::fprintf(stderr, "[nsp] cycle %d matvecs %lld N_ell %d theta0 %.3e theta_max %.3e reorth %d lanczos %.2fs rr %.2fs\n",
+                     st.cycles, (long long)matvecs, n_ell, hev[0], hev[K - 1], flags_h[3], t_lan, t_rr);
         std::fflush(stderr);
         last_print = now_s();
       }
@@ -268,8 +316,9 @@ struct Lanczos {
       st.restarts++;
       t_rr += now_s() - tc1;
     }
-    NSP_HIP(hipMemcpyAsync(flags_h, flags, sizeof(int) * 8, hipMemcpyDeviceToHost, c->stream));
+    NSP_HIP(hipMemcpyAsync(c->pin_i, flags, sizeof(int) * 8, hipMemcpyDeviceToHost, c->stream));
     NSP_HIP(hipStreamSynchronize(c->stream));
+    std::copy(c->pin_i, c->pin_i + 8, flags_h);
     st.nullity = n_ell;
     st.converged = stop ? 1 : 0;
     st.matvecs = matvecs;
@@ -279,6 +328,11 @@ struct Lanczos {
     st.theta_next = n_ell < K ? hev[n_ell] : 0.0;
     st.t_lanczos_s = t_lan;
     st.t_restart_s = t_rr;
+    if (prof.samples) {
+      st.t_spmv_a_us = prof.sum_a / prof.samples * 1e3;
+      st.t_spmv_at_us = prof.sum_at / prof.samples * 1e3;
+      st.spmv_samples = prof.samples;
+    }
     c->nullity = n_ell;
     c->state = 1;
     (void)t0;
@@ -304,44 +358,12 @@ struct Lanczos {
     // re-orthonormalise against the kept Ritz vectors: CGS2 with the Gram of the
     // result, then scale by R^{-1} (R ~ I)
     cgs2_full(slot(blk), kn, true, rinvc);
-    ts_scale<VT>(c, nullptr, d, 1, n, slot(blk), nullptr, rinvc, d > 1 ? zcol(blk) : nullptr, ldz);
-    // F = R Gamma_L V_Z(K-d:K, 0:kn)   (reading R11), on the host in FP64
-    std::vector<double> vlast((size_t)d * kn), gl((size_t)d * d), rr((size_t)2 * d * d);
-    NSP_HIP(hipMemcpy2DAsync(vlast.data(), sizeof(double) * d, T + (K - d), sizeof(double) * K,
-                             sizeof(double) * d, kn, hipMemcpyDeviceToHost, c->stream));
-    NSP_HIP(hipMemcpyAsync(gl.data(), gam + (size_t)L * d * d, sizeof(double) * d * d,
-                           hipMemcpyDeviceToHost, c->stream));
-    NSP_HIP(hipMemcpyAsync(rr.data(), rinvc, sizeof(double) * 2 * d * d, hipMemcpyDeviceToHost,
-                           c->stream));
-    NSP_HIP(hipStreamSynchronize(c->stream));
-    const double* rf = rr.data() + d * d;  // R follows R^{-1}
-    std::vector<double> rg((size_t)d * d, 0.0), f((size_t)d * kn, 0.0);
-    for (int i = 0; i < d; ++i)
-      for (int j = 0; j < d; ++j)
-        for (int l = 0; l < d; ++l) rg[i + j * d] += rf[i + l * d] * gl[l + j * d];
-    for (int j = 0; j < kn; ++j)
-      for (int i = 0; i < d; ++i) {
-        double s = 0.0;
-        for (int l = 0; l < d; ++l) s += rg[i + l * d] * vlast[l + (size_t)j * d];
-        f[i + (size_t)j * d] = s;
-      }
-    // block norms for the W-recurrence: ||Theta_k|| and ||F_k||_F, k = 1..kn/d
-    const int nb = kn / d;
-    std::vector<double> nth(L + 3, 0.0), nf(L + 3, 0.0);
-    for (int k = 1; k <= nb; ++k) {
-      double mx = 0.0, s2 = 0.0;
-      for (int j = (k - 1) * d; j < k * d; ++j) {
-        mx = std::max(mx, std::fabs(hev[j]));
-        for (int i = 0; i < d; ++i) s2 += f[i + (size_t)j * d] * f[i + (size_t)j * d];
-      }
-      nth[k] = mx;
-      nf[k] = std::sqrt(s2);
-    }
-    NSP_HIP(hipMemcpyAsync(fmat, f.data(), sizeof(double) * d * kn, hipMemcpyHostToDevice, c->stream));
-    NSP_HIP(hipMemcpyAsync(theta_kept, hev.data(), sizeof(double) * kn, hipMemcpyHostToDevice, c->stream));
-    NSP_HIP(hipMemcpyAsync(nrm_theta, nth.data(), sizeof(double) * (L + 3), hipMemcpyHostToDevice, c->stream));
-    NSP_HIP(hipMemcpyAsync(nrm_f, nf.data(), sizeof(double) * (L + 3), hipMemcpyHostToDevice, c->stream));
-    NSP_HIP(hipStreamSynchronize(c->stream));
+    ts_scale<VT>(c, nullptr, d, 1, n, slot(blk), nullptr, part_c, rinvc, d > 1 ? zcol(blk) : nullptr,
+                 ldz);
+    // F = R Gamma_L V_Z(K-d:K, 0:kn) (reading R11), Theta and the kept-block norms
+    restart_coupling(c, K, d, kn, T, gam + (size_t)L * d * d, rinvc, evals, fmat, theta_kept,
+                     nrm_theta, nrm_f);
+    (void)hev;
   }
 
   // V = Z(:, 0:K) V_Z(:, 0:N) in FP64, column-major n x N
@@ -385,10 +407,9 @@ struct Refiner {
     rocblas_int* inf = alloc_as<rocblas_int>(b_info, 1);
     gram_rows(vr, n, g);
     NSP_BLAS(rocsolver_dpotrf(c->blas, rocblas_fill_upper, k, g, k, inf));
-    rocblas_int h = 0;
-    NSP_HIP(hipMemcpyAsync(&h, inf, sizeof(h), hipMemcpyDeviceToHost, c->stream));
+    NSP_HIP(hipMemcpyAsync(c->pin_i + 8, inf, sizeof(rocblas_int), hipMemcpyDeviceToHost, c->stream));
     NSP_HIP(hipStreamSynchronize(c->stream));
-    if (h != 0) throw Error(NSP_ERR_BREAKDOWN, "refined basis lost rank (Cholesky QR failed)");
+    if (c->pin_i[8] != 0) throw Error(NSP_ERR_BREAKDOWN, "refined basis lost rank (Cholesky QR failed)");
     // V <- V R^{-1}: in the column-major view Vcm = V^T: Vcm <- R^{-T} Vcm
     const double one = 1.0;
     NSP_BLAS(rocblas_dtrsm(c->blas, rocblas_side_left, rocblas_fill_upper, rocblas_operation_transpose,
@@ -399,6 +420,8 @@ struct Refiner {
     nsp_params& p = c->prm;
     nsp_stats& st = c->stats;
     const double t0 = now_s();
+    c->pin_d = c->pind.ensure(std::max<size_t>((size_t)c->prm.max_dim + 16, (size_t)k * (k + 1) + 16));
+    c->pin_i = c->pini.ensure(std::max<size_t>(64, (size_t)k + 16));
     double* vr = alloc_as<double>(b_vr, (size_t)n * k);
     double* u = alloc_as<double>(b_u, (size_t)m * k);
     colmajor_to_rows(c, n, k, c->V.as<double>(), n, vr);
@@ -441,15 +464,18 @@ struct Refiner {
     std::vector<double> hs(k);
     std::vector<int> ha(k);
     auto update_active = [&]() -> bool {
-      NSP_HIP(hipMemcpyAsync(hs.data(), sn2, sizeof(double) * k, hipMemcpyDeviceToHost, c->stream));
+      NSP_HIP(hipMemcpyAsync(c->pin_d, sn2, sizeof(double) * k, hipMemcpyDeviceToHost, c->stream));
       NSP_HIP(hipStreamSynchronize(c->stream));
+      std::copy(c->pin_d, c->pin_d + k, hs.begin());
       bool any = false;
       for (int j = 0; j < k; ++j) {
         if (!std::isfinite(hs[j])) throw Error(NSP_ERR_NONFINITE, "non-finite value in refinement");
         ha[j] = std::sqrt(hs[j]) > tau ? 1 : 0;
         any |= ha[j] != 0;
       }
-      NSP_HIP(hipMemcpyAsync(act, ha.data(), sizeof(int) * k, hipMemcpyHostToDevice, c->stream));
+      std::copy(ha.begin(), ha.end(), c->pin_i);
+      NSP_HIP(hipMemcpyAsync(act, c->pin_i, sizeof(int) * k, hipMemcpyHostToDevice, c->stream));
+      NSP_HIP(hipStreamSynchronize(c->stream));
       return any;
     };
     int64_t it = 0;
@@ -491,9 +517,11 @@ struct Refiner {
     double* g = alloc_as<double>(b_small, (size_t)k * k);
     gram_rows(vr, n, g);
     std::vector<double> hg((size_t)k * k);
-    NSP_HIP(hipMemcpyAsync(hs.data(), sn2, sizeof(double) * k, hipMemcpyDeviceToHost, c->stream));
-    NSP_HIP(hipMemcpyAsync(hg.data(), g, sizeof(double) * k * k, hipMemcpyDeviceToHost, c->stream));
+    NSP_HIP(hipMemcpyAsync(c->pin_d, sn2, sizeof(double) * k, hipMemcpyDeviceToHost, c->stream));
+    NSP_HIP(hipMemcpyAsync(c->pin_d + k, g, sizeof(double) * k * k, hipMemcpyDeviceToHost, c->stream));
     NSP_HIP(hipStreamSynchronize(c->stream));
+    std::copy(c->pin_d, c->pin_d + k, hs.begin());
+    std::copy(c->pin_d + k, c->pin_d + k + (size_t)k * k, hg.begin());
     double res2 = 0.0, oe = 0.0;
     for (double v : hs) res2 += v;
     for (int i = 0; i < k; ++i)
@@ -547,6 +575,8 @@ void run_backward(nsp_ctx* c, const double* GsV, int64_t ld, double* grad, doubl
     return;
   }
   DBuf b_v, b_g, b_w, b_r, b_p, b_q, b_y, b_mm, b_dots, b_part, b_act;
+  c->pin_d = c->pind.ensure(std::max<size_t>((size_t)c->prm.max_dim + 16, (size_t)k + 16));
+  c->pin_i = c->pini.ensure(std::max<size_t>(64, (size_t)k + 16));
   double* vr = alloc_as<double>(b_v, (size_t)n * k);
   double* r = alloc_as<double>(b_r, (size_t)n * k);
   colmajor_to_rows(c, n, k, c->V.as<double>(), n, vr);
@@ -568,15 +598,18 @@ void run_backward(nsp_ctx* c, const double* GsV, int64_t ld, double* grad, doubl
   coldots(c, n, k, r, r, rr, part);
   std::vector<double> r0(k), hr(k);
   std::vector<int> ha(k);
-  NSP_HIP(hipMemcpyAsync(r0.data(), rr, sizeof(double) * k, hipMemcpyDeviceToHost, c->stream));
+  NSP_HIP(hipMemcpyAsync(c->pin_d, rr, sizeof(double) * k, hipMemcpyDeviceToHost, c->stream));
   NSP_HIP(hipStreamSynchronize(c->stream));
+  std::copy(c->pin_d, c->pin_d + k, r0.begin());
   bool any = false;
   for (int j = 0; j < k; ++j) {
     r0[j] = std::sqrt(r0[j]);
     ha[j] = r0[j] > 0.0 ? 1 : 0;
     any |= ha[j] != 0;
   }
-  NSP_HIP(hipMemcpyAsync(act, ha.data(), sizeof(int) * k, hipMemcpyHostToDevice, c->stream));
+  std::copy(ha.begin(), ha.end(), c->pin_i);
+  NSP_HIP(hipMemcpyAsync(act, c->pin_i, sizeof(int) * k, hipMemcpyHostToDevice, c->stream));
+  NSP_HIP(hipStreamSynchronize(c->stream));
   int64_t it = 0;
   while (any && it < max_iter) {
     spmm_wide(c, c->A, k, pp, y);
@@ -594,15 +627,18 @@ void run_backward(nsp_ctx* c, const double* GsV, int64_t ld, double* grad, doubl
       dgemm(c, rocblas_operation_none, rocblas_operation_transpose, k, k, n, 1.0, vr, k, r, k, 0.0, mm, k);
       dgemm(c, rocblas_operation_transpose, rocblas_operation_none, k, n, k, -1.0, mm, k, vr, k, 1.0, r, k);
       coldots(c, n, k, r, r, rr, part);
-      NSP_HIP(hipMemcpyAsync(hr.data(), rr, sizeof(double) * k, hipMemcpyDeviceToHost, c->stream));
+      NSP_HIP(hipMemcpyAsync(c->pin_d, rr, sizeof(double) * k, hipMemcpyDeviceToHost, c->stream));
       NSP_HIP(hipStreamSynchronize(c->stream));
+      std::copy(c->pin_d, c->pin_d + k, hr.begin());
       any = false;
       for (int j = 0; j < k; ++j) {
         if (!std::isfinite(hr[j])) throw Error(NSP_ERR_NONFINITE, "non-finite value in backward CG");
         ha[j] = std::sqrt(hr[j]) > tol * r0[j] ? 1 : 0;
         any |= ha[j] != 0;
       }
-      NSP_HIP(hipMemcpyAsync(act, ha.data(), sizeof(int) * k, hipMemcpyHostToDevice, c->stream));
+      std::copy(ha.begin(), ha.end(), c->pin_i);
+      NSP_HIP(hipMemcpyAsync(act, c->pin_i, sizeof(int) * k, hipMemcpyHostToDevice, c->stream));
+      NSP_HIP(hipStreamSynchronize(c->stream));
     }
   }
   // U = A W, grad_p = -2 <U_i, V_j>
