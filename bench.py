@@ -34,7 +34,7 @@ HBM_PEAK_GBS = 8000.0
 WORKLOADS = {
     "er20": dict(gen=("er20",), eps=0.1 * 0.36330958416634257 ** 2, max_dim=64,
                  desc="Laplacian of 20 disjoint G(100, 6/99) components, n=2000, nullity 20"),
-    "planted50k": dict(gen=("planted50k",), eps=2e-6, max_dim=512,
+    "planted50k": dict(gen=("planted50k",), eps=2e-6, max_dim=1024,
                        desc="planted A=[B, BR], m=n=50000, B 8 N(0,1)/col, R 4 N(0,1)/col, nullity 200"),
 }
 
@@ -118,11 +118,71 @@ def cpu_baseline(c, eps, d, max_dim, gpu_stats, budget_s=20.0):
     }
 
 
+def spmv_pair_bytes(m, n, nnz, d, esize):
+    """Algorithmic HBM bytes of one Lanczos step's SpMV pair (Alg. 2 inner loop).
+
+    y = A x reads A's CSR once (int32 row pointers and column indices, values
+    of ``esize`` bytes), x once and writes y; the fused second product reads
+    the stored transpose, y, x, the previous block and D, and writes P.
+    """
+    a = 4 * (m + 1) + nnz * (4 + esize) + esize * d * (n + m)
+    at = 4 * (n + 1) + nnz * (4 + esize) + esize * d * (m + n + n + n) + 8 * n
+    return a, at
+
+
+def kernel_rooflines(st, m, n, nnz, d, esize):
+    """Per-kernel achieved GB/s from the solver's HIP-event samples (profile mode)."""
+    a_b, at_b = spmv_pair_bytes(m, n, nnz, d, esize)
+    out = []
+    if st.get("spmv_samples", 0) > 0:
+        out.append(("k_spmm (y = A x)", st["t_spmv_a_us"], a_b))
+        out.append(("k_spmmT_step (P = A^T y + eps D x - Xp Gamma^T)", st["t_spmv_at_us"], at_b))
+    ns = st.get("ro_samples", 0)
+    if ns > 0:
+        out.append(("k_ts_tn + k_reduce_cols (H = Z^T [q_l, q_l+1])", st["ro_tn_ms"] / ns * 1e3,
+                    st["ro_tn_bytes"] / ns))
+        out.append(("k_ts_nn ([q_l, q_l+1] -= Z H, fused Gram)", st["ro_nn_ms"] / ns * 1e3,
+                    st["ro_nn_bytes"] / ns))
+    rows = []
+    for name, us, b in out:
+        gbs = b / (us * 1e-6) / 1e9 if us > 0 else 0.0
+        rows.append({"kernel": name, "avg_us": us, "bytes_per_launch": b, "achieved_gbs": gbs})
+    return rows
+
+
+def spmv_hbm(name, prec, d=1, max_dim=64):
+    """SpMV pair inside real Lanczos steps on a matrix far larger than the caches.
+
+    One restart cycle (``max_dim`` steps, no refinement) on the named workload;
+    the library times every 4th step's SpMV pair with HIP events on its stream.
+    """
+    import torch
+    from paper_2407_04634_amd import Context, PREC_FP64, PREC_MIXED
+    from workloads import generators as G
+
+    c = G.config(name)
+    ctx = Context(torch.from_numpy(c.rowptr).cuda(), torch.from_numpy(c.colind).cuda(),
+                  torch.from_numpy(c.vals).cuda(), c.m, c.n,
+                  D=torch.from_numpy(G.perturbation_diagonal(c.n, 1)).cuda(),
+                  Omega=torch.from_numpy(np.ascontiguousarray(G.gaussian_start_block(c.n, d, 1))).cuda(),
+                  eps=1e-3, d=d, max_dim=max_dim, prec=PREC_MIXED if prec == "mixed" else PREC_FP64,
+                  max_cycles=1, refine=0, profile=1)
+    st = ctx.lanczos_run(allow_noconv=True)
+    ctx.close()
+    esize = 4 if prec == "mixed" else 8
+    a_b, at_b = spmv_pair_bytes(c.m, c.n, c.nnz, d, esize)
+    t = st["t_spmv_a_us"] + st["t_spmv_at_us"]
+    gbs = (a_b + at_b) / (t * 1e-6) / 1e9
+    return {"workload": name, "m": c.m, "n": c.n, "nnz": c.nnz, "d": d, "prec": prec,
+            "samples": st["spmv_samples"], "us_A": st["t_spmv_a_us"], "us_AT": st["t_spmv_at_us"],
+            "bytes_pair": a_b + at_b, "achieved_gbs": gbs, "frac_hbm": gbs / HBM_PEAK_GBS}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=1)
-    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--warmup", type=int, default=0)
     ap.add_argument("--workload", default="planted50k", choices=sorted(WORKLOADS))
     ap.add_argument("--d", type=int, default=1)
     ap.add_argument("--prec", default="fp64", choices=["fp64", "mixed"])
@@ -131,7 +191,10 @@ def main():
     ap.add_argument("--max-cycles", type=int, default=0,
                     help="stop after this many restart cycles (profiling runs; the result is not valid)")
     ap.add_argument("--no-refine", action="store_true", help="skip the FP64 refinement (profiling runs)")
-    ap.add_argument("--profile", type=int, default=1, help="HIP-event timing of the SpMV pair")
+    ap.add_argument("--profile", type=int, default=1,
+                    help="HIP-event timing of the SpMV and reorthogonalisation kernels")
+    ap.add_argument("--spmv-workload", default="zipf4m",
+                    help="large matrix for the SpMV HBM measurement ('none' to skip)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only; --gpus {args.gpus} is not supported "
@@ -202,6 +265,21 @@ def main():
         "solver": {k: st[k] for k in ("matvecs", "restarts", "reorths", "refine_iters",
                                       "t_lanczos_s", "t_restart_s", "t_refine_s", "theta_next")},
     }
+    esize = 4 if args.prec == "mixed" else 8
+    kr = kernel_rooflines(st, c.m, c.n, c.nnz, args.d, esize)
+    if kr:
+        dom = max(kr, key=lambda r: r["avg_us"])  # every kernel here runs once per Lanczos step
+        line["roofline"] = {"kernel": dom["kernel"], "bound": "hbm", "achieved": dom["achieved_gbs"],
+                            "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                            "frac": dom["achieved_gbs"] / HBM_PEAK_GBS, "traffic": None,
+                            "avg_us": dom["avg_us"], "bytes_per_launch": dom["bytes_per_launch"]}
+        line["kernels"] = kr
+        line["reorth_active_frac"] = st["ro_active"] / max(1, st["ro_samples"])
+    if args.spmv_workload != "none":
+        sp = [spmv_hbm(args.spmv_workload, p) for p in ("fp64", "mixed")]
+        for r in sp:
+            print(f"[bench] spmv {json.dumps(r)}", file=sys.stderr, flush=True)
+        line["spmv_hbm"] = sp
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(c, eps, args.d, max_dim, st)
     print(json.dumps(line), flush=True)

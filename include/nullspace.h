@@ -79,8 +79,9 @@ typedef struct {
                             threshold of the enabled (non-zero) criteria applies.   */
   int64_t max_refine_iter; /* CGLS iteration cap of the refinement                   */
   int32_t max_cycles;    /* stop after this many restart cycles (0 = no limit)       */
-  int32_t profile;       /* 1: time the SpMV pair with HIP events on the context's
-                            stream at every 16th Lanczos step (nsp_stats.t_spmv_*)   */
+  int32_t profile;       /* 1: time the SpMV pair and the reorthogonalisation pair
+                            with HIP events on the library's stream at every 4th
+                            Lanczos step (nsp_stats.t_spmv_*, ro_*)                  */
   uint64_t seed;         /* seed of the built-in Philox4x32-10 draws of D and Omega,
                             used only when the caller passes D or Omega as NULL       */
 } nsp_params;
@@ -106,6 +107,15 @@ typedef struct {
   double t_spmv_a_us;      /* profile: mean duration of one y = A x launch (us)         */
   double t_spmv_at_us;     /* profile: mean duration of one fused A^T launch (us)       */
   int64_t spmv_samples;    /* profile: number of timed launch pairs                     */
+  double ro_tn_ms;         /* profile: summed duration of the sampled projections
+                              H = Z^T [Q_l, Q_l+1] (with their column reduction), ms;
+                              launches whose flag is clear return at once and count  */
+  double ro_tn_bytes;      /* ... their algorithmic bytes, (k n + 2 d n) elements each
+                              for the launches that ran, 0 for the others            */
+  double ro_nn_ms;         /* profile: same for the updates [Q_l, Q_l+1] -= Z H, ms   */
+  double ro_nn_bytes;      /* ... (k n + 4 d n) elements for the launches that ran    */
+  int64_t ro_samples;      /* profile: number of sampled steps                         */
+  int64_t ro_active;       /* profile: how many of them reorthogonalised               */
 } nsp_stats;
 
 /* Fill *p with defaults: eps = 1e-3 (Sec. 5.3), d = 1, max_dim = 64,
@@ -159,6 +169,20 @@ nsp_status extract_basis(nsp_ctx* ctx, double* V, int64_t ldv);
  *  theta  host buffer of capacity cap; *count receives the number written
  *  (min(cap, dim K)).  Before refinement, i.e. eigenvalues of T_ell. */
 nsp_status nullspace_ritz_values(nsp_ctx* ctx, double* theta, int32_t cap, int32_t* count);
+
+/* Eigen-decomposition of the restart matrix of Alg. 2 for block size 1
+ * (Eq. "defT"), the Rayleigh-Ritz step the solver runs once per restart:
+ *     T = [diag(theta)  f      0 ...      ]
+ *         [f^T          alpha0 beta0      ]
+ *         [0            beta0  alpha1 ... ]   (tridiagonal below the arrow tip)
+ * of order K >= 2 with 0 <= kk <= K-2 kept Ritz values.
+ *  theta  [kk] ascending, f [kk], alpha [K-kk], beta [K-kk-1]: device, FP64.
+ *  evals  [K] out, ascending; evecs [K x K] out, column-major (ld K), device.
+ * Exposed so the structured solver can be tested on its own; it runs on the
+ * context's stream and synchronises.  Errors: NSP_ERR_ARG, NSP_ERR_HIP. */
+nsp_status nullspace_ritz_eig(nsp_ctx* ctx, int32_t K, int32_t kk, const double* theta,
+                              const double* f, const double* alpha, const double* beta,
+                              double* evals, double* evecs);
 
 /* Backward pass for a loss L(P), P = V V^T, with V from extract_basis.
  *  GsV        [n x N], ld >= n, device: G_s V where G_s is the symmetric part

@@ -69,6 +69,12 @@ class Stats(ctypes.Structure):
         ("t_spmv_a_us", ctypes.c_double),
         ("t_spmv_at_us", ctypes.c_double),
         ("spmv_samples", ctypes.c_int64),
+        ("ro_tn_ms", ctypes.c_double),
+        ("ro_tn_bytes", ctypes.c_double),
+        ("ro_nn_ms", ctypes.c_double),
+        ("ro_nn_bytes", ctypes.c_double),
+        ("ro_samples", ctypes.c_int64),
+        ("ro_active", ctypes.c_int64),
     ]
 
     def as_dict(self) -> dict:
@@ -76,8 +82,8 @@ class Stats(ctypes.Structure):
 
 
 EXPORTS = ["nsp_default_params", "nullspace_init", "apply_op", "lanczos_run", "nullspace_nullity",
-           "extract_basis", "nullspace_ritz_values", "backward", "nullspace_destroy",
-           "nullspace_last_error"]
+           "extract_basis", "nullspace_ritz_values", "nullspace_ritz_eig", "backward",
+           "nullspace_destroy", "nullspace_last_error"]
 
 _lib = None
 
@@ -100,13 +106,14 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.nullspace_nullity.argtypes = [vp, ctypes.POINTER(i32)]
     lib.extract_basis.argtypes = [vp, vp, i64]
     lib.nullspace_ritz_values.argtypes = [vp, ctypes.POINTER(dbl), i32, ctypes.POINTER(i32)]
+    lib.nullspace_ritz_eig.argtypes = [vp, i32, i32, vp, vp, vp, vp, vp, vp]
     lib.backward.argtypes = [vp, vp, i64, vp, dbl, i64, ctypes.POINTER(i64)]
     lib.nullspace_destroy.argtypes = [vp]
     lib.nullspace_destroy.restype = None
     lib.nullspace_last_error.argtypes = []
     lib.nullspace_last_error.restype = ctypes.c_char_p
     for name in ("nullspace_init", "apply_op", "lanczos_run", "nullspace_nullity", "extract_basis",
-                 "nullspace_ritz_values", "backward"):
+                 "nullspace_ritz_values", "nullspace_ritz_eig", "backward"):
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -201,6 +208,17 @@ class Context:
         cnt = ctypes.c_int32()
         _check(load().nullspace_ritz_values(self._h, buf, cap, ctypes.byref(cnt)))
         return [buf[i] for i in range(cnt.value)]
+
+    def ritz_eig(self, theta, f, alpha, beta):
+        """Eigenpairs of the restart matrix (d = 1) from device float64 vectors."""
+        kk, m = int(theta.numel()), int(alpha.numel())
+        k = kk + m
+        ev = torch.empty(k, dtype=torch.float64, device="cuda")
+        vec = torch.empty((k, k), dtype=torch.float64, device="cuda")  # column-major as k x k^T
+        _check(load().nullspace_ritz_eig(self._h, k, kk, _ptr(theta) if kk else None,
+                                         _ptr(f) if kk else None, _ptr(alpha), _ptr(beta), _ptr(ev),
+                                         _ptr(vec)))
+        return ev, vec.t()
 
     def backward(self, gsv: torch.Tensor, tol: float = 1e-12, max_iter: int = 10 ** 6):
         """grad w.r.t. A's stored values for G_s V (n x N), via the library's CG + SDDMM."""

@@ -1,10 +1,13 @@
 // C ABI entry points (include/nullspace.h).  Validation, error codes, the
 // thread-local error message and context ownership live here; the numerical
 // work is in kernels_*.hip and solver.hip.
+#include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <vector>
 
 #include "common.h"
+#include "kernels.h"
 
 namespace {
 
@@ -185,6 +188,60 @@ nsp_status nullspace_ritz_values(nsp_ctx* ctx, double* theta, int32_t cap, int32
     const int32_t k = (int32_t)std::min<size_t>((size_t)cap, ctx->ritz.size());
     for (int32_t i = 0; i < k; ++i) theta[i] = ctx->ritz[i];
     *count = k;
+  });
+}
+
+nsp_status nullspace_ritz_eig(nsp_ctx* ctx, int32_t K, int32_t kk, const double* theta,
+                              const double* f, const double* alpha, const double* beta,
+                              double* evals, double* evecs) {
+  return guarded([&] {
+    NSP_REQUIRE(ctx != nullptr, "ctx must not be NULL");
+    NSP_REQUIRE(K >= 2 && kk >= 0 && kk <= K - 2, "need K >= 2 and 0 <= kk <= K-2");
+    NSP_REQUIRE(alpha && beta && evals && evecs && (kk == 0 || (theta && f)), "NULL argument");
+    enter(ctx);
+    const int m = K - kk;
+    // host copies give a bound on ||T|| (largest absolute row sum)
+    std::vector<double> ht(kk), hf(kk), ha(m), hb(m - 1);
+    if (kk) {
+      NSP_HIP(hipMemcpy(ht.data(), theta, sizeof(double) * kk, hipMemcpyDeviceToHost));
+      NSP_HIP(hipMemcpy(hf.data(), f, sizeof(double) * kk, hipMemcpyDeviceToHost));
+    }
+    NSP_HIP(hipMemcpy(ha.data(), alpha, sizeof(double) * m, hipMemcpyDeviceToHost));
+    if (m > 1) NSP_HIP(hipMemcpy(hb.data(), beta, sizeof(double) * (m - 1), hipMemcpyDeviceToHost));
+    double bound = 0.0, tip = std::fabs(ha[0]) + (m > 1 ? std::fabs(hb[0]) : 0.0);
+    for (int i = 0; i < kk; ++i) {
+      bound = std::max(bound, std::fabs(ht[i]) + std::fabs(hf[i]));
+      tip += std::fabs(hf[i]);
+    }
+    bound = std::max(bound, tip);
+    for (int i = 1; i < m; ++i)
+      bound = std::max(bound, std::fabs(ha[i]) + std::fabs(hb[i - 1]) + (i + 1 < m ? std::fabs(hb[i]) : 0.0));
+    // block-indexed copies: xi[kk+1+i] = alpha[i], gam[kk+1+i] = beta[i]
+    nsp::DBuf xi, gam, info;
+    xi.alloc(sizeof(double) * (K + 2));
+    gam.alloc(sizeof(double) * (K + 2));
+    info.alloc(sizeof(int) * 4);
+    NSP_HIP(hipMemsetAsync(xi.p, 0, sizeof(double) * (K + 2), ctx->stream));
+    NSP_HIP(hipMemsetAsync(gam.p, 0, sizeof(double) * (K + 2), ctx->stream));
+    NSP_HIP(hipMemsetAsync(info.p, 0, sizeof(int) * 4, ctx->stream));
+    NSP_HIP(hipMemcpyAsync(xi.as<double>() + kk + 1, alpha, sizeof(double) * m, hipMemcpyDeviceToDevice,
+                           ctx->stream));
+    if (m > 1)
+      NSP_HIP(hipMemcpyAsync(gam.as<double>() + kk + 1, beta, sizeof(double) * (m - 1),
+                             hipMemcpyDeviceToDevice, ctx->stream));
+    nsp::EigWork* w = nsp::eig_work_new();
+    try {
+      nsp::eig_restart_d1(ctx, *w, K, kk, bound, theta, f, xi.as<double>(), gam.as<double>(), evals,
+                          evecs, info.as<int>());
+      NSP_HIP(hipMemcpyAsync(ctx->pin_i, info.p, sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
+      NSP_HIP(hipStreamSynchronize(ctx->stream));
+    } catch (...) {
+      nsp::eig_work_delete(w);
+      throw;
+    }
+    nsp::eig_work_delete(w);
+    if (ctx->pin_i[0] != 0) throw nsp::Error(NSP_ERR_HIP, "tridiagonal eigensolver failed");
+    leave(ctx);
   });
 }
 

@@ -24,6 +24,7 @@ struct WArgs {
   const double *n_xi, *n_gam, *n_theta, *n_f;
   double* w;
   int* flags;
+  int* hist;  // optional: per-step record of the reorthogonalisation flag
 };
 
 // dense: Lanczos step.  Each returns its grid size = number of partials written.
@@ -46,7 +47,7 @@ int64_t ts_part_c_len(int64_t n, int nc);
 template <typename VT>
 void ts_project(nsp_ctx* c, const int* cond, int d, int na, int64_t n, const VT* z, int64_t ldz,
                 int k, VT* a0, VT* a1, double* h, double* hpart, bool gram, double* part_c,
-                double* rinv);
+                double* rinv, hipEvent_t ev_mid = nullptr);
 // C = C R^{-1}; R from the Gram partials of the preceding ts_project(gram) (R^{-1}, R -> rinv)
 template <typename VT>
 void ts_scale(nsp_ctx* c, const int* cond, int d, int na, int64_t n, VT* a0, VT* a1,
@@ -65,6 +66,14 @@ template <typename SRC, typename DST>
 void convert(nsp_ctx* c, int64_t cnt, const SRC* s, DST* o);
 template <typename SRC, typename DST>
 void copy_panel(nsp_ctx* c, int64_t rows, int cols, const SRC* s, int64_t lds, DST* o, int64_t ldo);
+
+// Ritz eigenproblem of the restart matrix for d = 1 (eig.hip)
+struct EigWork;
+EigWork* eig_work_new();
+void eig_work_delete(EigWork* w);
+void eig_restart_d1(nsp_ctx* c, EigWork& w, int K, int kk, double norm_t, const double* theta,
+                    const double* f, const double* xi, const double* gam, double* evals,
+                    double* evecs, int* info_dev);
 
 // dense: refinement / backward
 void coldots(nsp_ctx* c, int64_t rows, int k, const double* a, const double* b, double* out,

@@ -122,6 +122,7 @@ __device__ void wrec_block(const WArgs& a, double gi, double* red) {
   if (t == 0) {
     a.flags[0] = need ? 1 : 0;
     if (need) a.flags[3] += 1;
+    if (a.hist) a.hist[ell] = need ? 1 : 0;
   }
 }
 
@@ -827,7 +828,7 @@ int64_t ts_chunk_rows(int64_t n, int k, int nc) {
 template <typename VT, int DA, int NA>
 static void ts_proj_t(nsp_ctx* c, const int* cond, int64_t n, const VT* z, int64_t ldz, int k,
                       VT* a0, VT* a1, double* h, double* hpart, bool gram, double* part_c,
-                      double* rinv) {
+                      double* rinv, hipEvent_t ev_mid) {
   constexpr int NC = DA * NA;
   CPair<VT, DA, NA> cc{a0, a1};
   const unsigned nnblocks = (unsigned)((n + kWave - 1) / kWave);
@@ -840,6 +841,7 @@ static void ts_proj_t(nsp_ctx* c, const int* cond, int64_t n, const VT* z, int64
     k_reduce_cols<<<nblk((int64_t)k * NC, 32), 256, 0, c->stream>>>(cond, (int)nchunks, k * NC,
                                                                     hpart, h);
   }
+  if (ev_mid) NSP_HIP(hipEventRecord(ev_mid, c->stream));
   if (gram) {
     k_ts_nn<VT, DA, NA, true><<<nnblocks, kThreads, 0, c->stream>>>(cond, n, z, ldz, k, h, cc, part_c);
     if (NC > 4)
@@ -874,20 +876,21 @@ static void ts_scale_t(nsp_ctx* c, const int* cond, int64_t n, VT* a0, VT* a1, c
 template <typename VT>
 void ts_project(nsp_ctx* c, const int* cond, int d, int na, int64_t n, const VT* z, int64_t ldz,
                 int k, VT* a0, VT* a1, double* h, double* hpart, bool gram, double* part_c,
-                double* rinv) {
+                double* rinv, hipEvent_t ev_mid) {
   k = std::max(k, 0);
 #define NSP_TP(D)                                                                              \
   case D:                                                                                      \
-    if (na == 1) ts_proj_t<VT, D, 1>(c, cond, n, z, ldz, k, a0, a1, h, hpart, gram, part_c, rinv); \
-    else ts_proj_t<VT, D, 2>(c, cond, n, z, ldz, k, a0, a1, h, hpart, gram, part_c, rinv);          \
+    if (na == 1) ts_proj_t<VT, D, 1>(c, cond, n, z, ldz, k, a0, a1, h, hpart, gram, part_c, rinv, ev_mid); \
+    else ts_proj_t<VT, D, 2>(c, cond, n, z, ldz, k, a0, a1, h, hpart, gram, part_c, rinv, ev_mid);          \
     break;
   switch (d) { NSP_TP(1) NSP_TP(2) NSP_TP(4) NSP_TP(8) default: throw Error(NSP_ERR_ARG, "d"); }
 #undef NSP_TP
 }
 template void ts_project<double>(nsp_ctx*, const int*, int, int, int64_t, const double*, int64_t,
-                                 int, double*, double*, double*, double*, bool, double*, double*);
+                                 int, double*, double*, double*, double*, bool, double*, double*,
+                                 hipEvent_t);
 template void ts_project<float>(nsp_ctx*, const int*, int, int, int64_t, const float*, int64_t, int,
-                                float*, float*, double*, double*, bool, double*, double*);
+                                float*, float*, double*, double*, bool, double*, double*, hipEvent_t);
 
 template <typename VT>
 void ts_scale(nsp_ctx* c, const int* cond, int d, int na, int64_t n, VT* a0, VT* a1,

@@ -20,6 +20,7 @@
 #include <cstdlib>
 #include <cmath>
 #include <limits>
+#include <memory>
 
 #include "common.h"
 #include "kernels.h"
@@ -103,38 +104,58 @@ struct Lanczos {
   double *W, *theta_kept, *fmat, *T, *evals, *H, *hpart;
   int ldw;
   int* flags;
+  std::unique_ptr<EigWork, void (*)(EigWork*)> eigw{eig_work_new(), eig_work_delete};
   DBuf b_xi, b_gam, b_rinvc, b_nxi, b_ngam, b_nginv, b_ntheta, b_nf, b_W, b_hpart,
       b_H, b_info, b_vzf, b_tmpv;
 
-  // HIP-event timing of the SpMV pair at sampled steps (profile mode)
+  // HIP-event timing at sampled steps (profile mode): the SpMV pair and the
+  // reorthogonalisation pair (projection H = Z^T C with its reduction, then the
+  // update C -= Z H), with the per-step flag telling which pairs really ran
   struct Prof {
-    static constexpr int kSlots = 64;
+    static constexpr int kSlots = 160;
+    static constexpr int kEv = 6;
     bool on = false;
     int used = 0;
-    int64_t samples = 0;
-    double sum_a = 0.0, sum_at = 0.0;  // milliseconds
-    hipEvent_t ev[3 * kSlots];
+    int ell[kSlots];
+    int kcols[kSlots];
+    int64_t samples = 0, ro_active = 0;
+    double sum_a = 0.0, sum_at = 0.0, tn_ms = 0.0, nn_ms = 0.0, tn_bytes = 0.0, nn_bytes = 0.0;
+    hipEvent_t ev[kEv * kSlots];
     void init(bool enable) {
       on = enable;
       if (on)
         for (auto& e : ev) NSP_HIP(hipEventCreate(&e));
     }
-    void collect() {
+    hipEvent_t e(int slot, int i) { return ev[kEv * slot + i]; }
+    // hist: per-step reorthogonalisation flags of this cycle (host copy)
+    void collect(const int* hist, int64_t n, int d, int esize) {
       for (int i = 0; i < used; ++i) {
-        float a = 0.f, b = 0.f;
-        NSP_HIP(hipEventElapsedTime(&a, ev[3 * i], ev[3 * i + 1]));
-        NSP_HIP(hipEventElapsedTime(&b, ev[3 * i + 1], ev[3 * i + 2]));
+        float a = 0.f, b = 0.f, t = 0.f, u = 0.f;
+        NSP_HIP(hipEventElapsedTime(&a, e(i, 0), e(i, 1)));
+        NSP_HIP(hipEventElapsedTime(&b, e(i, 1), e(i, 2)));
+        NSP_HIP(hipEventElapsedTime(&t, e(i, 3), e(i, 4)));
+        NSP_HIP(hipEventElapsedTime(&u, e(i, 4), e(i, 5)));
         sum_a += a;
         sum_at += b;
+        tn_ms += t;
+        nn_ms += u;
         ++samples;
+        if (hist[ell[i]]) {
+          const double k = kcols[i];
+          tn_bytes += esize * (k * n + 2.0 * d * n);
+          nn_bytes += esize * (k * n + 4.0 * d * n);
+          ++ro_active;
+        }
       }
       used = 0;
     }
     ~Prof() {
       if (on)
-        for (auto& e : ev) (void)hipEventDestroy(e);
+        for (auto& x : ev) (void)hipEventDestroy(x);
     }
   } prof;
+  DBuf b_rohist;
+  int* ro_hist = nullptr;
 
   explicit Lanczos(nsp_ctx* ctx) : c(ctx) {
     n = c->n; m = c->m; d = c->prm.d; K = c->prm.max_dim; L = K / d;
@@ -179,6 +200,10 @@ struct Lanczos {
     NSP_HIP(hipMemsetAsync(nrm_theta, 0, sizeof(double) * nb, c->stream));
     NSP_HIP(hipMemsetAsync(nrm_f, 0, sizeof(double) * nb, c->stream));
     prof.init(c->prm.profile != 0);
+    if (prof.on) {
+      ro_hist = alloc_as<int>(b_rohist, L + 3);
+      NSP_HIP(hipMemsetAsync(ro_hist, 0, sizeof(int) * (L + 3), c->stream));
+    }
   }
 
   // row-interleaved copy of Lanczos block ``blk`` (1-based); for d = 1 it is
@@ -240,6 +265,12 @@ struct Lanczos {
     const char* ve = std::getenv("NSP_VERBOSE");
     const bool verbose = ve && (ve[0] == '1' || ve[0] == '2');
     const bool verbose_all = ve && ve[0] == '2';
+    const char* de = std::getenv("NSP_DENSE_EIG");
+    const bool dense_eig = de && de[0] == '1';
+    // diagnostics: NSP_NO_SPEED_STOP=1 runs until the matvec or cycle budget
+    const char* ns = std::getenv("NSP_NO_SPEED_STOP");
+    const bool no_speed_stop = ns && ns[0] == '1';
+    const double norm_t = c->normA1_inf + p.eps * c->maxD;  // bounds ||T|| <= ||B||
     double last_print = now_s();
     for (;;) {
       const double tc0 = now_s();
@@ -259,33 +290,54 @@ struct Lanczos {
         VT* x = slot(ell);
         VT* xp = slot(ell - 1);
         VT* xn = slot(ell + 1);
-        const bool timed = prof.on && (ell % 16 == 0) && prof.used < Prof::kSlots;
-        if (timed) NSP_HIP(hipEventRecord(prof.ev[3 * prof.used], c->stream));
+        const bool timed = prof.on && (ell % 4 == 0) && prof.used < Prof::kSlots;
+        const int slot = prof.used;
+        if (timed) NSP_HIP(hipEventRecord(prof.e(slot, 0), c->stream));
         spmm_block<VT>(c, c->A, d, x, Y);
-        if (timed) NSP_HIP(hipEventRecord(prof.ev[3 * prof.used + 1], c->stream));
+        if (timed) NSP_HIP(hipEventRecord(prof.e(slot, 1), c->stream));
         const int npx = spmmT_step<VT>(c, d, Y, x, xp, gam + (size_t)(ell - 1) * d * d, P, part_xi);
-        if (timed) NSP_HIP(hipEventRecord(prof.ev[3 * prof.used++ + 2], c->stream));
-        const WArgs wa{ell, l0, ldw, u_d, u_ro, nrm_xi, nrm_gam, nrm_theta, nrm_f, W, flags};
+        if (timed) NSP_HIP(hipEventRecord(prof.e(slot, 2), c->stream));
+        const WArgs wa{ell, l0, ldw, u_d, u_ro, nrm_xi, nrm_gam, nrm_theta, nrm_f, W, flags, ro_hist};
         qr_step(ell, ell + 1, true, npx, &wa);
         // partial reorthogonalisation of [Q_ell, Q_ell+1] against Z_{ell-1} when the
         // W-recurrence raised the flag: one CGS pass (reading R5), then Cholesky QR
         const int kz = (ell - 1) * d;
-        ts_project<VT>(c, flags, d, 2, n, Z, ldz, kz, x, xn, H, hpart, true, part_c, rinvc);
+        if (timed) NSP_HIP(hipEventRecord(prof.e(slot, 3), c->stream));
+        ts_project<VT>(c, flags, d, 2, n, Z, ldz, kz, x, xn, H, hpart, true, part_c, rinvc,
+                       timed ? prof.e(slot, 4) : nullptr);
+        if (timed) {
+          NSP_HIP(hipEventRecord(prof.e(slot, 5), c->stream));
+          prof.ell[slot] = ell;
+          prof.kcols[slot] = kz;
+          prof.used++;
+        }
         ts_scale<VT>(c, flags, d, 2, n, x, xn, part_c, rinvc, d > 1 ? zcol(ell) : nullptr, ldz);
         matvecs += d;
       }
       NSP_HIP(hipStreamSynchronize(c->stream));
       const double tc1 = now_s();
       t_lan += tc1 - tc0;
-      prof.collect();
-      // ---- Rayleigh-Ritz on T (Eq. "defT")
-      assemble_t(c, K, d, kk, theta_kept, fmat, xi, gam, T);
-      syevd(c, K, T, evals, c->ework, b_info);
+      if (prof.on) {
+        std::vector<int> hh(L + 3);
+        NSP_HIP(hipMemcpy(hh.data(), ro_hist, sizeof(int) * (L + 3), hipMemcpyDeviceToHost));
+        prof.collect(hh.data(), n, d, (int)sizeof(VT));
+      }
+      // ---- Rayleigh-Ritz on T (Eq. "defT"): the structured solver for d = 1,
+      // dense FP64 rocSOLVER otherwise
+      if (d == 1 && !dense_eig) {
+        eig_restart_d1(c, *eigw, K, kk, norm_t, theta_kept, fmat, xi, gam, evals, T, flags + 4);
+      } else {
+        assemble_t(c, K, d, kk, theta_kept, fmat, xi, gam, T);
+        syevd(c, K, T, evals, c->ework, b_info);
+      }
       NSP_HIP(hipMemcpyAsync(c->pin_d, evals, sizeof(double) * K, hipMemcpyDeviceToHost, c->stream));
       NSP_HIP(hipMemcpyAsync(c->pin_i, flags, sizeof(int) * 8, hipMemcpyDeviceToHost, c->stream));
       NSP_HIP(hipStreamSynchronize(c->stream));
       std::copy(c->pin_d, c->pin_d + K, hev.begin());
       std::copy(c->pin_i, c->pin_i + 8, flags_h);
+      if (flags_h[4] != 0)
+        throw Error(NSP_ERR_HIP, "tridiagonal eigensolver did not converge (info " +
+                                     std::to_string(flags_h[4]) + ")");
       if (flags_h[1]) throw Error(NSP_ERR_BREAKDOWN, "a Lanczos block lost rank (Krylov breakdown)");
       for (double v : hev)
         if (!std::isfinite(v)) throw Error(NSP_ERR_NONFINITE, "non-finite Ritz value");
@@ -298,7 +350,7 @@ struct Lanczos {
         std::fflush(stderr);
         last_print = now_s();
       }
-      stop = speed_rule(hist, d);
+      stop = !no_speed_stop && speed_rule(hist, d);
       const bool budget = matvecs >= p.max_matvec || (p.max_cycles > 0 && st.cycles >= p.max_cycles);
       c->ritz = hev;
       if (stop || budget) {
@@ -332,6 +384,12 @@ struct Lanczos {
       st.t_spmv_a_us = prof.sum_a / prof.samples * 1e3;
       st.t_spmv_at_us = prof.sum_at / prof.samples * 1e3;
       st.spmv_samples = prof.samples;
+      st.ro_tn_ms = prof.tn_ms;
+      st.ro_tn_bytes = prof.tn_bytes;
+      st.ro_nn_ms = prof.nn_ms;
+      st.ro_nn_bytes = prof.nn_bytes;
+      st.ro_samples = prof.samples;
+      st.ro_active = prof.ro_active;
     }
     c->nullity = n_ell;
     c->state = 1;

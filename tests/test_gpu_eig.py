@@ -1,0 +1,65 @@
+"""Structured Ritz eigensolver of the restart matrix (d = 1) vs LAPACK on the dense matrix."""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+
+def _dense(theta, f, alpha, beta):
+    kk, m = len(theta), len(alpha)
+    k = kk + m
+    t = np.zeros((k, k))
+    t[np.arange(kk), np.arange(kk)] = theta
+    t[kk, :kk] = f
+    t[:kk, kk] = f
+    t[np.arange(kk, k), np.arange(kk, k)] = alpha
+    t[np.arange(kk, k - 1), np.arange(kk + 1, k)] = beta
+    t[np.arange(kk + 1, k), np.arange(kk, k - 1)] = beta
+    return t
+
+
+def _case(k, kk, kind, seed):
+    rng = np.random.default_rng(seed)
+    theta = np.sort(rng.random(kk) * 10)
+    f = rng.standard_normal(kk)
+    if kind == "cluster":  # a tight cluster near zero, like the perturbed null space
+        nc = kk // 2
+        theta[:nc] = np.sort(1e-6 * rng.random(nc))
+        f[:nc] *= 1e-9
+    if kind == "deflate":  # exact zeros, tiny couplings and repeated poles
+        f[::3] = 0.0
+        f[1::5] = 1e-17
+        theta[2::4] = theta[1::4][: len(theta[2::4])]
+        theta = np.sort(theta)
+    alpha = rng.random(k - kk) * 10
+    beta = np.abs(rng.standard_normal(k - kk - 1)) + 0.1
+    if kind == "weak":  # nearly decoupled tail
+        beta[0] = 1e-14
+    return theta, f, alpha, beta
+
+
+@pytest.mark.parametrize("k,kk,kind", [
+    (2, 0, "plain"), (3, 1, "plain"), (10, 0, "plain"), (10, 8, "plain"), (64, 32, "plain"),
+    (257, 160, "plain"), (512, 356, "cluster"), (300, 150, "deflate"), (128, 64, "weak"),
+    (512, 256, "plain"),
+])
+def test_ritz_eig_matches_lapack(k, kk, kind):
+    import torch
+    from tests.gpu_util import context
+    from workloads import generators as G
+
+    print(f"[eig] K={k} kk={kk} {kind}", flush=True)
+    c = G.config("er20")
+    ctx, _, _ = context(c, 0.01, d=1, max_dim=64)
+    theta, f, alpha, beta = _case(k, kk, kind, seed=k + kk)
+    t = _dense(theta, f, alpha, beta)
+    ref = np.linalg.eigvalsh(t)
+    dev = lambda a: torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).cuda()  # noqa: E731
+    ev, vec = ctx.ritz_eig(dev(theta), dev(f), dev(alpha), dev(beta))
+    ev, vec = ev.cpu().numpy(), vec.cpu().numpy()
+    nt = np.abs(t).sum(axis=1).max()
+    assert np.all(np.diff(ev) >= 0)
+    assert np.max(np.abs(ev - ref)) <= 1e-13 * nt
+    assert np.linalg.norm(t @ vec - vec * ev[None, :]) <= 1e-12 * nt * np.sqrt(k)
+    assert np.linalg.norm(vec.T @ vec - np.eye(k)) <= 1e-12 * k
+    ctx.close()
