@@ -150,7 +150,7 @@ def kernel_rooflines(st, m, n, nnz, d, esize):
     return rows
 
 
-def spmv_hbm(name, prec, d=1, max_dim=64):
+def spmv_hbm(name, prec, d=1, max_dim=64, reorder=1):
     """SpMV pair inside real Lanczos steps on a matrix far larger than the caches.
 
     One restart cycle (``max_dim`` steps, no refinement) on the named workload;
@@ -166,7 +166,7 @@ def spmv_hbm(name, prec, d=1, max_dim=64):
                   D=torch.from_numpy(G.perturbation_diagonal(c.n, 1)).cuda(),
                   Omega=torch.from_numpy(np.ascontiguousarray(G.gaussian_start_block(c.n, d, 1))).cuda(),
                   eps=1e-3, d=d, max_dim=max_dim, prec=PREC_MIXED if prec == "mixed" else PREC_FP64,
-                  max_cycles=1, refine=0, profile=1)
+                  max_cycles=1, refine=0, profile=1, reorder=reorder)
     st = ctx.lanczos_run(allow_noconv=True)
     ctx.close()
     esize = 4 if prec == "mixed" else 8
@@ -174,6 +174,7 @@ def spmv_hbm(name, prec, d=1, max_dim=64):
     t = st["t_spmv_a_us"] + st["t_spmv_at_us"]
     gbs = (a_b + at_b) / (t * 1e-6) / 1e9
     return {"workload": name, "m": c.m, "n": c.n, "nnz": c.nnz, "d": d, "prec": prec,
+            "order": "locality (BFS)" if reorder else "as generated (random labels)",
             "samples": st["spmv_samples"], "us_A": st["t_spmv_a_us"], "us_AT": st["t_spmv_at_us"],
             "bytes_pair": a_b + at_b, "achieved_gbs": gbs, "frac_hbm": gbs / HBM_PEAK_GBS}
 
@@ -276,7 +277,8 @@ def main():
         line["kernels"] = kr
         line["reorth_active_frac"] = st["ro_active"] / max(1, st["ro_samples"])
     if args.spmv_workload != "none":
-        sp = [spmv_hbm(args.spmv_workload, p) for p in ("fp64", "mixed")]
+        sp = [spmv_hbm(args.spmv_workload, p, reorder=r) for p, r in
+              (("fp64", 1), ("mixed", 1), ("fp64", 0))]
         for r in sp:
             print(f"[bench] spmv {json.dumps(r)}", file=sys.stderr, flush=True)
         line["spmv_hbm"] = sp

@@ -82,6 +82,12 @@ typedef struct {
   int32_t profile;       /* 1: time the SpMV pair and the reorthogonalisation pair
                             with HIP events on the library's stream at every 4th
                             Lanczos step (nsp_stats.t_spmv_*, ro_*)                  */
+  int32_t reorder;       /* 1 (default): store A with rows and columns in a locality
+                            order (breadth-first over the row/column graph, see
+                            nullspace_locality_order) so the SpMV gathers stay in
+                            cache; B is then P B P^T for a permutation P, the same
+                            operator up to renumbering.  Every argument and result
+                            of the API stays in the caller's order.  0: keep it.   */
   uint64_t seed;         /* seed of the built-in Philox4x32-10 draws of D and Omega,
                             used only when the caller passes D or Omega as NULL       */
 } nsp_params;
@@ -200,6 +206,22 @@ nsp_status backward(nsp_ctx* ctx, const double* GsV, int64_t ld, double* grad_va
 
 /* Release everything the context owns.  NULL is accepted. */
 void nullspace_destroy(nsp_ctx* ctx);
+
+/* The locality order nullspace_init uses when params.reorder = 1 (host only,
+ * no GPU needed).  Breadth-first search over the bipartite graph of A's rows
+ * and columns, started from the lowest-numbered unvisited column; columns are
+ * numbered in the order the search reaches them and rows in the order they are
+ * first met, rows without entries last.  Every connected piece of the graph
+ * therefore occupies contiguous ranges of rows and columns.
+ *   rowptr   : host, m + 1 int64 (CSR, rowptr[0] = 0, non-decreasing)
+ *   colind   : host, rowptr[m] int32 in [0, n)
+ *   row_order: host, m int32 out; row_order[r] is the caller's row at position r
+ *   col_order: host, n int32 out; col_order[j] is the caller's column at position j
+ * Errors: NSP_ERR_ARG for NULL pointers, sizes outside [1, 2^31) or an invalid
+ * CSR. */
+nsp_status nullspace_locality_order(int64_t m, int64_t n, const int64_t* rowptr,
+                                    const int32_t* colind, int32_t* row_order,
+                                    int32_t* col_order);
 
 /* Message describing the last error on the calling thread ("" if none). */
 const char* nullspace_last_error(void);

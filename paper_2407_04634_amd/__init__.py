@@ -10,6 +10,7 @@ from ._lib import (  # noqa: F401
     Stats,
     default_params,
     load,
+    locality_order,
     PREC_FP64,
     PREC_MIXED,
 )

@@ -44,6 +44,7 @@ class Params(ctypes.Structure):
         ("max_refine_iter", ctypes.c_int64),
         ("max_cycles", ctypes.c_int32),
         ("profile", ctypes.c_int32),
+        ("reorder", ctypes.c_int32),
         ("seed", ctypes.c_uint64),
     ]
 
@@ -83,7 +84,7 @@ class Stats(ctypes.Structure):
 
 EXPORTS = ["nsp_default_params", "nullspace_init", "apply_op", "lanczos_run", "nullspace_nullity",
            "extract_basis", "nullspace_ritz_values", "nullspace_ritz_eig", "backward",
-           "nullspace_destroy", "nullspace_last_error"]
+           "nullspace_destroy", "nullspace_last_error", "nullspace_locality_order"]
 
 _lib = None
 
@@ -112,8 +113,10 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.nullspace_destroy.restype = None
     lib.nullspace_last_error.argtypes = []
     lib.nullspace_last_error.restype = ctypes.c_char_p
+    lib.nullspace_locality_order.argtypes = [i64, i64, vp, vp, vp, vp]
     for name in ("nullspace_init", "apply_op", "lanczos_run", "nullspace_nullity", "extract_basis",
-                 "nullspace_ritz_values", "nullspace_ritz_eig", "backward"):
+                 "nullspace_ritz_values", "nullspace_ritz_eig", "backward",
+                 "nullspace_locality_order"):
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -133,6 +136,22 @@ def default_params(**overrides) -> Params:
             raise KeyError(k)
         setattr(p, k, v)
     return p
+
+
+def locality_order(rowptr, colind, m: int, n: int):
+    """Host-side locality order of a CSR pattern (numpy int64 rowptr, int32 colind).
+
+    Returns (row_order, col_order): the caller's row / column at each position.
+    """
+    import numpy as np
+
+    rp = np.ascontiguousarray(rowptr, dtype=np.int64)
+    ci = np.ascontiguousarray(colind, dtype=np.int32)
+    ro = np.empty(m, dtype=np.int32)
+    co = np.empty(n, dtype=np.int32)
+    _check(load().nullspace_locality_order(int(m), int(n), rp.ctypes.data, ci.ctypes.data if ci.size else None,
+                                           ro.ctypes.data, co.ctypes.data))
+    return ro, co
 
 
 def _ptr(t):

@@ -59,6 +59,7 @@ void validate_params(const nsp_params* p, int64_t n) {
   NSP_REQUIRE(p->tol_rel_resid >= 0.0 && p->tol_abs_resid >= 0.0 && p->tol_angle >= 0.0,
               "tolerances must be >= 0");
   NSP_REQUIRE(p->max_cycles >= 0, "max_cycles must be >= 0");
+  NSP_REQUIRE(p->reorder == 0 || p->reorder == 1, "reorder must be 0 or 1");
 }
 
 }  // namespace
@@ -81,6 +82,7 @@ void nsp_default_params(nsp_params* p) {
   p->max_refine_iter = 1000000;
   p->max_cycles = 0;
   p->profile = 0;
+  p->reorder = 1;
   p->seed = 20240704ull;
 }
 
@@ -112,13 +114,11 @@ nsp_status nullspace_init(nsp_ctx** out, int64_t m, int64_t n, int64_t nnz, cons
     NSP_HIP(hipStreamSynchronize(c->user_stream));
     NSP_BLAS(rocblas_create_handle(&c->blas));
     NSP_BLAS(rocblas_set_stream(c->blas, c->stream));
-    c->A.colind = colind;
-    c->A.val = vals;
     // per-block partials of the step reductions (stream-ordered reuse)
     c->part_xi.alloc(sizeof(double) * nsp::kRedBlocks * nsp::kMaxD * nsp::kMaxD);
     c->part_g.alloc(sizeof(double) * nsp::kRedBlocks * nsp::kMaxD * nsp::kMaxD);
     c->part_g2.alloc(sizeof(double) * nsp::kRedBlocks * nsp::kMaxD * nsp::kMaxD);
-    nsp::build_transpose(c, rowptr);
+    nsp::prepare_matrix(c, rowptr, colind, vals);
     nsp::init_random(c, D, Omega);
     nsp::matrix_norms(c);
     NSP_HIP(hipStreamSynchronize(c->stream));
@@ -174,9 +174,8 @@ nsp_status extract_basis(nsp_ctx* ctx, double* V, int64_t ldv) {
     if (ctx->nullity == 0) return;
     NSP_REQUIRE(V != nullptr && ldv >= ctx->n, "V must be non-NULL with ldv >= n");
     enter(ctx);
-    NSP_HIP(hipMemcpy2DAsync(V, sizeof(double) * ldv, ctx->V.p, sizeof(double) * ctx->n,
-                             sizeof(double) * ctx->n, ctx->nullity, hipMemcpyDeviceToDevice,
-                             ctx->stream));
+    nsp::scatter_rows(ctx, ctx->n, ctx->nullity, ctx->colperm.as<int32_t>(), ctx->V.as<double>(),
+                      ctx->n, V, ldv);
     NSP_HIP(hipStreamSynchronize(ctx->stream));
   });
 }
@@ -271,5 +270,21 @@ void nullspace_destroy(nsp_ctx* ctx) {
 }
 
 const char* nullspace_last_error(void) { return g_last_error.c_str(); }
+
+nsp_status nullspace_locality_order(int64_t m, int64_t n, const int64_t* rowptr,
+                                    const int32_t* colind, int32_t* row_order,
+                                    int32_t* col_order) {
+  return guarded([&] {
+    NSP_REQUIRE(m >= 1 && n >= 1 && m < 2147483647LL && n < 2147483647LL,
+                "m and n must be in [1, 2^31)");
+    NSP_REQUIRE(rowptr && row_order && col_order, "arguments must not be NULL");
+    NSP_REQUIRE(rowptr[0] == 0 && rowptr[m] >= 0 && rowptr[m] < 2147483647LL,
+                "rowptr[0] must be 0 and nnz < 2^31");
+    NSP_REQUIRE(rowptr[m] == 0 || colind != nullptr, "colind must not be NULL");
+    for (int64_t i = 0; i < m; ++i) NSP_REQUIRE(rowptr[i + 1] >= rowptr[i], "rowptr must be non-decreasing");
+    for (int64_t p = 0; p < rowptr[m]; ++p) NSP_REQUIRE(colind[p] >= 0 && colind[p] < n, "colind out of range");
+    nsp::locality_order(m, n, rowptr, colind, row_order, col_order);
+  });
+}
 
 }  // extern "C"

@@ -71,6 +71,7 @@ struct DBuf {
 
 constexpr int kMaxD = 8;            // largest supported block size
 constexpr int kRedBlocks = 512;     // grid cap of kernels that write per-block partials
+constexpr int kWideBlocks = 1024;   // grid cap of the many-column SpMM (its partials: x k)
 constexpr int kThreads = 256;       // threads per block of streaming kernels
 
 // ---------------------------------------------------------------------------
@@ -122,9 +123,14 @@ struct nsp_ctx {
   double* pin_d = nullptr;            // = pind.p, at least max_dim + 16 doubles
   int* pin_i = nullptr;               // = pini.p, at least 64 ints
 
-  // A (caller's colind/vals; own int32 row offsets) and its stored transpose
+  // A (own copy, int32 row offsets, see prepare_matrix) and its stored transpose
   nsp::Csr A, AT;
   nsp::DBuf rowptr32, rowptrT, colindT, valsT, permT, vals32, valsT32;
+  // the library's own copy of A in the locality order (or the caller's order)
+  nsp::DBuf colindA, valsA;
+  nsp::DBuf permA;          // position in the stored A -> position in the caller's arrays
+  nsp::DBuf colperm;        // stored column (unknown) i -> caller's column colperm[i]
+  bool reordered = false;
   double normA_fro = 0.0;
   double normA1_inf = 0.0;  // ||A||_1 * ||A||_inf
   double maxD = 1.0;        // max of the perturbation diagonal
@@ -157,7 +163,21 @@ struct nsp_ctx {
 namespace nsp {
 
 // launchers implemented in kernels_*.hip -----------------------------------
-void build_transpose(nsp_ctx* c, const int64_t* rowptr64);
+void prepare_matrix(nsp_ctx* c, const int64_t* rowptr64, const int32_t* colind, const double* vals);
+// Locality order of A (host arrays): breadth-first search over the bipartite
+// row/column graph; row_order[r] / col_order[j] give the caller's row / column
+// placed at position r / j.  Connected pieces come out contiguous.
+void locality_order(int64_t m, int64_t n, const int64_t* rowptr, const int32_t* colind,
+                    int32_t* row_order, int32_t* col_order);
+// dst(i, j) = src(idx[i], j) (gather) or dst(idx[i], j) = src(i, j) (scatter),
+// column-major FP64; idx == nullptr is the identity
+void gather_rows(nsp_ctx* c, int64_t n, int ncols, const int32_t* idx, const double* src,
+                 int64_t lds, double* dst, int64_t ldd);
+void scatter_rows(nsp_ctx* c, int64_t n, int ncols, const int32_t* idx, const double* src,
+                  int64_t lds, double* dst, int64_t ldd);
+// dst[permA[p]] = src[p] over the nonzeros (results per stored nonzero back to
+// the caller's order)
+void scatter_vals(nsp_ctx* c, const double* src, double* dst);
 void init_random(nsp_ctx* c, const double* D, const double* Omega);
 double matrix_norms(nsp_ctx* c);
 

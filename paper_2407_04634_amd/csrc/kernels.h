@@ -12,7 +12,12 @@ void spmm_block(nsp_ctx* c, const Csr& a, int d, const VT* x, VT* y);
 template <typename VT>
 int spmmT_step(nsp_ctx* c, int d, const VT* y, const VT* x, const VT* xp, const double* gprev,
                VT* out, double* part_xi);
-void spmm_wide(nsp_ctx* c, const Csr& a, int k, const double* x, double* y);
+// Y = A X for row-major blocks of k columns; with ``part`` (kWideBlocks x k
+// doubles) it also leaves per-block column sums of Y^2 there and returns the
+// number of blocks for reduce_parts.
+int spmm_wide(nsp_ctx* c, const Csr& a, int k, const double* x, double* y, double* part = nullptr);
+// out[v] = sum_b part[b * nv + v] (fixed order)
+void reduce_parts(nsp_ctx* c, int nparts, int nv, const double* part, double* out);
 void sddmm(nsp_ctx* c, int k, const double* u, const double* v, double* grad);
 void colmajor_to_rows(nsp_ctx* c, int64_t rows, int k, const double* src, int64_t ld, double* dst);
 void rows_to_colmajor(nsp_ctx* c, int64_t rows, int k, const double* src, double* dst, int64_t ld);

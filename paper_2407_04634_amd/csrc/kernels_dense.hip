@@ -369,9 +369,31 @@ struct CPair {
 };
 
 template <int NC> struct TsShape {
-  static constexpr int JW = NC >= 8 ? 1 : (NC >= 4 ? 2 : 4);  // basis columns per wave
-  static constexpr int JB = 4 * JW;                            // basis columns per block
+  static constexpr int JW = NC >= 16 ? 1 : (NC >= 8 ? 2 : (NC >= 4 ? 4 : 8));  // basis columns per wave
+  static constexpr int JB = 4 * JW;                                            // basis columns per block
 };
+
+// Rows one lane loads at once from a basis column: 16 bytes per load.
+template <typename VT> struct RowVec;
+template <> struct RowVec<double> { static constexpr int R = 2; using T = double2; };
+template <> struct RowVec<float> { static constexpr int R = 4; using T = float4; };
+
+template <typename VT>
+__device__ __forceinline__ void load_rows(const VT* __restrict__ p, int64_t r, int64_t n,
+                                          double (&v)[RowVec<VT>::R]) {
+  constexpr int R = RowVec<VT>::R;
+  if (r + R <= n) {
+    const typename RowVec<VT>::T t = *reinterpret_cast<const typename RowVec<VT>::T*>(p + r);
+    if constexpr (R == 2) {
+      v[0] = t.x; v[1] = t.y;
+    } else {
+      v[0] = t.x; v[1] = t.y; v[2] = t.z; v[3] = t.w;
+    }
+  } else {
+#pragma unroll
+    for (int i = 0; i < R; ++i) v[i] = r + i < n ? (double)p[r + i] : 0.0;
+  }
+}
 
 // grid (row chunks, column groups); wave w of a block owns JW columns, lanes stride rows
 template <typename VT, int DA, int NA>
@@ -391,19 +413,30 @@ __global__ __launch_bounds__(kThreads) void k_ts_tn(const int* cond, int64_t n, 
   for (int q = 0; q < JW; ++q)
 #pragma unroll
     for (int c = 0; c < NC; ++c) acc[q][c] = 0.0;
+  // lanes take RV consecutive rows each (one 16-byte load per basis column);
+  // chunks start at multiples of 64 * RV rows, so the vector loads are aligned
+  constexpr int RV = RowVec<VT>::R;
   if (jn > 0) {
-    for (int64_t r = r0 + lane; r < r1; r += kWave) {
-      double cv[NC];
+    for (int64_t r = r0 + (int64_t)lane * RV; r < r1; r += kWave * RV) {
+      double cv[RV][NC];
 #pragma unroll
-      for (int c = 0; c < NC; ++c) cv[c] = (double)cc.get(r, c);
+      for (int i = 0; i < RV; ++i)
+#pragma unroll
+        for (int c = 0; c < NC; ++c) cv[i][c] = r + i < r1 ? (double)cc.get(r + i, c) : 0.0;
+      double zv[JW][RV];
 #pragma unroll
       for (int q = 0; q < JW; ++q) {
-        if (q < jn) {
-          const double zv = (double)z[r + (int64_t)(j0 + q) * ldz];
+        if (q < jn) load_rows<VT>(z + (int64_t)(j0 + q) * ldz, r, r1, zv[q]);
+        else
 #pragma unroll
-          for (int c = 0; c < NC; ++c) acc[q][c] = fma(zv, cv[c], acc[q][c]);
-        }
+          for (int i = 0; i < RV; ++i) zv[q][i] = 0.0;
       }
+#pragma unroll
+      for (int q = 0; q < JW; ++q)
+#pragma unroll
+        for (int i = 0; i < RV; ++i)
+#pragma unroll
+          for (int c = 0; c < NC; ++c) acc[q][c] = fma(zv[q][i], cv[i][c], acc[q][c]);
     }
   }
 #pragma unroll
@@ -494,6 +527,101 @@ __global__ __launch_bounds__(kThreads) void k_ts_nn(const int* cond, int64_t n,
     }
   }
 }
+
+// C -= Z H for NC <= 4.  A block owns 64 * RV consecutive rows (RV rows per
+// lane, one 16-byte load per basis column); its 8 waves split the k columns,
+// unrolled by 4 so every wave keeps several loads in flight, and combine the
+// partial sums in LDS.  With GRAM it also writes the block's partial Gram
+// matrix of the updated rows.
+template <typename VT, int DA, int NA, bool GRAM>
+__global__ __launch_bounds__(512) void k_ts_nn_v(const int* cond, int64_t n,
+                                                 const VT* __restrict__ z, int64_t ldz, int k,
+                                                 const double* __restrict__ h,
+                                                 CPair<VT, DA, NA> cc,
+                                                 double* __restrict__ part_c) {
+  constexpr int NC = DA * NA;
+  constexpr int RV = RowVec<VT>::R;
+  constexpr int NW = 8;
+  constexpr int TR = kWave * RV;  // rows per block
+  static_assert(NC <= 4, "wide C uses k_ts_nn");
+  if (cond && *cond == 0) return;
+  __shared__ double red[NW][NC][TR];
+  const int lane = threadIdx.x % kWave, wid = threadIdx.x / kWave;
+  const int64_t rb = (int64_t)blockIdx.x * TR;
+  const int64_t r = rb + (int64_t)lane * RV;
+  const int per = (k + NW - 1) / NW;
+  const int jb = min(k, wid * per), je = min(k, jb + per);
+  double acc[RV][NC];
+#pragma unroll
+  for (int i = 0; i < RV; ++i)
+#pragma unroll
+    for (int c = 0; c < NC; ++c) acc[i][c] = 0.0;
+  if (r < n) {
+    int j = jb;
+    for (; j + 4 <= je; j += 4) {
+      double zv[4][RV];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) load_rows<VT>(z + (int64_t)(j + u) * ldz, r, n, zv[u]);
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+#pragma unroll
+        for (int c = 0; c < NC; ++c) {
+          const double hv = h[(int64_t)(j + u) * NC + c];
+#pragma unroll
+          for (int i = 0; i < RV; ++i) acc[i][c] = fma(zv[u][i], hv, acc[i][c]);
+        }
+    }
+    for (; j < je; ++j) {
+      double zv[RV];
+      load_rows<VT>(z + (int64_t)j * ldz, r, n, zv);
+#pragma unroll
+      for (int c = 0; c < NC; ++c) {
+        const double hv = h[(int64_t)j * NC + c];
+#pragma unroll
+        for (int i = 0; i < RV; ++i) acc[i][c] = fma(zv[i], hv, acc[i][c]);
+      }
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < RV; ++i)
+#pragma unroll
+    for (int c = 0; c < NC; ++c) red[wid][c][lane * RV + i] = acc[i][c];
+  __syncthreads();
+  // thread t < TR finishes row rb + t
+  constexpr int NG = GRAM ? NC * NC : 1;
+  double g[NG];
+#pragma unroll
+  for (int i = 0; i < NG; ++i) g[i] = 0.0;
+  const int t = threadIdx.x;
+  if (t < TR && rb + t < n) {
+    const int64_t row = rb + t;
+    double o[NC];
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+      double sum = 0.0;
+#pragma unroll
+      for (int w = 0; w < NW; ++w) sum += red[w][c][t];
+      o[c] = (double)VT((double)cc.get(row, c) - sum);
+      cc.set(row, c, VT(o[c]));
+    }
+    if constexpr (GRAM) {
+#pragma unroll
+      for (int a = 0; a < NC; ++a)
+#pragma unroll
+        for (int b = 0; b < NC; ++b) g[a + b * NC] += o[a] * o[b];
+    }
+  }
+  if constexpr (GRAM) {
+    __syncthreads();
+    block_sum<NG>(g, &red[0][0][0]);  // reuses the LDS: needs NW * NG doubles
+    if (threadIdx.x == 0)
+#pragma unroll
+      for (int i = 0; i < NG; ++i) part_c[(size_t)blockIdx.x * NG + i] = g[i];
+  }
+}
+
+// Rows per block of the C -= Z H kernel (and so the number of Gram partials).
+template <typename VT, int NC> constexpr int ts_nn_rows() { return NC <= 4 ? kWave * RowVec<VT>::R : kWave; }
 
 // One block: Gram of C from the partials, Cholesky; writes R^{-1} then R (NC x NC each).
 template <int NC>
@@ -669,12 +797,24 @@ __global__ __launch_bounds__(kThreads) void k_coldots_partial(int64_t rows, int 
   }
 }
 
-__global__ void k_sum_parts(int nparts, int k, const double* __restrict__ part, double* __restrict__ out) {
-  const int c = blockIdx.x * blockDim.x + threadIdx.x;
-  if (c >= k) return;
+// out[v] = sum_b part[b * nv + v]: 8 values x 32 partial groups per block,
+// combined in a fixed order
+__global__ __launch_bounds__(256) void k_reduce_parts(int nparts, int nv,
+                                                      const double* __restrict__ part,
+                                                      double* __restrict__ out) {
+  __shared__ double sm[256];
+  const int vl = threadIdx.x % 8, g = threadIdx.x / 8;
+  const int v = blockIdx.x * 8 + vl;
   double s = 0.0;
-  for (int b = 0; b < nparts; ++b) s += part[(int64_t)b * k + c];
-  out[c] = s;
+  if (v < nv)
+    for (int b = g; b < nparts; b += 32) s += part[(size_t)b * nv + v];
+  sm[threadIdx.x] = s;
+  __syncthreads();
+  if (threadIdx.x < 8 && v < nv) {
+    double r = 0.0;
+    for (int q = 0; q < 32; ++q) r += sm[q * 8 + vl];
+    out[v] = r;
+  }
 }
 
 // CGLS update: alpha_c = gamma_c / qq_c (0 for inactive columns)
@@ -816,13 +956,15 @@ void w_reset(nsp_ctx* c, int col0, int ncols, double u_d, double* w, int ldw) {
 
 // Rows per chunk of the TN kernel: aim for ~1024 blocks in total with chunks of
 // at least 1024 rows (so each lane accumulates >= 16 rows before the wave sum).
+// Row chunk of the H = Z^T C kernel: about 2048 blocks over (chunks x column
+// groups), at least 1024 rows, a multiple of 256 rows (aligned vector loads).
 int64_t ts_chunk_rows(int64_t n, int k, int nc) {
-  const int jb = nc >= 8 ? 4 : (nc >= 4 ? 8 : 16);
+  const int jb = nc >= 16 ? 4 : (nc >= 8 ? 8 : (nc >= 4 ? 16 : 32));
   const int64_t col_groups = std::max<int64_t>(1, (k + jb - 1) / jb);
-  const int64_t chunks = std::max<int64_t>(1, 1024 / col_groups);
+  const int64_t chunks = std::max<int64_t>(1, 2048 / col_groups);
   int64_t rows = (n + chunks - 1) / chunks;
   rows = std::max<int64_t>(rows, 1024);
-  return (rows + 63) / 64 * 64;
+  return (rows + 255) / 256 * 256;
 }
 
 template <typename VT, int DA, int NA>
@@ -831,7 +973,8 @@ static void ts_proj_t(nsp_ctx* c, const int* cond, int64_t n, const VT* z, int64
                       double* rinv, hipEvent_t ev_mid) {
   constexpr int NC = DA * NA;
   CPair<VT, DA, NA> cc{a0, a1};
-  const unsigned nnblocks = (unsigned)((n + kWave - 1) / kWave);
+  constexpr int TR = ts_nn_rows<VT, NC>();
+  const unsigned nnblocks = (unsigned)((n + TR - 1) / TR);
   if (k > 0) {
     const int64_t chunk = ts_chunk_rows(n, k, NC);
     const unsigned nchunks = (unsigned)((n + chunk - 1) / chunk);
@@ -842,13 +985,20 @@ static void ts_proj_t(nsp_ctx* c, const int* cond, int64_t n, const VT* z, int64
                                                                     hpart, h);
   }
   if (ev_mid) NSP_HIP(hipEventRecord(ev_mid, c->stream));
-  if (gram) {
-    k_ts_nn<VT, DA, NA, true><<<nnblocks, kThreads, 0, c->stream>>>(cond, n, z, ldz, k, h, cc, part_c);
-    if (NC > 4)
+  if constexpr (NC <= 4) {
+    if (gram)
+      k_ts_nn_v<VT, DA, NA, true><<<nnblocks, 512, 0, c->stream>>>(cond, n, z, ldz, k, h, cc, part_c);
+    else if (k > 0)
+      k_ts_nn_v<VT, DA, NA, false><<<nnblocks, 512, 0, c->stream>>>(cond, n, z, ldz, k, h, cc,
+                                                                    nullptr);
+  } else {
+    if (gram) {
+      k_ts_nn<VT, DA, NA, true><<<nnblocks, kThreads, 0, c->stream>>>(cond, n, z, ldz, k, h, cc, part_c);
       k_ts_gramfin<NC><<<1, 256, 0, c->stream>>>(cond, (int)nnblocks, part_c, rinv, c->flags.as<int>());
-  } else if (k > 0) {
-    k_ts_nn<VT, DA, NA, false><<<nnblocks, kThreads, 0, c->stream>>>(cond, n, z, ldz, k, h, cc,
-                                                                     nullptr);
+    } else if (k > 0) {
+      k_ts_nn<VT, DA, NA, false><<<nnblocks, kThreads, 0, c->stream>>>(cond, n, z, ldz, k, h, cc,
+                                                                       nullptr);
+    }
   }
   NSP_HIP(hipGetLastError());
 }
@@ -860,7 +1010,8 @@ static void ts_scale_t(nsp_ctx* c, const int* cond, int64_t n, VT* a0, VT* a1, c
                        double* rinv, VT* z0, int64_t ldz) {
   constexpr int NC = DA * NA;
   CPair<VT, DA, NA> cc{a0, a1};
-  const int nparts = (int)((n + kWave - 1) / kWave);
+  constexpr int TR = ts_nn_rows<VT, NC>();
+  const int nparts = (int)((n + TR - 1) / TR);
   const unsigned grid = cap_grid(n, kThreads, 2048);
   if constexpr (NC <= 4)
     k_ts_scale<VT, DA, NA, true><<<grid, kThreads, 0, c->stream>>>(cond, n, cc, part_c, nparts, rinv,
@@ -958,13 +1109,18 @@ void coldots(nsp_ctx* c, int64_t rows, int k, const double* a, const double* b, 
   const unsigned nb = (unsigned)((rows + rpb - 1) / rpb);
   const int thr = k >= 256 ? 256 : std::max(64, (k + 63) / 64 * 64);
   k_coldots_partial<<<nb, thr, 0, c->stream>>>(rows, k, a, b, part, rpb);
-  k_sum_parts<<<nblk(k, 256), 256, 0, c->stream>>>((int)nb, k, part, out);
+  reduce_parts(c, (int)nb, k, part, out);
+}
+
+void reduce_parts(nsp_ctx* c, int nparts, int nv, const double* part, double* out) {
+  if (nv <= 0) return;
+  k_reduce_parts<<<nblk(nv, 8), 256, 0, c->stream>>>(nparts, nv, part, out);
   NSP_HIP(hipGetLastError());
 }
 
 int64_t coldots_parts(int64_t rows) {
   const int64_t rpb = std::max<int64_t>(64, (rows + 1023) / 1024);
-  return (rows + rpb - 1) / rpb;
+  return std::max<int64_t>((rows + rpb - 1) / rpb, kWideBlocks);
 }
 
 void cgls_xs(nsp_ctx* c, int64_t n, int64_t m, int k, const double* gamma, const double* qq,

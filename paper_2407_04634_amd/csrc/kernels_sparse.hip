@@ -128,26 +128,80 @@ __global__ __launch_bounds__(kThreads) void k_spmmT_step(
   }
 }
 
-// ---------------------------------------------------------------------------
-// wide SpMM: y(rows x k) = A x(n x k), row-major, one wavefront per row,
-// lanes over the k columns.  Used by the refinement and the backward pass.
-// ---------------------------------------------------------------------------
+// Y (rows x k, row-major) = A X (X: cols x k, row-major), many right-hand
+// sides.  One wavefront per row, grid-stride over rows; lane l owns columns
+// 4l .. 4l+3 of each 256-column panel, read as two 16-byte loads when k is even.
+// With SQ every block also writes partial column sums of Y^2, part[block * k + c],
+// summed in block order by reduce_parts.
+template <bool VEC, bool SQ>
 __global__ __launch_bounds__(kThreads) void k_spmm_wide(int64_t nrows, int k,
                                                         const int32_t* __restrict__ rp,
                                                         const int32_t* __restrict__ ci,
                                                         const double* __restrict__ av,
                                                         const double* __restrict__ x,
-                                                        double* __restrict__ y) {
-  const int64_t row = (int64_t)blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave;
-  const int lane = threadIdx.x % kWave;
-  if (row >= nrows) return;
-  const int beg = rp[row], end = rp[row + 1];
-  for (int c0 = 0; c0 < k; c0 += kWave) {
-    const int c = c0 + lane;
-    double acc = 0.0;
-    if (c < k) {
-      for (int p = beg; p < end; ++p) acc = fma(av[p], x[(int64_t)ci[p] * k + c], acc);
-      y[row * k + c] = acc;
+                                                        double* __restrict__ y,
+                                                        double* __restrict__ part) {
+  constexpr int CPL = 4;
+  constexpr int NWB = kThreads / kWave;
+  __shared__ double red[SQ ? NWB : 1][SQ ? kWave * CPL : 1];
+  const int lane = threadIdx.x % kWave, wid = threadIdx.x / kWave;
+  const int64_t gw = (int64_t)blockIdx.x * NWB + wid;
+  const int64_t nw = (int64_t)gridDim.x * NWB;
+  for (int c0 = 0; c0 < k; c0 += kWave * CPL) {
+    const int cb = c0 + lane * CPL;
+    const bool full = cb + CPL <= k;
+    double sq[CPL];
+#pragma unroll
+    for (int t = 0; t < CPL; ++t) sq[t] = 0.0;
+    for (int64_t row = gw; row < nrows; row += nw) {
+      const int beg = rp[row], end = rp[row + 1];
+      double acc[CPL];
+#pragma unroll
+      for (int t = 0; t < CPL; ++t) acc[t] = 0.0;
+      if (cb < k) {
+        for (int p = beg; p < end; ++p) {
+          const double a = av[p];
+          const double* xr = x + (int64_t)ci[p] * k + cb;
+          if (VEC && full) {
+            const double2 u = *reinterpret_cast<const double2*>(xr);
+            const double2 v = *reinterpret_cast<const double2*>(xr + 2);
+            acc[0] = fma(a, u.x, acc[0]);
+            acc[1] = fma(a, u.y, acc[1]);
+            acc[2] = fma(a, v.x, acc[2]);
+            acc[3] = fma(a, v.y, acc[3]);
+          } else {
+#pragma unroll
+            for (int t = 0; t < CPL; ++t)
+              if (cb + t < k) acc[t] = fma(a, xr[t], acc[t]);
+          }
+        }
+        double* yr = y + row * k + cb;
+        if (VEC && full) {
+          *reinterpret_cast<double2*>(yr) = make_double2(acc[0], acc[1]);
+          *reinterpret_cast<double2*>(yr + 2) = make_double2(acc[2], acc[3]);
+        } else {
+#pragma unroll
+          for (int t = 0; t < CPL; ++t)
+            if (cb + t < k) yr[t] = acc[t];
+        }
+        if constexpr (SQ) {
+#pragma unroll
+          for (int t = 0; t < CPL; ++t) sq[t] = fma(acc[t], acc[t], sq[t]);
+        }
+      }
+    }
+    if constexpr (SQ) {
+#pragma unroll
+      for (int t = 0; t < CPL; ++t) red[wid][lane * CPL + t] = sq[t];
+      __syncthreads();
+      const int j = threadIdx.x;  // kThreads == kWave * CPL columns of the panel
+      if (c0 + j < k) {
+        double s = 0.0;
+#pragma unroll
+        for (int w = 0; w < NWB; ++w) s += red[w][j];
+        part[(int64_t)blockIdx.x * k + c0 + j] = s;
+      }
+      __syncthreads();
     }
   }
 }
@@ -351,12 +405,20 @@ template int spmmT_step<double>(nsp_ctx*, int, const double*, const double*, con
 template int spmmT_step<float>(nsp_ctx*, int, const float*, const float*, const float*,
                                const double*, float*, double*);
 
-void spmm_wide(nsp_ctx* c, const Csr& a, int k, const double* x, double* y) {
-  if (a.rows == 0 || k == 0) return;
-  const int rows_per_block = kThreads / kWave;
-  k_spmm_wide<<<nblocks(a.rows, rows_per_block), kThreads, 0, c->stream>>>(a.rows, k, a.rowptr,
-                                                                            a.colind, a.val, x, y);
+int spmm_wide(nsp_ctx* c, const Csr& a, int k, const double* x, double* y, double* part) {
+  if (a.rows == 0 || k == 0) return 0;
+  static_assert(kThreads == 4 * kWave, "one 256-column panel per block");
+  const int grid = (int)std::min<int64_t>(nblocks(a.rows, kThreads / kWave), kWideBlocks);
+  const bool vec = k % 2 == 0;
+#define NSP_W(V, S) k_spmm_wide<V, S><<<grid, kThreads, 0, c->stream>>>(a.rows, k, a.rowptr, a.colind, a.val, x, y, part)
+  if (part) {
+    if (vec) NSP_W(true, true); else NSP_W(false, true);
+  } else {
+    if (vec) NSP_W(true, false); else NSP_W(false, false);
+  }
+#undef NSP_W
   NSP_HIP(hipGetLastError());
+  return grid;
 }
 
 void sddmm(nsp_ctx* c, int k, const double* u, const double* v, double* grad) {
@@ -388,48 +450,129 @@ static int choose_lpr(int64_t rows, int64_t nnz) {
   return l;
 }
 
-// Stored transpose: counting sort of A's entries by column on the host (once,
-// at init; the only place host work touches the matrix), then the values are
-// gathered on the device through the permutation.
-void build_transpose(nsp_ctx* c, const int64_t* rowptr64) {
+void locality_order(int64_t m, int64_t n, const int64_t* rp, const int32_t* ci,
+                    int32_t* row_order, int32_t* col_order) {
+  const int64_t nnz = rp[m];
+  // column -> rows lists (pattern of A^T) by a counting sort
+  std::vector<int64_t> cp(n + 1, 0);
+  std::vector<int32_t> cr(std::max<int64_t>(nnz, 1));
+  for (int64_t p = 0; p < nnz; ++p) cp[ci[p] + 1]++;
+  for (int64_t j = 0; j < n; ++j) cp[j + 1] += cp[j];
+  {
+    std::vector<int64_t> next(cp.begin(), cp.end() - 1);
+    for (int64_t i = 0; i < m; ++i)
+      for (int64_t p = rp[i]; p < rp[i + 1]; ++p) cr[next[ci[p]]++] = (int32_t)i;
+  }
+  std::vector<uint8_t> rseen(m, 0), cseen(n, 0);
+  int64_t nr = 0, nc = 0;
+  // col_order doubles as the queue of the search; each start column begins a
+  // new connected piece once the previous piece is exhausted
+  for (int64_t s = 0; s < n; ++s) {
+    if (cseen[s]) continue;
+    cseen[s] = 1;
+    col_order[nc++] = (int32_t)s;
+    for (int64_t h = nc - 1; h < nc; ++h) {
+      const int32_t j = col_order[h];
+      for (int64_t q = cp[j]; q < cp[j + 1]; ++q) {
+        const int32_t i = cr[q];
+        if (rseen[i]) continue;
+        rseen[i] = 1;
+        row_order[nr++] = i;
+        for (int64_t p = rp[i]; p < rp[i + 1]; ++p) {
+          const int32_t j2 = ci[p];
+          if (!cseen[j2]) {
+            cseen[j2] = 1;
+            col_order[nc++] = j2;
+          }
+        }
+      }
+    }
+  }
+  for (int64_t i = 0; i < m; ++i)  // rows without entries go last
+    if (!rseen[i]) row_order[nr++] = (int32_t)i;
+}
+
+// The library's copy of A: rows and columns in the locality order (or the
+// caller's order when reordering is off), columns sorted within a row, then
+// the stored transpose by a counting sort by column.  Host work happens only
+// here, once, at init; values are permuted on the device.
+void prepare_matrix(nsp_ctx* c, const int64_t* rowptr64, const int32_t* colind, const double* vals) {
   const int64_t m = c->m, n = c->n, nnz = c->nnz;
   std::vector<int64_t> hrp(m + 1);
-  std::vector<int32_t> hci(nnz);
+  std::vector<int32_t> hci(std::max<int64_t>(nnz, 1));
   NSP_HIP(hipMemcpy(hrp.data(), rowptr64, sizeof(int64_t) * (m + 1), hipMemcpyDeviceToHost));
-  if (nnz) NSP_HIP(hipMemcpy(hci.data(), c->A.colind, sizeof(int32_t) * nnz, hipMemcpyDeviceToHost));
+  if (nnz) NSP_HIP(hipMemcpy(hci.data(), colind, sizeof(int32_t) * nnz, hipMemcpyDeviceToHost));
   NSP_REQUIRE(hrp[0] == 0 && hrp[m] == nnz, "rowptr[0] must be 0 and rowptr[m] must equal nnz");
   for (int64_t i = 0; i < m; ++i) NSP_REQUIRE(hrp[i + 1] >= hrp[i], "rowptr must be non-decreasing");
-  std::vector<int32_t> rp32(m + 1), rpt(n + 1, 0), cit(nnz), perm(nnz);
-  for (int64_t i = 0; i <= m; ++i) rp32[i] = (int32_t)hrp[i];
-  for (int64_t p = 0; p < nnz; ++p) {
-    const int32_t j = hci[p];
-    NSP_REQUIRE(j >= 0 && j < n, "colind out of range");
-    rpt[j + 1]++;
+  for (int64_t p = 0; p < nnz; ++p) NSP_REQUIRE(hci[p] >= 0 && hci[p] < n, "colind out of range");
+
+  const bool re = c->prm.reorder != 0;
+  std::vector<int32_t> rord(m), cord(n), cinv(n);
+  if (re) {
+    locality_order(m, n, hrp.data(), hci.data(), rord.data(), cord.data());
+  } else {
+    std::iota(rord.begin(), rord.end(), 0);
+    std::iota(cord.begin(), cord.end(), 0);
   }
-  for (int64_t j = 0; j < n; ++j) rpt[j + 1] += rpt[j];
-  std::vector<int32_t> next(rpt.begin(), rpt.end() - 1);
-  for (int64_t i = 0; i < m; ++i)
-    for (int64_t p = hrp[i]; p < hrp[i + 1]; ++p) {
-      const int32_t q = next[hci[p]]++;
-      cit[q] = (int32_t)i;
-      perm[q] = (int32_t)p;
+  for (int64_t j = 0; j < n; ++j) cinv[cord[j]] = (int32_t)j;
+
+  std::vector<int32_t> rp32(m + 1), ci2(std::max<int64_t>(nnz, 1)), pa(std::max<int64_t>(nnz, 1));
+  std::vector<std::pair<int32_t, int32_t>> row;
+  rp32[0] = 0;
+  for (int64_t r = 0; r < m; ++r) {
+    const int64_t i = rord[r];
+    const int64_t b = hrp[i], e = hrp[i + 1];
+    row.clear();
+    for (int64_t p = b; p < e; ++p) row.emplace_back(cinv[hci[p]], (int32_t)p);
+    if (re) std::sort(row.begin(), row.end());
+    const int64_t o = rp32[r];
+    for (size_t t = 0; t < row.size(); ++t) {
+      ci2[o + t] = row[t].first;
+      pa[o + t] = row[t].second;
     }
+    rp32[r + 1] = (int32_t)(o + (int64_t)row.size());
+  }
+  std::vector<int32_t> rpt(n + 1, 0), cit(std::max<int64_t>(nnz, 1)), pt(std::max<int64_t>(nnz, 1));
+  for (int64_t p = 0; p < nnz; ++p) rpt[ci2[p] + 1]++;
+  for (int64_t j = 0; j < n; ++j) rpt[j + 1] += rpt[j];
+  {
+    std::vector<int32_t> next(rpt.begin(), rpt.end() - 1);
+    for (int64_t r = 0; r < m; ++r)
+      for (int64_t p = rp32[r]; p < rp32[r + 1]; ++p) {
+        const int32_t q = next[ci2[p]]++;
+        cit[q] = (int32_t)r;
+        pt[q] = (int32_t)p;
+      }
+  }
+  const size_t nz = (size_t)std::max<int64_t>(nnz, 1);
   c->rowptr32.alloc(sizeof(int32_t) * (m + 1));
+  c->colindA.alloc(sizeof(int32_t) * nz);
+  c->permA.alloc(sizeof(int32_t) * nz);
+  c->valsA.alloc(sizeof(double) * nz);
+  c->colperm.alloc(sizeof(int32_t) * n);
   c->rowptrT.alloc(sizeof(int32_t) * (n + 1));
-  c->colindT.alloc(sizeof(int32_t) * std::max<int64_t>(nnz, 1));
-  c->permT.alloc(sizeof(int32_t) * std::max<int64_t>(nnz, 1));
-  c->valsT.alloc(sizeof(double) * std::max<int64_t>(nnz, 1));
+  c->colindT.alloc(sizeof(int32_t) * nz);
+  c->permT.alloc(sizeof(int32_t) * nz);
+  c->valsT.alloc(sizeof(double) * nz);
   NSP_HIP(hipMemcpy(c->rowptr32.p, rp32.data(), sizeof(int32_t) * (m + 1), hipMemcpyHostToDevice));
+  NSP_HIP(hipMemcpy(c->colperm.p, cord.data(), sizeof(int32_t) * n, hipMemcpyHostToDevice));
   NSP_HIP(hipMemcpy(c->rowptrT.p, rpt.data(), sizeof(int32_t) * (n + 1), hipMemcpyHostToDevice));
   if (nnz) {
+    NSP_HIP(hipMemcpy(c->colindA.p, ci2.data(), sizeof(int32_t) * nnz, hipMemcpyHostToDevice));
+    NSP_HIP(hipMemcpy(c->permA.p, pa.data(), sizeof(int32_t) * nnz, hipMemcpyHostToDevice));
     NSP_HIP(hipMemcpy(c->colindT.p, cit.data(), sizeof(int32_t) * nnz, hipMemcpyHostToDevice));
-    NSP_HIP(hipMemcpy(c->permT.p, perm.data(), sizeof(int32_t) * nnz, hipMemcpyHostToDevice));
+    NSP_HIP(hipMemcpy(c->permT.p, pt.data(), sizeof(int32_t) * nnz, hipMemcpyHostToDevice));
     k_gather_vals<<<nblocks(nnz, kThreads), kThreads, 0, c->stream>>>(
-        nnz, c->permT.as<int32_t>(), c->A.val, c->valsT.as<double>());
+        nnz, c->permA.as<int32_t>(), vals, c->valsA.as<double>());
+    k_gather_vals<<<nblocks(nnz, kThreads), kThreads, 0, c->stream>>>(
+        nnz, c->permT.as<int32_t>(), c->valsA.as<double>(), c->valsT.as<double>());
     NSP_HIP(hipGetLastError());
   }
+  c->reordered = re;
   c->A.rows = m; c->A.cols = n; c->A.nnz = nnz;
   c->A.rowptr = c->rowptr32.as<int32_t>();
+  c->A.colind = c->colindA.as<int32_t>();
+  c->A.val = c->valsA.as<double>();
   c->A.lpr = choose_lpr(m, nnz);
   c->AT.rows = n; c->AT.cols = m; c->AT.nnz = nnz;
   c->AT.rowptr = c->rowptrT.as<int32_t>();
@@ -445,26 +588,77 @@ void build_transpose(nsp_ctx* c, const int64_t* rowptr64) {
     c->A.val32 = c->vals32.as<float>();
     c->AT.val32 = c->valsT32.as<float>();
   }
+  NSP_HIP(hipStreamSynchronize(c->stream));
 }
 
+__global__ void k_rows_copy(int64_t n, int ncols, const int32_t* __restrict__ idx, bool scatter,
+                            const double* __restrict__ src, int64_t lds, double* __restrict__ dst,
+                            int64_t ldd) {
+  const int64_t total = n * ncols;
+  for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < total;
+       t += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t i = t % n, j = t / n;
+    const int64_t k = idx ? idx[i] : i;
+    if (scatter) dst[k + j * ldd] = src[i + j * lds];
+    else dst[i + j * ldd] = src[k + j * lds];
+  }
+}
+
+void gather_rows(nsp_ctx* c, int64_t n, int ncols, const int32_t* idx, const double* src,
+                 int64_t lds, double* dst, int64_t ldd) {
+  if (n <= 0 || ncols <= 0) return;
+  const int g = (int)std::min<int64_t>(nblocks(n * ncols, kThreads), 4096);
+  k_rows_copy<<<g, kThreads, 0, c->stream>>>(n, ncols, idx, false, src, lds, dst, ldd);
+  NSP_HIP(hipGetLastError());
+}
+
+void scatter_rows(nsp_ctx* c, int64_t n, int ncols, const int32_t* idx, const double* src,
+                  int64_t lds, double* dst, int64_t ldd) {
+  if (n <= 0 || ncols <= 0) return;
+  const int g = (int)std::min<int64_t>(nblocks(n * ncols, kThreads), 4096);
+  k_rows_copy<<<g, kThreads, 0, c->stream>>>(n, ncols, idx, true, src, lds, dst, ldd);
+  NSP_HIP(hipGetLastError());
+}
+
+__global__ void k_scatter_vals(int64_t nnz, const int32_t* __restrict__ perm,
+                               const double* __restrict__ src, double* __restrict__ dst) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < nnz) dst[perm[i]] = src[i];
+}
+
+void scatter_vals(nsp_ctx* c, const double* src, double* dst) {
+  if (c->nnz == 0) return;
+  k_scatter_vals<<<nblocks(c->nnz, kThreads), kThreads, 0, c->stream>>>(
+      c->nnz, c->permA.as<int32_t>(), src, dst);
+  NSP_HIP(hipGetLastError());
+}
+
+// D and Omega are given (or drawn) in the caller's order of the unknowns and
+// stored in the library's order.
 void init_random(nsp_ctx* c, const double* D, const double* Omega) {
   const int64_t n = c->n;
   const int d = c->prm.d;
+  const int32_t* cp = c->colperm.as<int32_t>();
   c->Dv.alloc(sizeof(double) * n);
   c->omega.alloc(sizeof(double) * n * d);
+  DBuf draw;
+  if (!D || !Omega) draw.alloc(sizeof(double) * n * d);
   if (D) {
-    NSP_HIP(hipMemcpyAsync(c->Dv.p, D, sizeof(double) * n, hipMemcpyDeviceToDevice, c->stream));
+    gather_rows(c, n, 1, cp, D, n, c->Dv.as<double>(), n);
   } else {
     k_philox_uniform<<<nblocks(n, kThreads), kThreads, 0, c->stream>>>(n, c->prm.seed, 0u,
-                                                                        c->Dv.as<double>());
+                                                                        draw.as<double>());
+    NSP_HIP(hipGetLastError());
+    gather_rows(c, n, 1, cp, draw.as<double>(), n, c->Dv.as<double>(), n);
   }
   if (Omega) {
-    NSP_HIP(hipMemcpyAsync(c->omega.p, Omega, sizeof(double) * n * d, hipMemcpyDeviceToDevice,
-                           c->stream));
+    gather_rows(c, n, d, cp, Omega, n, c->omega.as<double>(), n);
   } else {
     for (int j = 0; j < d; ++j)
       k_philox_normal<<<nblocks(n, kThreads), kThreads, 0, c->stream>>>(
-          n, c->prm.seed, (uint32_t)(j + 1), c->omega.as<double>() + (int64_t)j * n);
+          n, c->prm.seed, (uint32_t)(j + 1), draw.as<double>() + (int64_t)j * n);
+    NSP_HIP(hipGetLastError());
+    gather_rows(c, n, d, cp, draw.as<double>(), n, c->omega.as<double>(), n);
   }
   NSP_HIP(hipGetLastError());
   std::vector<double> hd(n);
@@ -514,18 +708,22 @@ double matrix_norms(nsp_ctx* c) {
 // row-interleaved path in chunks of at most 8.
 void apply_b_colmajor(nsp_ctx* c, const double* X, int64_t ldx, double* Y, int64_t ldy, int ncols) {
   const int64_t m = c->m, n = c->n;
-  DBuf xr, yr, zr;
+  const int32_t* cp = c->colperm.as<int32_t>();
+  DBuf xc, xr, yr, zr;
+  xc.alloc(sizeof(double) * n * kMaxD);
   xr.alloc(sizeof(double) * n * kMaxD);
   yr.alloc(sizeof(double) * m * kMaxD);
   zr.alloc(sizeof(double) * n * kMaxD);
   for (int j0 = 0; j0 < ncols;) {
     const int left = ncols - j0;
     const int w = left >= 8 ? 8 : left >= 4 ? 4 : left >= 2 ? 2 : 1;
-    colmajor_to_rows(c, n, w, X + (int64_t)j0 * ldx, ldx, xr.as<double>());
+    gather_rows(c, n, w, cp, X + (int64_t)j0 * ldx, ldx, xc.as<double>(), n);
+    colmajor_to_rows(c, n, w, xc.as<double>(), n, xr.as<double>());
     spmm_block<double>(c, c->A, w, xr.as<double>(), yr.as<double>());
     spmmT_step<double>(c, w, yr.as<double>(), xr.as<double>(), nullptr, nullptr, zr.as<double>(),
                        nullptr);
-    rows_to_colmajor(c, n, w, zr.as<double>(), Y + (int64_t)j0 * ldy, ldy);
+    rows_to_colmajor(c, n, w, zr.as<double>(), xc.as<double>(), n);
+    scatter_rows(c, n, w, cp, xc.as<double>(), n, Y + (int64_t)j0 * ldy, ldy);
     j0 += w;
   }
   NSP_HIP(hipStreamSynchronize(c->stream));

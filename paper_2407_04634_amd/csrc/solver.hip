@@ -542,14 +542,14 @@ struct Refiner {
     const bool verbose = ve && ve[0] == '1';
     double last_print = now_s();
     while (any && it < p.max_refine_iter) {
-      spmm_wide(c, c->A, k, pp, q);
-      coldots(c, m, k, q, q, qq, part);
+      // q = A p with its column norms fused; r = A^T s likewise
+      const int nq = spmm_wide(c, c->A, k, pp, q, part);
+      reduce_parts(c, nq, k, part, qq);
       cgls_xs(c, n, m, k, gamma, qq, act, x, pp, sv, q);
-      spmm_wide(c, c->AT, k, sv, r);
-      coldots(c, n, k, r, r, gnew, part);
+      const int nr = spmm_wide(c, c->AT, k, sv, r, part);
+      reduce_parts(c, nr, k, part, gnew);
       cgls_p(c, n, k, gnew, gamma, act, r, pp);
-      // gamma <- gnew for active columns (inactive ones keep alpha = 0 anyway)
-      NSP_HIP(hipMemcpyAsync(gamma, gnew, sizeof(double) * k, hipMemcpyDeviceToDevice, c->stream));
+      std::swap(gamma, gnew);  // the new gamma is the next iteration's old one
       ++it;
       if (it % 16 == 0) {
         coldots(c, m, k, sv, sv, sn2, part);
@@ -638,7 +638,14 @@ void run_backward(nsp_ctx* c, const double* GsV, int64_t ld, double* grad, doubl
   double* vr = alloc_as<double>(b_v, (size_t)n * k);
   double* r = alloc_as<double>(b_r, (size_t)n * k);
   colmajor_to_rows(c, n, k, c->V.as<double>(), n, vr);
-  colmajor_to_rows(c, n, k, GsV, ld, r);
+  {
+    // G_s V arrives in the caller's order of the unknowns
+    DBuf b_gc;
+    double* gc = alloc_as<double>(b_gc, (size_t)n * k);
+    gather_rows(c, n, k, c->colperm.as<int32_t>(), GsV, ld, gc, n);
+    colmajor_to_rows(c, n, k, gc, n, r);
+    NSP_HIP(hipStreamSynchronize(c->stream));
+  }
   // R = G - V (V^T G)
   double* mm = alloc_as<double>(b_mm, (size_t)k * k);
   dgemm(c, rocblas_operation_none, rocblas_operation_transpose, k, k, n, 1.0, vr, k, r, k, 0.0, mm, k);
@@ -701,8 +708,14 @@ void run_backward(nsp_ctx* c, const double* GsV, int64_t ld, double* grad, doubl
   }
   // U = A W, grad_p = -2 <U_i, V_j>
   spmm_wide(c, c->A, k, w, y);
-  sddmm(c, k, y, vr, grad);
-  NSP_HIP(hipStreamSynchronize(c->stream));
+  {
+    // gradient per stored nonzero, then back to the caller's order
+    DBuf b_gs;
+    double* gs = alloc_as<double>(b_gs, (size_t)std::max<int64_t>(c->nnz, 1));
+    sddmm(c, k, y, vr, gs);
+    scatter_vals(c, gs, grad);
+    NSP_HIP(hipStreamSynchronize(c->stream));
+  }
   if (iters) *iters = it;
   if (any) throw Error(NSP_ERR_NOCONV, "backward CG reached max_iter");
 }
