@@ -115,7 +115,7 @@ nsp_status nullspace_init(nsp_ctx** out, int64_t m, int64_t n, int64_t nnz, cons
     NSP_BLAS(rocblas_create_handle(&c->blas));
     NSP_BLAS(rocblas_set_stream(c->blas, c->stream));
     // per-block partials of the step reductions (stream-ordered reuse)
-    c->part_xi.alloc(sizeof(double) * nsp::kRedBlocks * nsp::kMaxD * nsp::kMaxD);
+    c->part_xi.alloc(sizeof(double) * (nsp::kStreamBlocks + 1) * nsp::kMaxD * nsp::kMaxD);
     c->part_g.alloc(sizeof(double) * nsp::kRedBlocks * nsp::kMaxD * nsp::kMaxD);
     c->part_g2.alloc(sizeof(double) * nsp::kRedBlocks * nsp::kMaxD * nsp::kMaxD);
     nsp::prepare_matrix(c, rowptr, colind, vals);

@@ -72,6 +72,9 @@ struct DBuf {
 constexpr int kMaxD = 8;            // largest supported block size
 constexpr int kRedBlocks = 512;     // grid cap of kernels that write per-block partials
 constexpr int kWideBlocks = 1024;   // grid cap of the many-column SpMM (its partials: x k)
+constexpr int kXcds = 8;            // accelerator complex dies; workgroups go round-robin over them
+constexpr int kStreamBlocks = 2048; // grid cap of the streaming SpMV
+constexpr int64_t kStreamMinNnz = 1 << 21;  // smaller matrices use the lanes-per-row kernels
 constexpr int kThreads = 256;       // threads per block of streaming kernels
 
 // ---------------------------------------------------------------------------
@@ -84,7 +87,15 @@ struct Csr {
   const double* val = nullptr;
   const float* val32 = nullptr;
   int lpr = 1;                      // lanes per row chosen from the mean row length
+  // row blocks of the streaming kernels (each at most stream_tile(d) nonzeros,
+  // or one longer row), built at init for the solver's block size d
+  const int32_t* rblk = nullptr;
+  int nrb = 0;
+  int rblk_d = 0;
 };
+
+// nonzeros per row block of the streaming SpMV for a block of d columns
+constexpr int stream_tile(int d) { return 2048 / d; }
 
 // pinned host buffer for the small read-backs (hipHostMalloc, grown on demand)
 template <typename T>
@@ -129,6 +140,7 @@ struct nsp_ctx {
   // the library's own copy of A in the locality order (or the caller's order)
   nsp::DBuf colindA, valsA;
   nsp::DBuf permA;          // position in the stored A -> position in the caller's arrays
+  nsp::DBuf rblkA, rblkT;   // row blocks of A and A^T for the streaming SpMV
   nsp::DBuf colperm;        // stored column (unknown) i -> caller's column colperm[i]
   bool reordered = false;
   double normA_fro = 0.0;

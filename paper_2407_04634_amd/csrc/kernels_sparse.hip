@@ -326,6 +326,174 @@ static inline unsigned nblocks(int64_t work, int per) { return (unsigned)((work 
 // ---------------------------------------------------------------------------
 // host-side launchers
 // ---------------------------------------------------------------------------
+// ---------------------------------------------------------------------------
+// CSR streaming, used for the Lanczos step's SpMV pair.  The rows are cut at
+// init into row blocks of at most stream_tile(D) nonzeros (a longer row is a
+// block of its own).  A workgroup streams a row block's column indices and
+// values with consecutive lanes on consecutive nonzeros (coalesced), gathers
+// the operand rows, parks the D products per nonzero in LDS, and then one
+// thread per row sums that row's segment in order.  The grid is persistent:
+// workgroup b takes row blocks b, b + grid, ...
+// STEP adds the epilogue of the fused second product (k_spmmT_step):
+//   P = A^T Y + eps D X [- Xp Gamma_prev^T], with per-workgroup partials of
+//   Xi = X^T P when XI is set.
+// ---------------------------------------------------------------------------
+template <typename VT, int D, bool STEP, bool PREV, bool XI>
+__global__ __launch_bounds__(kThreads) void k_csr_stream(
+    int nrb, const int32_t* __restrict__ rblk, const int32_t* __restrict__ rp,
+    const int32_t* __restrict__ ci, const VT* __restrict__ av, const VT* __restrict__ xin,
+    const VT* __restrict__ x, const double* __restrict__ dv, double eps,
+    const VT* __restrict__ xp, const double* __restrict__ gprev, VT* __restrict__ out,
+    double* __restrict__ part_xi) {
+  constexpr int TILE = stream_tile(D);
+  constexpr int NV = XI ? D * D : 1;
+  __shared__ VT prod[TILE * D];
+  __shared__ double gp[D * D];
+  __shared__ double smem[(kThreads / kWave) * NV];
+  const int t = threadIdx.x;
+  const int lane = t % kWave, wid = t / kWave;
+  if (PREV && t < D * D) gp[t] = gprev[t];  // read after the loop's first barrier
+  double dots[NV];
+#pragma unroll
+  for (int i = 0; i < NV; ++i) dots[i] = 0.0;
+  // XCD-aware order: workgroups are dispatched round-robin over the 8 XCDs, so
+  // workgroup w runs on XCD w % 8.  Each XCD takes one contiguous eighth of the
+  // row blocks; with rows in locality order its gathers then stay in its own
+  // L2.  The grid is a multiple of 8.
+  const int xcd = blockIdx.x % kXcds, slot = blockIdx.x / kXcds, per = gridDim.x / kXcds;
+  const int lo = (int)((int64_t)nrb * xcd / kXcds), hi = (int)((int64_t)nrb * (xcd + 1) / kXcds);
+  for (int b = lo + slot; b < hi; b += per) {
+    const int r0 = rblk[b], r1 = rblk[b + 1];
+    const int e0 = rp[r0];
+    const int cnt = rp[r1] - e0;
+    const bool tiled = cnt <= TILE;  // uniform over the workgroup
+    if (tiled) {
+      // the matrix is read once per product: non-temporal loads keep it from
+      // evicting the gathered operand rows out of L2
+      for (int i = t; i < cnt; i += kThreads) {
+        const VT a = __builtin_nontemporal_load(av + e0 + i);
+        const VT* xr = xin + (int64_t)__builtin_nontemporal_load(ci + e0 + i) * D;
+#pragma unroll
+        for (int j = 0; j < D; ++j) prod[i * D + j] = a * xr[j];
+      }
+    } else {
+      VT acc[D];
+#pragma unroll
+      for (int j = 0; j < D; ++j) acc[j] = VT(0);
+      for (int i = t; i < cnt; i += kThreads) {
+        const VT a = av[e0 + i];
+        const VT* xr = xin + (int64_t)ci[e0 + i] * D;
+#pragma unroll
+        for (int j = 0; j < D; ++j) acc[j] = fma(a, xr[j], acc[j]);
+      }
+#pragma unroll
+      for (int j = 0; j < D; ++j) {
+        const VT v = wave_sum(acc[j]);
+        if (lane == 0) prod[wid * D + j] = v;
+      }
+    }
+    __syncthreads();
+    for (int r = r0 + t; r < r1; r += kThreads) {
+      VT s[D];
+#pragma unroll
+      for (int j = 0; j < D; ++j) s[j] = VT(0);
+      if (tiled) {
+        const int pe = rp[r + 1] - e0;
+        for (int p = rp[r] - e0; p < pe; ++p)
+#pragma unroll
+          for (int j = 0; j < D; ++j) s[j] += prod[p * D + j];
+      } else {  // a single long row, r == r0, t == 0
+#pragma unroll
+        for (int w = 0; w < kThreads / kWave; ++w)
+#pragma unroll
+          for (int j = 0; j < D; ++j) s[j] += prod[w * D + j];
+      }
+      if constexpr (STEP) {
+        const VT sd = VT(eps * dv[r]);
+        VT xr[D];
+#pragma unroll
+        for (int j = 0; j < D; ++j) xr[j] = x[(int64_t)r * D + j];
+#pragma unroll
+        for (int j = 0; j < D; ++j) s[j] = fma(sd, xr[j], s[j]);
+        if (PREV) {
+          VT pr[D];
+#pragma unroll
+          for (int j = 0; j < D; ++j) pr[j] = xp[(int64_t)r * D + j];
+#pragma unroll
+          for (int a = 0; a < D; ++a) {
+            VT u = s[a];
+#pragma unroll
+            for (int q = 0; q < D; ++q) u = fma(-pr[q], VT(gp[a + q * D]), u);
+            s[a] = u;
+          }
+        }
+        if constexpr (XI) {
+#pragma unroll
+          for (int a = 0; a < D; ++a)
+#pragma unroll
+            for (int q = 0; q < D; ++q) dots[a * D + q] += (double)xr[a] * (double)s[q];
+        }
+      }
+#pragma unroll
+      for (int j = 0; j < D; ++j) out[(int64_t)r * D + j] = s[j];
+    }
+    __syncthreads();  // prod is rewritten by the next row block
+  }
+  if constexpr (XI) {
+    block_sum<NV>(dots, smem);
+    if (t == 0) {
+#pragma unroll
+      for (int i = 0; i < NV; ++i) part_xi[(size_t)blockIdx.x * NV + i] = dots[i];
+    }
+  }
+}
+
+template <typename VT, int D, bool STEP, bool PREV, bool XI>
+static int csr_stream(nsp_ctx* c, const Csr& a, const VT* xin, const VT* x, const VT* xp,
+                      const double* gprev, VT* out, double* part_xi) {
+  const VT* av = nullptr;
+  if constexpr (sizeof(VT) == 8) av = a.val; else av = a.val32;
+  if (a.nrb == 0) return 0;
+  // a multiple of kXcds workgroups, about one row block each up to the cap
+  const int grid = std::min(kStreamBlocks, (a.nrb + kXcds - 1) / kXcds * kXcds);
+  // with many workgroups the Xi partials go behind the first kMaxD^2 slots and
+  // one extra launch sums them, so the next kernel reads a single partial
+  const bool split = XI && grid > kRedBlocks;
+  double* pw = split ? part_xi + kMaxD * kMaxD : part_xi;
+  k_csr_stream<VT, D, STEP, PREV, XI><<<grid, kThreads, 0, c->stream>>>(
+      a.nrb, a.rblk, a.rowptr, a.colind, av, xin, x, c->Dv.as<double>(), c->prm.eps, xp, gprev, out,
+      pw);
+  NSP_HIP(hipGetLastError());
+  if (split) {
+    reduce_parts(c, grid, D * D, pw, part_xi);
+    return 1;
+  }
+  return grid;
+}
+
+// Row blocks for the streaming kernels: consecutive rows while their nonzeros
+// fit in ``tile`` (and at most 1024 rows); a row longer than ``tile`` alone.
+static std::vector<int32_t> stream_blocks(const std::vector<int32_t>& rp, int64_t rows, int tile) {
+  std::vector<int32_t> b{0};
+  int64_t start = 0, acc = 0;
+  for (int64_t r = 0; r < rows; ++r) {
+    const int64_t len = (int64_t)rp[r + 1] - rp[r];
+    if (r > start && (acc + len > tile || r - start >= 1024)) {
+      b.push_back((int32_t)r);
+      start = r;
+      acc = 0;
+    }
+    acc += len;
+    if (len > tile) {
+      b.push_back((int32_t)(r + 1));
+      start = r + 1;
+      acc = 0;
+    }
+  }
+  if (b.back() != rows) b.push_back((int32_t)rows);
+  return b;
+}
+
 template <typename VT, int D>
 static void spmm_d(nsp_ctx* c, const Csr& a, const VT* x, VT* y) {
   const VT* av = nullptr;
@@ -347,6 +515,15 @@ static void spmm_d(nsp_ctx* c, const Csr& a, const VT* x, VT* y) {
 
 template <typename VT>
 void spmm_block(nsp_ctx* c, const Csr& a, int d, const VT* x, VT* y) {
+  if (a.rblk && a.rblk_d == d) {
+    switch (d) {
+      case 1: csr_stream<VT, 1, false, false, false>(c, a, x, nullptr, nullptr, nullptr, y, nullptr); return;
+      case 2: csr_stream<VT, 2, false, false, false>(c, a, x, nullptr, nullptr, nullptr, y, nullptr); return;
+      case 4: csr_stream<VT, 4, false, false, false>(c, a, x, nullptr, nullptr, nullptr, y, nullptr); return;
+      case 8: csr_stream<VT, 8, false, false, false>(c, a, x, nullptr, nullptr, nullptr, y, nullptr); return;
+      default: break;
+    }
+  }
   switch (d) {
     case 1: spmm_d<VT, 1>(c, a, x, y); break;
     case 2: spmm_d<VT, 2>(c, a, x, y); break;
@@ -386,6 +563,22 @@ template <typename VT>
 int spmmT_step(nsp_ctx* c, int d, const VT* y, const VT* x, const VT* xp, const double* gprev,
                VT* out, double* part_xi) {
   const bool prev = xp != nullptr, dots = part_xi != nullptr;
+  const Csr& at = c->AT;
+  if (at.rblk && at.rblk_d == d) {
+#define NSP_STREAM(D)                                                                                     \
+    if (prev && dots) return csr_stream<VT, D, true, true, true>(c, at, y, x, xp, gprev, out, part_xi);   \
+    else if (prev) return csr_stream<VT, D, true, true, false>(c, at, y, x, xp, gprev, out, part_xi);     \
+    else if (dots) return csr_stream<VT, D, true, false, true>(c, at, y, x, xp, gprev, out, part_xi);     \
+    else return csr_stream<VT, D, true, false, false>(c, at, y, x, xp, gprev, out, part_xi);
+    switch (d) {
+      case 1: { NSP_STREAM(1) }
+      case 2: { NSP_STREAM(2) }
+      case 4: { NSP_STREAM(4) }
+      case 8: { NSP_STREAM(8) }
+      default: break;
+    }
+#undef NSP_STREAM
+  }
 #define NSP_DISPATCH(D)                                                                        \
   if (prev && dots) return spmmT_step_d<VT, D, true, true>(c, y, x, xp, gprev, out, part_xi);   \
   else if (prev) return spmmT_step_d<VT, D, true, false>(c, y, x, xp, gprev, out, part_xi);     \
@@ -567,6 +760,24 @@ void prepare_matrix(nsp_ctx* c, const int64_t* rowptr64, const int32_t* colind, 
     k_gather_vals<<<nblocks(nnz, kThreads), kThreads, 0, c->stream>>>(
         nnz, c->permT.as<int32_t>(), c->valsA.as<double>(), c->valsT.as<double>());
     NSP_HIP(hipGetLastError());
+  }
+  if (nnz >= kStreamMinNnz) {
+    // nonzeros per row block: the LDS capacity, or less for smaller matrices so
+    // that there are about 2048 row blocks to spread over the chip
+    const int d = c->prm.d;
+    int tile = 64;
+    while (tile < stream_tile(d) && (int64_t)tile * 2048 < nnz) tile *= 2;
+    const std::vector<int32_t> ba = stream_blocks(rp32, m, tile), bt = stream_blocks(rpt, n, tile);
+    c->rblkA.alloc(sizeof(int32_t) * ba.size());
+    c->rblkT.alloc(sizeof(int32_t) * bt.size());
+    NSP_HIP(hipMemcpy(c->rblkA.p, ba.data(), sizeof(int32_t) * ba.size(), hipMemcpyHostToDevice));
+    NSP_HIP(hipMemcpy(c->rblkT.p, bt.data(), sizeof(int32_t) * bt.size(), hipMemcpyHostToDevice));
+    c->A.rblk = c->rblkA.as<int32_t>();
+    c->A.nrb = (int)ba.size() - 1;
+    c->A.rblk_d = d;
+    c->AT.rblk = c->rblkT.as<int32_t>();
+    c->AT.nrb = (int)bt.size() - 1;
+    c->AT.rblk_d = d;
   }
   c->reordered = re;
   c->A.rows = m; c->A.cols = n; c->A.nnz = nnz;
