@@ -28,6 +28,19 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 
+# HBM bytes per launch of the dominant kernel, from two rocprofv3 --pmc runs of
+# this script (FETCH_SIZE, then WRITE_SIZE, KiB per dispatch) scaled by the same
+# counters on the plain copy of --copy-calibration; the summary with the full
+# commands is profiles/k_ts_nn_v_planted50k_traffic.md.  Keyed by (workload, d,
+# precision, kernel); an entry is dropped whenever that kernel changes.
+TRAFFIC = {
+    # FETCH_SIZE 152798 KiB x 2.0 + WRITE_SIZE 813 KiB x 1.0 per launch that
+    # reorthogonalised, against 303.8 MB algorithmic in the same 40-cycle run
+    ("planted50k", 1, "fp64", "k_ts_nn_v"): {"ratio": 1.033},
+    # FETCH_SIZE 160740 KiB x 2.0 + WRITE_SIZE (partials) < 1 MiB, against 303.0 MB
+    ("planted50k", 1, "fp64", "k_ts_tn"): {"ratio": 1.086},
+}
+
 # eps = c * sigma_min(A)^2 with c ~ 0.1 (Remark after Thm. "thmmain" asks for c < 1/3);
 # sigma_min comes from dense SVD on same-shaped probes (planted) or the known
 # smallest Laplacian eigenvalue (er20).
@@ -137,17 +150,36 @@ def kernel_rooflines(st, m, n, nnz, d, esize):
     if st.get("spmv_samples", 0) > 0:
         out.append(("k_spmm (y = A x)", st["t_spmv_a_us"], a_b))
         out.append(("k_spmmT_step (P = A^T y + eps D x - Xp Gamma^T)", st["t_spmv_at_us"], at_b))
-    ns = st.get("ro_samples", 0)
-    if ns > 0:
-        out.append(("k_ts_tn + k_reduce_cols (H = Z^T [q_l, q_l+1])", st["ro_tn_ms"] / ns * 1e3,
-                    st["ro_tn_bytes"] / ns))
-        out.append(("k_ts_nn ([q_l, q_l+1] -= Z H, fused Gram)", st["ro_nn_ms"] / ns * 1e3,
-                    st["ro_nn_bytes"] / ns))
+    na = st.get("ro_active", 0)
+    if na > 0:
+        # launches at steps whose W-recurrence flag was clear return at once; the
+        # figures below are per launch that reorthogonalised
+        out.append(("k_ts_tn (H = Z^T [q_l, q_l+1], per-chunk partials)", st["ro_tn_ms"] / na * 1e3,
+                    st["ro_tn_bytes"] / na))
+        out.append(("k_ts_nn_v ([q_l, q_l+1] -= Z H, fused Gram)", st["ro_nn_ms"] / na * 1e3,
+                    st["ro_nn_bytes"] / na))
     rows = []
     for name, us, b in out:
         gbs = b / (us * 1e-6) / 1e9 if us > 0 else 0.0
         rows.append({"kernel": name, "avg_us": us, "bytes_per_launch": b, "achieved_gbs": gbs})
     return rows
+
+
+def copy_calibration(nbytes=1 << 30, reps=5):
+    """A plain copy of known size for scaling rocprofv3's FETCH_SIZE / WRITE_SIZE.
+
+    Runs ``reps`` launches of an elementwise kernel that reads ``nbytes`` and
+    writes ``nbytes`` (dst = src * 1.0, FP64).
+    """
+    import torch
+
+    src = torch.ones(nbytes // 8, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(reps):
+        torch.mul(src, 1.0, out=dst)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_calibration": {"bytes_read": nbytes, "bytes_written": nbytes,
+                                           "launches": reps, "kernel": "torch.mul(src, 1.0, out=dst)"}}))
 
 
 def spmv_hbm(name, prec, d=1, max_dim=64, reorder=1):
@@ -194,9 +226,14 @@ def main():
     ap.add_argument("--no-refine", action="store_true", help="skip the FP64 refinement (profiling runs)")
     ap.add_argument("--profile", type=int, default=1,
                     help="HIP-event timing of the SpMV and reorthogonalisation kernels")
-    ap.add_argument("--spmv-workload", default="zipf4m",
-                    help="large matrix for the SpMV HBM measurement ('none' to skip)")
+    ap.add_argument("--spmv-workload", default="zipf4m,coboundary1m",
+                    help="comma-separated large matrices for the SpMV HBM measurement ('none' to skip)")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run the plain copy that scales the rocprofv3 byte counters")
     args = ap.parse_args()
+    if args.copy_calibration:
+        copy_calibration()
+        return
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only; --gpus {args.gpus} is not supported "
               "(the multi-GPU sharding is a design note, not built)", file=sys.stderr)
@@ -269,16 +306,24 @@ def main():
     esize = 4 if args.prec == "mixed" else 8
     kr = kernel_rooflines(st, c.m, c.n, c.nnz, args.d, esize)
     if kr:
-        dom = max(kr, key=lambda r: r["avg_us"])  # every kernel here runs once per Lanczos step
+        # dominant kernel: the largest total time over the run (SpMV pair every
+        # step, reorthogonalisation pair at the flagged steps)
+        steps = st["matvecs"] / args.d
+        frac = st["ro_active"] / max(1, st["ro_samples"])
+        weight = [steps if r["kernel"].startswith("k_spmm") else steps * frac for r in kr]
+        dom = max(zip(kr, weight), key=lambda t: t[0]["avg_us"] * t[1])[0]
+        tr = TRAFFIC.get((args.workload, args.d, args.prec, dom["kernel"].split()[0]))
         line["roofline"] = {"kernel": dom["kernel"], "bound": "hbm", "achieved": dom["achieved_gbs"],
                             "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                            "frac": dom["achieved_gbs"] / HBM_PEAK_GBS, "traffic": None,
-                            "avg_us": dom["avg_us"], "bytes_per_launch": dom["bytes_per_launch"]}
+                            "frac": dom["achieved_gbs"] / HBM_PEAK_GBS,
+                            "traffic": tr["ratio"] * dom["bytes_per_launch"] if tr else None,
+                            "avg_us": dom["avg_us"], "bytes_per_launch": dom["bytes_per_launch"],
+                            "launches": "per launch that reorthogonalised" if "ts_" in dom["kernel"] else "per launch"}
         line["kernels"] = kr
-        line["reorth_active_frac"] = st["ro_active"] / max(1, st["ro_samples"])
+        line["reorth_active_frac"] = frac
+        line["reorth_idle_launch_us"] = st["ro_idle_ms"] / max(1, st["ro_samples"] - st["ro_active"]) * 1e3
     if args.spmv_workload != "none":
-        sp = [spmv_hbm(args.spmv_workload, p, reorder=r) for p, r in
-              (("fp64", 1), ("mixed", 1), ("fp64", 0))]
+        sp = [spmv_hbm(w, p) for w in args.spmv_workload.split(",") for p in ("fp64", "mixed")]
         for r in sp:
             print(f"[bench] spmv {json.dumps(r)}", file=sys.stderr, flush=True)
         line["spmv_hbm"] = sp

@@ -113,13 +113,15 @@ typedef struct {
   double t_spmv_a_us;      /* profile: mean duration of one y = A x launch (us)         */
   double t_spmv_at_us;     /* profile: mean duration of one fused A^T launch (us)       */
   int64_t spmv_samples;    /* profile: number of timed launch pairs                     */
-  double ro_tn_ms;         /* profile: summed duration of the sampled projections
-                              H = Z^T [Q_l, Q_l+1] (with their column reduction), ms;
-                              launches whose flag is clear return at once and count  */
-  double ro_tn_bytes;      /* ... their algorithmic bytes, (k n + 2 d n) elements each
-                              for the launches that ran, 0 for the others            */
+  double ro_tn_ms;         /* profile: summed duration of the sampled projection
+                              launches H = Z^T [Q_l, Q_l+1] (partials per row chunk)
+                              at steps that reorthogonalised, ms                      */
+  double ro_tn_bytes;      /* ... their algorithmic bytes, (k n + 2 d n) elements each */
   double ro_nn_ms;         /* profile: same for the updates [Q_l, Q_l+1] -= Z H, ms   */
-  double ro_nn_bytes;      /* ... (k n + 4 d n) elements for the launches that ran    */
+  double ro_nn_bytes;      /* ... (k n + 4 d n) elements each                          */
+  double ro_idle_ms;       /* profile: summed duration of the sampled projection plus
+                              update launches at steps whose flag was clear (they
+                              return at once), ms                                    */
   int64_t ro_samples;      /* profile: number of sampled steps                         */
   int64_t ro_active;       /* profile: how many of them reorthogonalised               */
 } nsp_stats;

@@ -74,6 +74,7 @@ class Stats(ctypes.Structure):
         ("ro_tn_bytes", ctypes.c_double),
         ("ro_nn_ms", ctypes.c_double),
         ("ro_nn_bytes", ctypes.c_double),
+        ("ro_idle_ms", ctypes.c_double),
         ("ro_samples", ctypes.c_int64),
         ("ro_active", ctypes.c_int64),
     ]

@@ -52,7 +52,7 @@ int64_t ts_part_c_len(int64_t n, int nc);
 template <typename VT>
 void ts_project(nsp_ctx* c, const int* cond, int d, int na, int64_t n, const VT* z, int64_t ldz,
                 int k, VT* a0, VT* a1, double* h, double* hpart, bool gram, double* part_c,
-                double* rinv, hipEvent_t ev_mid = nullptr);
+                double* rinv, hipEvent_t ev_tn = nullptr, hipEvent_t ev_red = nullptr);
 // C = C R^{-1}; R from the Gram partials of the preceding ts_project(gram) (R^{-1}, R -> rinv)
 template <typename VT>
 void ts_scale(nsp_ctx* c, const int* cond, int d, int na, int64_t n, VT* a0, VT* a1,

@@ -970,7 +970,7 @@ int64_t ts_chunk_rows(int64_t n, int k, int nc) {
 template <typename VT, int DA, int NA>
 static void ts_proj_t(nsp_ctx* c, const int* cond, int64_t n, const VT* z, int64_t ldz, int k,
                       VT* a0, VT* a1, double* h, double* hpart, bool gram, double* part_c,
-                      double* rinv, hipEvent_t ev_mid) {
+                      double* rinv, hipEvent_t ev_tn, hipEvent_t ev_red) {
   constexpr int NC = DA * NA;
   CPair<VT, DA, NA> cc{a0, a1};
   constexpr int TR = ts_nn_rows<VT, NC>();
@@ -981,10 +981,13 @@ static void ts_proj_t(nsp_ctx* c, const int* cond, int64_t n, const VT* z, int64
     const unsigned gy = (unsigned)((k + TsShape<NC>::JB - 1) / TsShape<NC>::JB);
     k_ts_tn<VT, DA, NA><<<dim3(nchunks, gy), kThreads, 0, c->stream>>>(cond, n, chunk, z, ldz, k, cc,
                                                                         hpart);
+    if (ev_tn) NSP_HIP(hipEventRecord(ev_tn, c->stream));
     k_reduce_cols<<<nblk((int64_t)k * NC, 32), 256, 0, c->stream>>>(cond, (int)nchunks, k * NC,
                                                                     hpart, h);
+  } else if (ev_tn) {
+    NSP_HIP(hipEventRecord(ev_tn, c->stream));
   }
-  if (ev_mid) NSP_HIP(hipEventRecord(ev_mid, c->stream));
+  if (ev_red) NSP_HIP(hipEventRecord(ev_red, c->stream));
   if constexpr (NC <= 4) {
     if (gram)
       k_ts_nn_v<VT, DA, NA, true><<<nnblocks, 512, 0, c->stream>>>(cond, n, z, ldz, k, h, cc, part_c);
@@ -1027,21 +1030,22 @@ static void ts_scale_t(nsp_ctx* c, const int* cond, int64_t n, VT* a0, VT* a1, c
 template <typename VT>
 void ts_project(nsp_ctx* c, const int* cond, int d, int na, int64_t n, const VT* z, int64_t ldz,
                 int k, VT* a0, VT* a1, double* h, double* hpart, bool gram, double* part_c,
-                double* rinv, hipEvent_t ev_mid) {
+                double* rinv, hipEvent_t ev_tn, hipEvent_t ev_red) {
   k = std::max(k, 0);
 #define NSP_TP(D)                                                                              \
   case D:                                                                                      \
-    if (na == 1) ts_proj_t<VT, D, 1>(c, cond, n, z, ldz, k, a0, a1, h, hpart, gram, part_c, rinv, ev_mid); \
-    else ts_proj_t<VT, D, 2>(c, cond, n, z, ldz, k, a0, a1, h, hpart, gram, part_c, rinv, ev_mid);          \
+    if (na == 1) ts_proj_t<VT, D, 1>(c, cond, n, z, ldz, k, a0, a1, h, hpart, gram, part_c, rinv, ev_tn, ev_red); \
+    else ts_proj_t<VT, D, 2>(c, cond, n, z, ldz, k, a0, a1, h, hpart, gram, part_c, rinv, ev_tn, ev_red);          \
     break;
   switch (d) { NSP_TP(1) NSP_TP(2) NSP_TP(4) NSP_TP(8) default: throw Error(NSP_ERR_ARG, "d"); }
 #undef NSP_TP
 }
 template void ts_project<double>(nsp_ctx*, const int*, int, int, int64_t, const double*, int64_t,
                                  int, double*, double*, double*, double*, bool, double*, double*,
-                                 hipEvent_t);
+                                 hipEvent_t, hipEvent_t);
 template void ts_project<float>(nsp_ctx*, const int*, int, int, int64_t, const float*, int64_t, int,
-                                float*, float*, double*, double*, bool, double*, double*, hipEvent_t);
+                                float*, float*, double*, double*, bool, double*, double*, hipEvent_t,
+                                hipEvent_t);
 
 template <typename VT>
 void ts_scale(nsp_ctx* c, const int* cond, int d, int na, int64_t n, VT* a0, VT* a1,

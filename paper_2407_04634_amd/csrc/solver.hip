@@ -113,13 +113,14 @@ struct Lanczos {
   // update C -= Z H), with the per-step flag telling which pairs really ran
   struct Prof {
     static constexpr int kSlots = 160;
-    static constexpr int kEv = 6;
+    static constexpr int kEv = 7;
     bool on = false;
     int used = 0;
     int ell[kSlots];
     int kcols[kSlots];
     int64_t samples = 0, ro_active = 0;
     double sum_a = 0.0, sum_at = 0.0, tn_ms = 0.0, nn_ms = 0.0, tn_bytes = 0.0, nn_bytes = 0.0;
+    double idle_ms = 0.0;
     hipEvent_t ev[kEv * kSlots];
     void init(bool enable) {
       on = enable;
@@ -130,21 +131,24 @@ struct Lanczos {
     // hist: per-step reorthogonalisation flags of this cycle (host copy)
     void collect(const int* hist, int64_t n, int d, int esize) {
       for (int i = 0; i < used; ++i) {
+        // events: 0 | A x | 1 | A^T y | 2 ... 3 | Z^T C | 4 | reduce | 5 | C -= Z H | 6
         float a = 0.f, b = 0.f, t = 0.f, u = 0.f;
         NSP_HIP(hipEventElapsedTime(&a, e(i, 0), e(i, 1)));
         NSP_HIP(hipEventElapsedTime(&b, e(i, 1), e(i, 2)));
         NSP_HIP(hipEventElapsedTime(&t, e(i, 3), e(i, 4)));
-        NSP_HIP(hipEventElapsedTime(&u, e(i, 4), e(i, 5)));
+        NSP_HIP(hipEventElapsedTime(&u, e(i, 5), e(i, 6)));
         sum_a += a;
         sum_at += b;
-        tn_ms += t;
-        nn_ms += u;
         ++samples;
         if (hist[ell[i]]) {
           const double k = kcols[i];
+          tn_ms += t;
+          nn_ms += u;
           tn_bytes += esize * (k * n + 2.0 * d * n);
           nn_bytes += esize * (k * n + 4.0 * d * n);
           ++ro_active;
+        } else {
+          idle_ms += t + u;
         }
       }
       used = 0;
@@ -304,9 +308,9 @@ struct Lanczos {
         const int kz = (ell - 1) * d;
         if (timed) NSP_HIP(hipEventRecord(prof.e(slot, 3), c->stream));
         ts_project<VT>(c, flags, d, 2, n, Z, ldz, kz, x, xn, H, hpart, true, part_c, rinvc,
-                       timed ? prof.e(slot, 4) : nullptr);
+                       timed ? prof.e(slot, 4) : nullptr, timed ? prof.e(slot, 5) : nullptr);
         if (timed) {
-          NSP_HIP(hipEventRecord(prof.e(slot, 5), c->stream));
+          NSP_HIP(hipEventRecord(prof.e(slot, 6), c->stream));
           prof.ell[slot] = ell;
           prof.kcols[slot] = kz;
           prof.used++;
@@ -388,6 +392,7 @@ struct Lanczos {
       st.ro_tn_bytes = prof.tn_bytes;
       st.ro_nn_ms = prof.nn_ms;
       st.ro_nn_bytes = prof.nn_bytes;
+      st.ro_idle_ms = prof.idle_ms;
       st.ro_samples = prof.samples;
       st.ro_active = prof.ro_active;
     }
