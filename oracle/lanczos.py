@@ -62,7 +62,7 @@ import math
 
 import numpy as np
 
-from .operator import apply_b, norm_upper_bound_ata
+from .operator import operator
 
 U = 2.0 ** -52
 
@@ -102,12 +102,14 @@ def _inv_fro(g: np.ndarray) -> float:
 # ---------------------------------------------------------------------------
 # Algorithm 1
 # ---------------------------------------------------------------------------
-def algorithm1(a, eps: float, dvec: np.ndarray, omega: np.ndarray, ell: int):
+def algorithm1(a, eps: float, dvec: np.ndarray, omega: np.ndarray, ell: int, op: str = "normal"):
     """Algorithm 1 with full reorthogonalisation.
 
     Returns dict(V, theta, N, Z, T, Q_next, Gamma_last) with V = Z_ell V_Z(:, 1:N)
-    and N = #{theta < 3 eps}.
+    and N = #{theta < 3 eps}.  ``op`` selects B = A^T A + eps D ('normal') or
+    B = A + eps D ('sym', A symmetric positive semi-definite).
     """
+    apply_b, _ = operator(op)
     n, d = omega.shape
     q1, _ = block_qr(omega)
     blocks = [q1]
@@ -220,11 +222,12 @@ def speed_rule(history, d: int):
 
 def algorithm2(a, eps: float, dvec: np.ndarray, omega: np.ndarray, dim_k: int,
                max_matvec: int = 10 ** 7, ro_tol: float | None = None, full_reorth: bool = False,
-               track_orth: bool = False, max_cycles: int | None = None):
+               track_orth: bool = False, max_cycles: int | None = None, op: str = "normal"):
     """Algorithm 2: restarted randomized small-block Lanczos with partial reorthogonalisation.
 
     Returns dict(V, N, theta, matvecs, restarts, reorths, history, converged,
-    orth_trace) where V = Z_ell V_Z(:, 1:N_ell) from the final cycle.
+    orth_trace) where V = Z_ell V_Z(:, 1:N_ell) from the final cycle.  ``op`` as
+    in algorithm1.
     ``track_orth`` records max_k ||Q_k^T Q_{ell+1}|| (true value) next to the W
     bound at every step, for testing that the bound holds.
     """
@@ -233,7 +236,8 @@ def algorithm2(a, eps: float, dvec: np.ndarray, omega: np.ndarray, dim_k: int,
         raise ValueError("dim_k must be a multiple of d and at least 3d")
     nb = dim_k // d
     u_ro = math.sqrt(U) if ro_tol is None else ro_tol
-    norm_b = norm_upper_bound_ata(a) + eps * float(np.max(dvec))
+    apply_b, norm_bound = operator(op)
+    norm_b = norm_bound(a) + eps * float(np.max(dvec))
     u_d = d * math.sqrt(n) * U * norm_b
 
     zb = np.zeros((n, dim_k + d))
