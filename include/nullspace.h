@@ -59,6 +59,16 @@ typedef enum {
                          the residual check and the backward pass                    */
 } nsp_precision;
 
+typedef enum {
+  NSP_OP_NORMAL = 0, /* B = A^T A + eps D (Eq. "defB"), any A                         */
+  NSP_OP_SYM = 1     /* B = A + eps D for a symmetric positive semi-definite A (the
+                        graph Laplacian experiments of Sec. 5.1): one product with A
+                        per step, condition number not squared.  Requires m = n and
+                        A stored with a symmetric pattern and equal mirrored values
+                        (checked at init, NSP_ERR_ARG otherwise).  Semi-definiteness
+                        is the caller's promise; the null space is then null(A).  */
+} nsp_op;
+
 /* Solver parameters (host struct).  nsp_default_params() fills defaults. */
 typedef struct {
   double eps;            /* perturbation strength eps > 0 (Eq. "defB"); the paper's
@@ -74,9 +84,11 @@ typedef struct {
   double tol_abs_resid;  /* absolute per-column target ||A v|| <= this                */
   double tol_angle;      /* target sine of the largest principal angle to null(A): a
                             column is done once ||A v|| <= this * s / (2 sqrt(N)),
-                            s^2 = theta_next - eps max(D) estimating sigma_min(A)^2
-                            from the smallest Ritz value above 3 eps.  The smallest
-                            threshold of the enabled (non-zero) criteria applies.   */
+                            s = sigma_min(A) estimated from the smallest Ritz value
+                            above 3 eps: s^2 = theta_next - eps max(D) for
+                            NSP_OP_NORMAL, s = theta_next - eps max(D) for NSP_OP_SYM.
+                            The smallest threshold of the enabled (non-zero)
+                            criteria applies.                                       */
   int64_t max_refine_iter; /* CGLS iteration cap of the refinement                   */
   int32_t max_cycles;    /* stop after this many restart cycles (0 = no limit)       */
   int32_t profile;       /* 1: time the SpMV pair and the reorthogonalisation pair
@@ -88,6 +100,7 @@ typedef struct {
                             cache; B is then P B P^T for a permutation P, the same
                             operator up to renumbering.  Every argument and result
                             of the API stays in the caller's order.  0: keep it.   */
+  int32_t op;            /* nsp_op: operator form, NSP_OP_NORMAL by default           */
   uint64_t seed;         /* seed of the built-in Philox4x32-10 draws of D and Omega,
                             used only when the caller passes D or Omega as NULL       */
 } nsp_params;
@@ -152,7 +165,8 @@ nsp_status nullspace_init(nsp_ctx** out, int64_t m, int64_t n, int64_t nnz,
                           const double* D, const double* Omega, const nsp_params* p,
                           void* stream);
 
-/* Y = B X = A^T (A X) + eps D X for ncols >= 1 columns (Sec. 1.2).
+/* Y = B X for ncols >= 1 columns: A^T (A X) + eps D X (Sec. 1.2), or
+ * A X + eps D X with NSP_OP_SYM.
  *  X [n x ncols], ld ldx >= n; Y [n x ncols], ld ldy >= n; device, FP64.
  *  Uses the FP64 values regardless of the precision mode.  X and Y must not
  *  overlap.  Allowed in any state after init. */

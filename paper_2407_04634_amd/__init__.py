@@ -13,4 +13,6 @@ from ._lib import (  # noqa: F401
     locality_order,
     PREC_FP64,
     PREC_MIXED,
+    OP_NORMAL,
+    OP_SYM,
 )

@@ -20,6 +20,7 @@ NSP_OK, NSP_ERR_ARG, NSP_ERR_HIP, NSP_ERR_NOMEM, NSP_ERR_STATE, NSP_ERR_NOCONV, 
 STATUS_NAMES = ["NSP_OK", "NSP_ERR_ARG", "NSP_ERR_HIP", "NSP_ERR_NOMEM", "NSP_ERR_STATE",
                 "NSP_ERR_NOCONV", "NSP_ERR_BREAKDOWN", "NSP_ERR_NONFINITE"]
 PREC_FP64, PREC_MIXED = 0, 1
+OP_NORMAL, OP_SYM = 0, 1
 
 
 class NspError(RuntimeError):
@@ -45,6 +46,7 @@ class Params(ctypes.Structure):
         ("max_cycles", ctypes.c_int32),
         ("profile", ctypes.c_int32),
         ("reorder", ctypes.c_int32),
+        ("op", ctypes.c_int32),
         ("seed", ctypes.c_uint64),
     ]
 

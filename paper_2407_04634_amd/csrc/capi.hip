@@ -60,6 +60,7 @@ void validate_params(const nsp_params* p, int64_t n) {
               "tolerances must be >= 0");
   NSP_REQUIRE(p->max_cycles >= 0, "max_cycles must be >= 0");
   NSP_REQUIRE(p->reorder == 0 || p->reorder == 1, "reorder must be 0 or 1");
+  NSP_REQUIRE(p->op == NSP_OP_NORMAL || p->op == NSP_OP_SYM, "op must be NSP_OP_NORMAL or NSP_OP_SYM");
 }
 
 }  // namespace
@@ -83,6 +84,7 @@ void nsp_default_params(nsp_params* p) {
   p->max_cycles = 0;
   p->profile = 0;
   p->reorder = 1;
+  p->op = NSP_OP_NORMAL;
   p->seed = 20240704ull;
 }
 
@@ -99,6 +101,7 @@ nsp_status nullspace_init(nsp_ctx** out, int64_t m, int64_t n, int64_t nnz, cons
     NSP_REQUIRE(rowptr != nullptr, "rowptr must not be NULL");
     NSP_REQUIRE(nnz == 0 || (colind != nullptr && vals != nullptr), "colind/vals must not be NULL");
     validate_params(p, n);
+    NSP_REQUIRE(p->op != NSP_OP_SYM || m == n, "op = NSP_OP_SYM needs a square A (m == n)");
     c = new nsp_ctx();
     c->m = m;
     c->n = n;

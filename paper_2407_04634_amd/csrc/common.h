@@ -145,6 +145,8 @@ struct nsp_ctx {
   bool reordered = false;
   double normA_fro = 0.0;
   double normA1_inf = 0.0;  // ||A||_1 * ||A||_inf
+  double normA_inf = 0.0;   // ||A||_inf (bounds ||A||_2 when A is symmetric)
+  bool sym = false;         // B = A + eps D (NSP_OP_SYM)
   double maxD = 1.0;        // max of the perturbation diagonal
 
   // perturbation diagonal and start block

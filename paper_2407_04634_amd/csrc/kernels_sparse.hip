@@ -234,6 +234,13 @@ __global__ void k_gather_vals(int64_t nnz, const int32_t* __restrict__ perm,
   if (i < nnz) dst[i] = src[perm[i]];
 }
 
+// flag[0] = 1 if a[i] != b[i] for some i (any thread may set it; only 0 -> 1)
+__global__ void k_values_differ(int64_t n, const double* __restrict__ a, const double* __restrict__ b,
+                                int* flag) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n && !(a[i] == b[i])) flag[0] = 1;
+}
+
 __global__ void k_to_f32(int64_t n, const double* __restrict__ src, float* __restrict__ dst) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) dst[i] = (float)src[i];
@@ -700,9 +707,11 @@ void prepare_matrix(nsp_ctx* c, const int64_t* rowptr64, const int32_t* colind, 
   for (int64_t p = 0; p < nnz; ++p) NSP_REQUIRE(hci[p] >= 0 && hci[p] < n, "colind out of range");
 
   const bool re = c->prm.reorder != 0;
+  const bool sym = c->prm.op == NSP_OP_SYM;
   std::vector<int32_t> rord(m), cord(n), cinv(n);
   if (re) {
     locality_order(m, n, hrp.data(), hci.data(), rord.data(), cord.data());
+    if (sym) rord = cord;  // a symmetric permutation keeps A symmetric
   } else {
     std::iota(rord.begin(), rord.end(), 0);
     std::iota(cord.begin(), cord.end(), 0);
@@ -717,7 +726,7 @@ void prepare_matrix(nsp_ctx* c, const int64_t* rowptr64, const int32_t* colind, 
     const int64_t b = hrp[i], e = hrp[i + 1];
     row.clear();
     for (int64_t p = b; p < e; ++p) row.emplace_back(cinv[hci[p]], (int32_t)p);
-    if (re) std::sort(row.begin(), row.end());
+    if (re || sym) std::sort(row.begin(), row.end());
     const int64_t o = rp32[r];
     for (size_t t = 0; t < row.size(); ++t) {
       ci2[o + t] = row[t].first;
@@ -779,6 +788,25 @@ void prepare_matrix(nsp_ctx* c, const int64_t* rowptr64, const int32_t* colind, 
     c->AT.nrb = (int)bt.size() - 1;
     c->AT.rblk_d = d;
   }
+  if (sym) {
+    // the stored A must equal its stored transpose: same pattern here, same
+    // values checked on the device below
+    NSP_REQUIRE(rp32 == rpt && std::equal(ci2.begin(), ci2.begin() + nnz, cit.begin()),
+                "op = NSP_OP_SYM needs a structurally symmetric A");
+    if (nnz) {
+      DBuf flag;
+      flag.alloc(sizeof(int));
+      NSP_HIP(hipMemsetAsync(flag.p, 0, sizeof(int), c->stream));
+      k_values_differ<<<nblocks(nnz, kThreads), kThreads, 0, c->stream>>>(
+          nnz, c->valsA.as<double>(), c->valsT.as<double>(), flag.as<int>());
+      NSP_HIP(hipGetLastError());
+      int hflag = 0;
+      NSP_HIP(hipMemcpyAsync(&hflag, flag.p, sizeof(int), hipMemcpyDeviceToHost, c->stream));
+      NSP_HIP(hipStreamSynchronize(c->stream));
+      NSP_REQUIRE(hflag == 0, "op = NSP_OP_SYM needs A(i,j) == A(j,i) for every stored entry");
+    }
+  }
+  c->sym = sym;
   c->reordered = re;
   c->A.rows = m; c->A.cols = n; c->A.nnz = nnz;
   c->A.rowptr = c->rowptr32.as<int32_t>();
@@ -912,6 +940,7 @@ double matrix_norms(nsp_ctx* c) {
   for (int64_t j = 0; j < n; ++j) n1 = std::max(n1, hc[j]);
   c->normA_fro = std::sqrt(fro);
   c->normA1_inf = n1 * ninf;
+  c->normA_inf = ninf;
   return c->normA_fro;
 }
 
@@ -930,9 +959,14 @@ void apply_b_colmajor(nsp_ctx* c, const double* X, int64_t ldx, double* Y, int64
     const int w = left >= 8 ? 8 : left >= 4 ? 4 : left >= 2 ? 2 : 1;
     gather_rows(c, n, w, cp, X + (int64_t)j0 * ldx, ldx, xc.as<double>(), n);
     colmajor_to_rows(c, n, w, xc.as<double>(), n, xr.as<double>());
-    spmm_block<double>(c, c->A, w, xr.as<double>(), yr.as<double>());
-    spmmT_step<double>(c, w, yr.as<double>(), xr.as<double>(), nullptr, nullptr, zr.as<double>(),
-                       nullptr);
+    // B X: A^T (A X) + eps D X, or A X + eps D X for the symmetric form (the
+    // stored A^T is A itself then)
+    const double* yin = xr.as<double>();
+    if (!c->sym) {
+      spmm_block<double>(c, c->A, w, xr.as<double>(), yr.as<double>());
+      yin = yr.as<double>();
+    }
+    spmmT_step<double>(c, w, yin, xr.as<double>(), nullptr, nullptr, zr.as<double>(), nullptr);
     rows_to_colmajor(c, n, w, zr.as<double>(), xc.as<double>(), n);
     scatter_rows(c, n, w, cp, xc.as<double>(), n, Y + (int64_t)j0 * ldy, ldy);
     j0 += w;

@@ -238,6 +238,19 @@ struct Lanczos {
                        nrm_ginv + blk_from, wa);
   }
 
+  // P = B X - Xp Gamma_prev^T with the Xi partials (Alg. 2 inner loop):
+  // A^T (A X) + eps D X, or A X + eps D X for the symmetric form (the stored
+  // A^T is A itself then).  ``mid`` is recorded between the two products.
+  int apply_b(VT* x, const VT* xp, const double* gprev, hipEvent_t mid = nullptr) {
+    const VT* yin = x;
+    if (!c->sym) {
+      spmm_block<VT>(c, c->A, d, x, Y);
+      yin = Y;
+    }
+    if (mid) NSP_HIP(hipEventRecord(mid, c->stream));
+    return spmmT_step<VT>(c, d, yin, x, xp, gprev, P, part_xi);
+  }
+
   void cgs2_full(VT* a, int k, bool final_gram, double* rinv_out) {
     ts_project<VT>(c, nullptr, d, 1, n, Z, ldz, k, a, nullptr, H, hpart, false, nullptr, nullptr);
     ts_project<VT>(c, nullptr, d, 1, n, Z, ldz, k, a, nullptr, H, hpart, final_gram, part_c,
@@ -251,7 +264,9 @@ struct Lanczos {
     const double t0 = now_s();
     const double u = sizeof(VT) == 8 ? std::ldexp(1.0, -52) : std::ldexp(1.0, -23);
     const double u_ro = p.ro_tol > 0 ? p.ro_tol : std::sqrt(u);
-    double norm_b = c->normA1_inf + p.eps * c->maxD;
+    // reading R7: a cheap upper bound of ||B|| until the first Ritz values exist
+    const double norm_t = (c->sym ? c->normA_inf : c->normA1_inf) + p.eps * c->maxD;
+    double norm_b = norm_t;
     double u_d = d * std::sqrt((double)n) * u * norm_b;
 
     // Q_1 = orth(Omega)
@@ -274,7 +289,6 @@ struct Lanczos {
     // diagnostics: NSP_NO_SPEED_STOP=1 runs until the matvec or cycle budget
     const char* ns = std::getenv("NSP_NO_SPEED_STOP");
     const bool no_speed_stop = ns && ns[0] == '1';
-    const double norm_t = c->normA1_inf + p.eps * c->maxD;  // bounds ||T|| <= ||B||
     double last_print = now_s();
     for (;;) {
       const double tc0 = now_s();
@@ -282,8 +296,7 @@ struct Lanczos {
       // ---- first step of the cycle: Q' = B Q_{l0+1}, Xi, QR((I - Z Z^T) Q')
       {
         const int blk = l0 + 1;
-        spmm_block<VT>(c, c->A, d, slot(blk), Y);
-        const int npx = spmmT_step<VT>(c, d, Y, slot(blk), nullptr, nullptr, P, part_xi);
+        const int npx = apply_b(slot(blk), nullptr, nullptr);
         cgs2_full(P, kk + d, false, nullptr);
         qr_step(blk, blk + 1, false, npx);
         w_reset(c, l0 + 1, 2, u_d, W, ldw);
@@ -297,9 +310,8 @@ struct Lanczos {
         const bool timed = prof.on && (ell % 4 == 0) && prof.used < Prof::kSlots;
         const int slot = prof.used;
         if (timed) NSP_HIP(hipEventRecord(prof.e(slot, 0), c->stream));
-        spmm_block<VT>(c, c->A, d, x, Y);
-        if (timed) NSP_HIP(hipEventRecord(prof.e(slot, 1), c->stream));
-        const int npx = spmmT_step<VT>(c, d, Y, x, xp, gam + (size_t)(ell - 1) * d * d, P, part_xi);
+        const int npx = apply_b(x, xp, gam + (size_t)(ell - 1) * d * d,
+                                timed ? prof.e(slot, 1) : nullptr);
         if (timed) NSP_HIP(hipEventRecord(prof.e(slot, 2), c->stream));
         const WArgs wa{ell, l0, ldw, u_d, u_ro, nrm_xi, nrm_gam, nrm_theta, nrm_f, W, flags, ro_hist};
         qr_step(ell, ell + 1, true, npx, &wa);
@@ -520,8 +532,10 @@ struct Refiner {
     if (p.tol_rel_resid > 0) tau = std::min(tau, p.tol_rel_resid * c->normA_fro / rk);
     if (p.tol_abs_resid > 0) tau = std::min(tau, p.tol_abs_resid);
     if (p.tol_angle > 0) {
+      // sigma_min(A) from the smallest Ritz value above 3 eps: B's eigenvalue
+      // there is sigma^2 (normal form) or sigma (symmetric form) plus at most eps max D
       const double s2 = st.theta_next - p.eps * c->maxD;
-      if (s2 > 0) tau = std::min(tau, p.tol_angle * std::sqrt(s2) / (2.0 * rk));
+      if (s2 > 0) tau = std::min(tau, p.tol_angle * (c->sym ? s2 : std::sqrt(s2)) / (2.0 * rk));
     }
     if (!std::isfinite(tau)) tau = 1e-10 * c->normA_fro / rk;
     std::vector<double> hs(k);

@@ -33,6 +33,9 @@ def _init(**kw):
     (dict(nnz=-1), "nnz"),
     (dict(max_matvec=0), "max_matvec"),
     (dict(prec=7), "precision"),
+    (dict(op=5), "op must be"),
+    (dict(reorder=3), "reorder"),
+    (dict(op=1, m=120, n=100), "square"),
 ])
 def test_invalid_arguments_are_rejected(kw, msg):
     from paper_2407_04634_amd import _lib

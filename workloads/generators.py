@@ -268,6 +268,9 @@ def config(name: str, scale: str = "full") -> CSR:
         return rgg_coboundary(20000 if small else 1_000_000, 8.0)
     if name == "zipf4m":
         return zipf_component_laplacian(40000 if small else 4_000_000, 10 if small else 1000, 10.0)
+    if name == "zipf400k":  # the 4M-vertex Laplacian's construction at a tenth of the size
+        return zipf_component_laplacian(4000 if small else 400_000, 10 if small else 100, 10.0,
+                                        seed=BASE_SEED + 6)
     if name == "planted200k":
         return (planted_nullity(4000, 4000, 8, seed=BASE_SEED + 5) if small
                 else planted_nullity(200000, 200000, 64, seed=BASE_SEED + 5))
