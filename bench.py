@@ -211,6 +211,49 @@ def spmv_hbm(name, prec, d=1, max_dim=64, reorder=1):
             "bytes_pair": a_b + at_b, "achieved_gbs": gbs, "frac_hbm": gbs / HBM_PEAK_GBS}
 
 
+def mixed_vs_fp64(name="zipf400k", max_dim=256, eps=1e-2):
+    """Mixed precision against plain FP64 at equal accuracy.
+
+    The Laplacian workload in the symmetric form B = L + eps D (Sec. 5.1), d = 1:
+    one full solve per precision, each refined in FP64 to the same targets and
+    checked against the closed-form null space (component indicators).
+    """
+    import torch
+    from paper_2407_04634_amd import Context, OP_SYM, PREC_FP64, PREC_MIXED
+    from workloads import generators as G
+
+    c = G.config(name)
+    v0 = torch.from_numpy(closed_form_basis(c)).cuda()
+    rp, ci, va = (torch.from_numpy(c.rowptr).cuda(), torch.from_numpy(c.colind).cuda(),
+                  torch.from_numpy(c.vals).cuda())
+    dv = torch.from_numpy(G.perturbation_diagonal(c.n, 1)).cuda()
+    om = torch.from_numpy(np.ascontiguousarray(G.gaussian_start_block(c.n, 1, 1))).cuda()
+    runs = []
+    for prec in ("fp64", "mixed"):
+        ctx = Context(rp, ci, va, c.m, c.n, D=dv, Omega=om, eps=eps, d=1, max_dim=max_dim, op=OP_SYM,
+                      prec=PREC_MIXED if prec == "mixed" else PREC_FP64, tol_angle=1e-9,
+                      tol_rel_resid=1e-10, max_matvec=5_000_000)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        st = ctx.lanczos_run()
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        v = ctx.extract_basis().contiguous()
+        sine = max_sine(v, v0) if v.shape[1] == v0.shape[1] else 1.0
+        runs.append({"prec": prec, "s": t1 - t0, "nullity": st["nullity"], "max_sin_angle": sine,
+                     "rel_resid_fro": st["rel_resid_fro"], "matvecs": st["matvecs"],
+                     "reorths": st["reorths"], "t_lanczos_s": st["t_lanczos_s"],
+                     "t_restart_s": st["t_restart_s"], "t_refine_s": st["t_refine_s"],
+                     "refine_iters": st["refine_iters"],
+                     "valid": bool(st["nullity"] == v0.shape[1] and sine <= 1e-8
+                                   and st["rel_resid_fro"] <= 1e-8)})
+        print(f"[bench] mixed_vs_fp64 {json.dumps(runs[-1])}", file=sys.stderr, flush=True)
+        ctx.close()
+    return {"workload": name, "n": c.n, "nnz": c.nnz, "nullity": v0.shape[1], "op": "B = L + eps D",
+            "d": 1, "max_dim": max_dim, "eps": eps, "runs": runs,
+            "speedup_mixed": runs[0]["s"] / runs[1]["s"]}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -228,6 +271,8 @@ def main():
                     help="HIP-event timing of the SpMV and reorthogonalisation kernels")
     ap.add_argument("--spmv-workload", default="zipf4m,coboundary1m",
                     help="comma-separated large matrices for the SpMV HBM measurement ('none' to skip)")
+    ap.add_argument("--mixed-workload", default="zipf400k",
+                    help="Laplacian for the mixed-vs-FP64 comparison ('none' to skip)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run the plain copy that scales the rocprofv3 byte counters")
     args = ap.parse_args()
@@ -327,6 +372,8 @@ def main():
         for r in sp:
             print(f"[bench] spmv {json.dumps(r)}", file=sys.stderr, flush=True)
         line["spmv_hbm"] = sp
+    if args.mixed_workload != "none":
+        line["mixed_vs_fp64"] = mixed_vs_fp64(args.mixed_workload)
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(c, eps, args.d, max_dim, st)
     print(json.dumps(line), flush=True)

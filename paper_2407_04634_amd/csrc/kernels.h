@@ -13,9 +13,11 @@ template <typename VT>
 int spmmT_step(nsp_ctx* c, int d, const VT* y, const VT* x, const VT* xp, const double* gprev,
                VT* out, double* part_xi);
 // Y = A X for row-major blocks of k columns; with ``part`` (kWideBlocks x k
-// doubles) it also leaves per-block column sums of Y^2 there and returns the
-// number of blocks for reduce_parts.
-int spmm_wide(nsp_ctx* c, const Csr& a, int k, const double* x, double* y, double* part = nullptr);
+// doubles) it also leaves per-block column sums there — of Y^2, or with
+// ``dot`` (square A) of Y .* X — and returns the number of blocks for
+// reduce_parts.
+int spmm_wide(nsp_ctx* c, const Csr& a, int k, const double* x, double* y, double* part = nullptr,
+              bool dot = false);
 // out[v] = sum_b part[b * nv + v] (fixed order)
 void reduce_parts(nsp_ctx* c, int nparts, int nv, const double* part, double* out);
 void sddmm(nsp_ctx* c, int k, const double* u, const double* v, double* grad);

@@ -74,18 +74,17 @@ __device__ double fro(int k, const double* a) {
 // ---------------------------------------------------------------------------
 __device__ void wrec_block(const WArgs& a, double gi, double* red) {
   const int t = threadIdx.x, ell = a.ell, l0 = a.l0;
+  const int lane = t % kWave, wid = t / kWave, nw = blockDim.x / kWave;
   double* w = a.w;
   const int ldw = a.ldw;
   auto W = [&](int k, int j) -> double& { return w[k + (int64_t)j * ldw]; };
   double s = 0.0;
   for (int i = 1 + t; i <= l0; i += blockDim.x) s += W(i, ell) * a.n_f[i];
-  red[t] = s;
+  s = wave_sum(s);
+  if (lane == 0) red[wid] = s;
   __syncthreads();
-  for (int off = blockDim.x / 2; off > 0; off >>= 1) {
-    if (t < off) red[t] += red[t + off];
-    __syncthreads();
-  }
-  const double sum_f = red[0];
+  double sum_f = 0.0;
+  for (int q = 0; q < nw; ++q) sum_f += red[q];
   __syncthreads();
   double mx = 0.0;
   for (int k = 1 + t; k <= ell; k += blockDim.x) {
@@ -105,15 +104,15 @@ __device__ void wrec_block(const WArgs& a, double gi, double* red) {
       v = gi * acc;
     }
     W(k, ell + 1) = v;
-    if (k < ell) mx = fmax(mx, v);
+    if (k < ell) mx = (v == v) ? fmax(mx, v) : INFINITY;  // a NaN bound forces a reorthogonalisation
   }
-  red[t] = mx;
+#pragma unroll
+  for (int off = kWave / 2; off > 0; off >>= 1) mx = fmax(mx, __shfl_xor(mx, off, kWave));
+  if (lane == 0) red[wid] = mx;
   __syncthreads();
-  for (int off = blockDim.x / 2; off > 0; off >>= 1) {
-    if (t < off) red[t] = fmax(red[t], red[t + off]);
-    __syncthreads();
-  }
-  const bool need = red[0] > a.u_ro || !(red[0] == red[0]);
+  double m = 0.0;
+  for (int q = 0; q < nw; ++q) m = fmax(m, red[q]);
+  const bool need = m > a.u_ro;
   __syncthreads();
   if (need) {
     for (int k = 1 + t; k < ell; k += blockDim.x) W(k, ell) = a.u_d;
@@ -164,27 +163,32 @@ __global__ __launch_bounds__(kThreads) void k_sub_gram(int64_t n, VT* __restrict
   for (int i = 0; i < NV; ++i) g[i] = 0.0;
   for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < n;
        r += (int64_t)gridDim.x * blockDim.x) {
-    VT v[D];
+    double v[D];  // FP64 arithmetic, one rounding to the working precision on store
 #pragma unroll
     for (int j = 0; j < D; ++j) v[j] = p[r * D + j];
     if constexpr (SUB) {
-      VT xr[D];
+      double xr[D];
 #pragma unroll
       for (int j = 0; j < D; ++j) xr[j] = x[r * D + j];
+      double w[D];
 #pragma unroll
       for (int a = 0; a < D; ++a) {
-        VT s = v[a];
+        double s = v[a];
 #pragma unroll
-        for (int b = 0; b < D; ++b) s = fma(-xr[b], VT(xs[b + a * D]), s);
-        v[a] = s;
+        for (int b = 0; b < D; ++b) s = fma(-xr[b], xs[b + a * D], s);
+        w[a] = s;
       }
 #pragma unroll
-      for (int j = 0; j < D; ++j) p[r * D + j] = v[j];
+      for (int j = 0; j < D; ++j) {
+        const VT o = VT(w[j]);
+        p[r * D + j] = o;
+        v[j] = (double)o;
+      }
     }
 #pragma unroll
     for (int a = 0; a < D; ++a)
 #pragma unroll
-      for (int b = 0; b < D; ++b) g[a + b * D] += (double)v[a] * (double)v[b];
+      for (int b = 0; b < D; ++b) g[a + b * D] += v[a] * v[b];
   }
   block_sum<NV>(g, smem);
   if (threadIdx.x == 0) {
@@ -225,37 +229,39 @@ __global__ __launch_bounds__(kThreads) void k_scale(int64_t n, const VT* p,
     }
   }
   __syncthreads();
-  // the W-recurrence needs ||Gamma_ell^{-1}||; for d = 1 the QR is final here
+  // the W-recurrence needs ||Gamma_ell^{-1}||; for d = 1 the QR is final here.
+  // Block 0 runs it while the other blocks scale the rows.
   if constexpr (WREC) {
-    if (blockIdx.x == 0) wrec_block(wa, gi_s, smem);
+    if (blockIdx.x == 0) {
+      wrec_block(wa, gi_s, smem);
+      return;
+    }
   }
   constexpr int NG = GRAM ? NV : 1;
   double g[NG];
 #pragma unroll
   for (int i = 0; i < NG; ++i) g[i] = 0.0;
-  for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < n;
-       r += (int64_t)gridDim.x * blockDim.x) {
-    VT v[D], o[D];
+  const int b0 = WREC ? 1 : 0;
+  for (int64_t r = (int64_t)(blockIdx.x - b0) * blockDim.x + threadIdx.x; r < n;
+       r += (int64_t)(gridDim.x - b0) * blockDim.x) {
+    double v[D], o[D];  // FP64 arithmetic, one rounding on store
 #pragma unroll
     for (int j = 0; j < D; ++j) v[j] = p[r * D + j];
 #pragma unroll
     for (int a = 0; a < D; ++a) {
-      VT s = VT(0);
+      double s = 0.0;
 #pragma unroll
-      for (int b = 0; b <= a; ++b) s = fma(v[b], VT(ri[b + a * D]), s);
-      o[a] = s;
-    }
-#pragma unroll
-    for (int j = 0; j < D; ++j) xn[r * D + j] = o[j];
-    if (zcol) {
-#pragma unroll
-      for (int j = 0; j < D; ++j) zcol[r + j * ldz] = o[j];
+      for (int b = 0; b <= a; ++b) s = fma(v[b], ri[b + a * D], s);
+      const VT q = VT(s);
+      o[a] = (double)q;
+      xn[r * D + a] = q;
+      if (zcol) zcol[r + a * ldz] = q;
     }
     if constexpr (GRAM) {
 #pragma unroll
       for (int a = 0; a < D; ++a)
 #pragma unroll
-        for (int b = 0; b < D; ++b) g[a + b * D] += (double)o[a] * (double)o[b];
+        for (int b = 0; b < D; ++b) g[a + b * D] += o[a] * o[b];
     }
   }
   if constexpr (GRAM) {
@@ -318,25 +324,25 @@ __global__ __launch_bounds__(kThreads) void k_scale2(int64_t n, const double* __
   }
   __syncthreads();
   if constexpr (WREC) {
-    if (blockIdx.x == 0) wrec_block(wa, gi_s, smem);
+    if (blockIdx.x == 0) {
+      wrec_block(wa, gi_s, smem);
+      return;
+    }
   }
-  for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < n;
-       r += (int64_t)gridDim.x * blockDim.x) {
-    VT v[D], o[D];
+  const int b0 = WREC ? 1 : 0;
+  for (int64_t r = (int64_t)(blockIdx.x - b0) * blockDim.x + threadIdx.x; r < n;
+       r += (int64_t)(gridDim.x - b0) * blockDim.x) {
+    double v[D];  // FP64 arithmetic, one rounding on store
 #pragma unroll
     for (int j = 0; j < D; ++j) v[j] = xn[r * D + j];
 #pragma unroll
     for (int a = 0; a < D; ++a) {
-      VT s = VT(0);
+      double s = 0.0;
 #pragma unroll
-      for (int b = 0; b <= a; ++b) s = fma(v[b], VT(ri[b + a * D]), s);
-      o[a] = s;
-    }
-#pragma unroll
-    for (int j = 0; j < D; ++j) xn[r * D + j] = o[j];
-    if (zcol) {
-#pragma unroll
-      for (int j = 0; j < D; ++j) zcol[r + j * ldz] = o[j];
+      for (int b = 0; b <= a; ++b) s = fma(v[b], ri[b + a * D], s);
+      const VT q = VT(s);
+      xn[r * D + a] = q;
+      if (zcol) zcol[r + a * ldz] = q;
     }
   }
 }
@@ -907,8 +913,8 @@ int scale_block(nsp_ctx* c, int d, int64_t n, const VT* p, const double* part_g,
     if (part_g2)                                                                               \
       k_scale<VT, D, true, false><<<grid, kThreads, 0, c->stream>>>(n, p, part_g, nparts, xn,  \
           zcol, ldz, gam_out, nrm_gam, nrm_ginv, part_g2, flags, w);                           \
-    else if (wa)                                                                               \
-      k_scale<VT, D, false, true><<<grid, kThreads, 0, c->stream>>>(n, p, part_g, nparts, xn,  \
+    else if (wa) /* one extra block: block 0 runs the W-recurrence */                        \
+      k_scale<VT, D, false, true><<<grid + 1, kThreads, 0, c->stream>>>(n, p, part_g, nparts, xn, \
           zcol, ldz, gam_out, nrm_gam, nrm_ginv, part_g2, flags, w);                           \
     else                                                                                       \
       k_scale<VT, D, false, false><<<grid, kThreads, 0, c->stream>>>(n, p, part_g, nparts, xn, \
@@ -933,8 +939,8 @@ void scale_block2(nsp_ctx* c, int d, int64_t n, const double* part_g2, int npart
   if (wa) w = *wa;
 #define NSP_SC2(D)                                                                             \
   case D:                                                                                      \
-    if (wa)                                                                                    \
-      k_scale2<VT, D, true><<<grid, kThreads, 0, c->stream>>>(n, part_g2, nparts, xn, zcol,    \
+    if (wa) /* one extra block: block 0 runs the W-recurrence */                               \
+      k_scale2<VT, D, true><<<grid + 1, kThreads, 0, c->stream>>>(n, part_g2, nparts, xn, zcol, \
           ldz, gam, nrm_gam, nrm_ginv, flags, w);                                              \
     else                                                                                       \
       k_scale2<VT, D, false><<<grid, kThreads, 0, c->stream>>>(n, part_g2, nparts, xn, zcol,   \

@@ -29,23 +29,23 @@ __global__ __launch_bounds__(kThreads) void k_spmm(int64_t nrows, const int32_t*
   const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int64_t row = g / LPR;
   const int lane = threadIdx.x % LPR;
-  VT acc[D];
+  double acc[D];  // FP64 accumulation also for FP32 operands
 #pragma unroll
-  for (int j = 0; j < D; ++j) acc[j] = VT(0);
+  for (int j = 0; j < D; ++j) acc[j] = 0.0;
   if (row < nrows) {
     const int beg = rp[row], end = rp[row + 1];
     for (int p = beg + lane; p < end; p += LPR) {
-      const VT a = av[p];
+      const double a = av[p];
       const VT* xr = x + (int64_t)ci[p] * D;
 #pragma unroll
-      for (int j = 0; j < D; ++j) acc[j] = fma(a, xr[j], acc[j]);
+      for (int j = 0; j < D; ++j) acc[j] = fma(a, (double)xr[j], acc[j]);
     }
   }
 #pragma unroll
-  for (int j = 0; j < D; ++j) acc[j] = group_sum<VT, LPR>(acc[j]);
+  for (int j = 0; j < D; ++j) acc[j] = group_sum<double, LPR>(acc[j]);
   if (row < nrows && lane == 0) {
 #pragma unroll
-    for (int j = 0; j < D; ++j) y[row * D + j] = acc[j];
+    for (int j = 0; j < D; ++j) y[row * D + j] = VT(acc[j]);
   }
 }
 
@@ -77,44 +77,48 @@ __global__ __launch_bounds__(kThreads) void k_spmmT_step(
   // grid-stride over rows; the LPR lanes of a group always share ``row``
   for (int64_t row = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / LPR; row < nrows;
        row += rows_per_grid) {
-    VT acc[D];
+    double acc[D];  // FP64 accumulation also for FP32 operands
 #pragma unroll
-    for (int j = 0; j < D; ++j) acc[j] = VT(0);
+    for (int j = 0; j < D; ++j) acc[j] = 0.0;
     const int beg = rp[row], end = rp[row + 1];
     for (int p = beg + lane; p < end; p += LPR) {
-      const VT a = av[p];
+      const double a = av[p];
       const VT* yr = y + (int64_t)ci[p] * D;
 #pragma unroll
-      for (int j = 0; j < D; ++j) acc[j] = fma(a, yr[j], acc[j]);
+      for (int j = 0; j < D; ++j) acc[j] = fma(a, (double)yr[j], acc[j]);
     }
 #pragma unroll
-    for (int j = 0; j < D; ++j) acc[j] = group_sum<VT, LPR>(acc[j]);
+    for (int j = 0; j < D; ++j) acc[j] = group_sum<double, LPR>(acc[j]);
     if (lane == 0) {
-      const VT sd = VT(eps * dv[row]);
-      VT xr[D];
+      const double sd = eps * dv[row];
+      double xr[D];
 #pragma unroll
       for (int j = 0; j < D; ++j) xr[j] = x[row * D + j];
 #pragma unroll
       for (int j = 0; j < D; ++j) acc[j] = fma(sd, xr[j], acc[j]);
       if (PREV) {
-        VT pr[D];
+        double pr[D];
 #pragma unroll
         for (int j = 0; j < D; ++j) pr[j] = xp[row * D + j];
 #pragma unroll
         for (int a = 0; a < D; ++a) {
-          VT s = acc[a];
+          double s = acc[a];
 #pragma unroll
-          for (int b = 0; b < D; ++b) s = fma(-pr[b], VT(gp[a + b * D]), s);
+          for (int b = 0; b < D; ++b) s = fma(-pr[b], gp[a + b * D], s);
           acc[a] = s;
         }
       }
 #pragma unroll
-      for (int j = 0; j < D; ++j) out[row * D + j] = acc[j];
+      for (int j = 0; j < D; ++j) {
+        const VT o = VT(acc[j]);
+        out[row * D + j] = o;
+        acc[j] = (double)o;  // the Xi sums see the stored values
+      }
       if constexpr (XI) {
 #pragma unroll
         for (int a = 0; a < D; ++a)
 #pragma unroll
-          for (int b = 0; b < D; ++b) dots[a * D + b] += (double)xr[a] * (double)acc[b];
+          for (int b = 0; b < D; ++b) dots[a * D + b] += xr[a] * acc[b];
       }
     }
   }
@@ -131,9 +135,10 @@ __global__ __launch_bounds__(kThreads) void k_spmmT_step(
 // Y (rows x k, row-major) = A X (X: cols x k, row-major), many right-hand
 // sides.  One wavefront per row, grid-stride over rows; lane l owns columns
 // 4l .. 4l+3 of each 256-column panel, read as two 16-byte loads when k is even.
-// With SQ every block also writes partial column sums of Y^2, part[block * k + c],
+// With RED = 1 every block also writes partial column sums of Y^2, with RED = 2
+// of Y .* X(row, :) (square A: the operand's own row), part[block * k + c],
 // summed in block order by reduce_parts.
-template <bool VEC, bool SQ>
+template <bool VEC, int RED>
 __global__ __launch_bounds__(kThreads) void k_spmm_wide(int64_t nrows, int k,
                                                         const int32_t* __restrict__ rp,
                                                         const int32_t* __restrict__ ci,
@@ -143,6 +148,7 @@ __global__ __launch_bounds__(kThreads) void k_spmm_wide(int64_t nrows, int k,
                                                         double* __restrict__ part) {
   constexpr int CPL = 4;
   constexpr int NWB = kThreads / kWave;
+  constexpr bool SQ = RED != 0;
   __shared__ double red[SQ ? NWB : 1][SQ ? kWave * CPL : 1];
   const int lane = threadIdx.x % kWave, wid = threadIdx.x / kWave;
   const int64_t gw = (int64_t)blockIdx.x * NWB + wid;
@@ -184,9 +190,14 @@ __global__ __launch_bounds__(kThreads) void k_spmm_wide(int64_t nrows, int k,
           for (int t = 0; t < CPL; ++t)
             if (cb + t < k) yr[t] = acc[t];
         }
-        if constexpr (SQ) {
+        if constexpr (RED == 1) {
 #pragma unroll
           for (int t = 0; t < CPL; ++t) sq[t] = fma(acc[t], acc[t], sq[t]);
+        } else if constexpr (RED == 2) {
+          const double* xo = x + row * k + cb;
+#pragma unroll
+          for (int t = 0; t < CPL; ++t)
+            if (cb + t < k) sq[t] = fma(acc[t], xo[t], sq[t]);
         }
       }
     }
@@ -354,7 +365,7 @@ __global__ __launch_bounds__(kThreads) void k_csr_stream(
     double* __restrict__ part_xi) {
   constexpr int TILE = stream_tile(D);
   constexpr int NV = XI ? D * D : 1;
-  __shared__ VT prod[TILE * D];
+  __shared__ double prod[TILE * D];  // FP64 products also for FP32 operands
   __shared__ double gp[D * D];
   __shared__ double smem[(kThreads / kWave) * NV];
   const int t = threadIdx.x;
@@ -378,32 +389,32 @@ __global__ __launch_bounds__(kThreads) void k_csr_stream(
       // the matrix is read once per product: non-temporal loads keep it from
       // evicting the gathered operand rows out of L2
       for (int i = t; i < cnt; i += kThreads) {
-        const VT a = __builtin_nontemporal_load(av + e0 + i);
+        const double a = __builtin_nontemporal_load(av + e0 + i);
         const VT* xr = xin + (int64_t)__builtin_nontemporal_load(ci + e0 + i) * D;
 #pragma unroll
-        for (int j = 0; j < D; ++j) prod[i * D + j] = a * xr[j];
+        for (int j = 0; j < D; ++j) prod[i * D + j] = a * (double)xr[j];
       }
     } else {
-      VT acc[D];
+      double acc[D];
 #pragma unroll
-      for (int j = 0; j < D; ++j) acc[j] = VT(0);
+      for (int j = 0; j < D; ++j) acc[j] = 0.0;
       for (int i = t; i < cnt; i += kThreads) {
-        const VT a = av[e0 + i];
+        const double a = av[e0 + i];
         const VT* xr = xin + (int64_t)ci[e0 + i] * D;
 #pragma unroll
-        for (int j = 0; j < D; ++j) acc[j] = fma(a, xr[j], acc[j]);
+        for (int j = 0; j < D; ++j) acc[j] = fma(a, (double)xr[j], acc[j]);
       }
 #pragma unroll
       for (int j = 0; j < D; ++j) {
-        const VT v = wave_sum(acc[j]);
+        const double v = wave_sum(acc[j]);
         if (lane == 0) prod[wid * D + j] = v;
       }
     }
     __syncthreads();
     for (int r = r0 + t; r < r1; r += kThreads) {
-      VT s[D];
+      double s[D];
 #pragma unroll
-      for (int j = 0; j < D; ++j) s[j] = VT(0);
+      for (int j = 0; j < D; ++j) s[j] = 0.0;
       if (tiled) {
         const int pe = rp[r + 1] - e0;
         for (int p = rp[r] - e0; p < pe; ++p)
@@ -415,34 +426,38 @@ __global__ __launch_bounds__(kThreads) void k_csr_stream(
 #pragma unroll
           for (int j = 0; j < D; ++j) s[j] += prod[w * D + j];
       }
+      double xr[D];
       if constexpr (STEP) {
-        const VT sd = VT(eps * dv[r]);
-        VT xr[D];
+        const double sd = eps * dv[r];
 #pragma unroll
         for (int j = 0; j < D; ++j) xr[j] = x[(int64_t)r * D + j];
 #pragma unroll
         for (int j = 0; j < D; ++j) s[j] = fma(sd, xr[j], s[j]);
         if (PREV) {
-          VT pr[D];
+          double pr[D];
 #pragma unroll
           for (int j = 0; j < D; ++j) pr[j] = xp[(int64_t)r * D + j];
 #pragma unroll
           for (int a = 0; a < D; ++a) {
-            VT u = s[a];
+            double u = s[a];
 #pragma unroll
-            for (int q = 0; q < D; ++q) u = fma(-pr[q], VT(gp[a + q * D]), u);
+            for (int q = 0; q < D; ++q) u = fma(-pr[q], gp[a + q * D], u);
             s[a] = u;
           }
         }
-        if constexpr (XI) {
-#pragma unroll
-          for (int a = 0; a < D; ++a)
-#pragma unroll
-            for (int q = 0; q < D; ++q) dots[a * D + q] += (double)xr[a] * (double)s[q];
-        }
       }
 #pragma unroll
-      for (int j = 0; j < D; ++j) out[(int64_t)r * D + j] = s[j];
+      for (int j = 0; j < D; ++j) {
+        const VT o = VT(s[j]);
+        out[(int64_t)r * D + j] = o;
+        s[j] = (double)o;  // the Xi sums see the stored values
+      }
+      if constexpr (STEP && XI) {
+#pragma unroll
+        for (int a = 0; a < D; ++a)
+#pragma unroll
+          for (int q = 0; q < D; ++q) dots[a * D + q] += xr[a] * s[q];
+      }
     }
     __syncthreads();  // prod is rewritten by the next row block
   }
@@ -605,17 +620,17 @@ template int spmmT_step<double>(nsp_ctx*, int, const double*, const double*, con
 template int spmmT_step<float>(nsp_ctx*, int, const float*, const float*, const float*,
                                const double*, float*, double*);
 
-int spmm_wide(nsp_ctx* c, const Csr& a, int k, const double* x, double* y, double* part) {
+int spmm_wide(nsp_ctx* c, const Csr& a, int k, const double* x, double* y, double* part, bool dot) {
   if (a.rows == 0 || k == 0) return 0;
   static_assert(kThreads == 4 * kWave, "one 256-column panel per block");
+  if (dot) NSP_REQUIRE(a.rows == a.cols, "the fused x . Ax sums need a square A");
   const int grid = (int)std::min<int64_t>(nblocks(a.rows, kThreads / kWave), kWideBlocks);
   const bool vec = k % 2 == 0;
-#define NSP_W(V, S) k_spmm_wide<V, S><<<grid, kThreads, 0, c->stream>>>(a.rows, k, a.rowptr, a.colind, a.val, x, y, part)
-  if (part) {
-    if (vec) NSP_W(true, true); else NSP_W(false, true);
-  } else {
-    if (vec) NSP_W(true, false); else NSP_W(false, false);
-  }
+  const int red = part ? (dot ? 2 : 1) : 0;
+#define NSP_W(V, R) k_spmm_wide<V, R><<<grid, kThreads, 0, c->stream>>>(a.rows, k, a.rowptr, a.colind, a.val, x, y, part)
+#define NSP_WV(R) if (vec) NSP_W(true, R); else NSP_W(false, R)
+  if (red == 2) { NSP_WV(2); } else if (red == 1) { NSP_WV(1); } else { NSP_WV(0); }
+#undef NSP_WV
 #undef NSP_W
   NSP_HIP(hipGetLastError());
   return grid;

@@ -262,12 +262,19 @@ struct Lanczos {
     nsp_stats& st = c->stats;
     st = nsp_stats{};
     const double t0 = now_s();
-    const double u = sizeof(VT) == 8 ? std::ldexp(1.0, -52) : std::ldexp(1.0, -23);
+    // Reading R8: u of the working (storage) precision sets u_RO = sqrt(u).  The
+    // round-off of one step (Eq. "defmprd") is d sqrt(n) u ||B|| when all
+    // arithmetic is in that precision; the FP32 mode accumulates in FP64 and
+    // rounds each stored vector once, so its per-step error is d (sqrt(n) u64
+    // + u32) ||B||.
+    const double u64 = std::ldexp(1.0, -52), u32 = std::ldexp(1.0, -23);
+    const double u = sizeof(VT) == 8 ? u64 : u32;
     const double u_ro = p.ro_tol > 0 ? p.ro_tol : std::sqrt(u);
+    const double u_step = sizeof(VT) == 8 ? std::sqrt((double)n) * u64 : std::sqrt((double)n) * u64 + u32;
     // reading R7: a cheap upper bound of ||B|| until the first Ritz values exist
     const double norm_t = (c->sym ? c->normA_inf : c->normA1_inf) + p.eps * c->maxD;
     double norm_b = norm_t;
-    double u_d = d * std::sqrt((double)n) * u * norm_b;
+    double u_d = d * u_step * norm_b;
 
     // Q_1 = orth(Omega)
     cm_to_ri<double, VT>(c, n, d, c->omega.as<double>(), n, slot(1));
@@ -379,7 +386,7 @@ struct Lanczos {
       if (n_ell > kn) throw Error(NSP_ERR_ARG, "max_dim too small for the detected nullity");
       restart(kn, hev);
       norm_b = hev[K - 1];  // reading R7
-      u_d = d * std::sqrt((double)n) * u * norm_b;
+      u_d = d * u_step * norm_b;
       l0 = kn / d;
       st.restarts++;
       t_rr += now_s() - tc1;
@@ -522,9 +529,11 @@ struct Refiner {
     double *gamma = dots, *qq = dots + k, *gnew = dots + 2 * k, *sn2 = dots + 3 * k;
     NSP_HIP(hipMemsetAsync(x, 0, sizeof(double) * n * k, c->stream));
     spmm_wide(c, c->A, k, vr, sv);
-    spmm_wide(c, c->AT, k, sv, r);
-    NSP_HIP(hipMemcpyAsync(pp, r, sizeof(double) * n * k, hipMemcpyDeviceToDevice, c->stream));
-    coldots(c, n, k, r, r, gamma, part);
+    if (!c->sym) {
+      spmm_wide(c, c->AT, k, sv, r);
+      NSP_HIP(hipMemcpyAsync(pp, r, sizeof(double) * n * k, hipMemcpyDeviceToDevice, c->stream));
+      coldots(c, n, k, r, r, gamma, part);
+    }
     coldots(c, m, k, sv, sv, sn2, part);
     // per-column target: the smallest threshold of the enabled criteria
     const double rk = std::sqrt((double)k);
@@ -540,8 +549,9 @@ struct Refiner {
     if (!std::isfinite(tau)) tau = 1e-10 * c->normA_fro / rk;
     std::vector<double> hs(k);
     std::vector<int> ha(k);
-    auto update_active = [&]() -> bool {
-      NSP_HIP(hipMemcpyAsync(c->pin_d, sn2, sizeof(double) * k, hipMemcpyDeviceToHost, c->stream));
+    // per column ||A v_j||^2 (the residual norms) -> active flags
+    auto update_active = [&](const double* res2) -> bool {
+      NSP_HIP(hipMemcpyAsync(c->pin_d, res2, sizeof(double) * k, hipMemcpyDeviceToHost, c->stream));
       NSP_HIP(hipStreamSynchronize(c->stream));
       std::copy(c->pin_d, c->pin_d + k, hs.begin());
       bool any = false;
@@ -556,11 +566,38 @@ struct Refiner {
       return any;
     };
     int64_t it = 0;
-    bool any = update_active();
     const char* ve = std::getenv("NSP_VERBOSE");
     const bool verbose = ve && ve[0] == '1';
     double last_print = now_s();
+    if (c->sym) {
+      // Symmetric positive semi-definite A: CG on A x = A v from x = 0 stays in
+      // range(A) and converges to x = A^+ A v like CGLS, in about sqrt(kappa(A))
+      // instead of kappa(A) iterations; r = A (v - x) is the residual.
+      NSP_HIP(hipMemcpyAsync(r, sv, sizeof(double) * n * k, hipMemcpyDeviceToDevice, c->stream));
+      NSP_HIP(hipMemcpyAsync(pp, sv, sizeof(double) * n * k, hipMemcpyDeviceToDevice, c->stream));
+      coldots(c, n, k, r, r, gamma, part);
+    }
+    bool any = update_active(c->sym ? gamma : sn2);
     while (any && it < p.max_refine_iter) {
+      if (c->sym) {
+        // q = A p with p . q fused; x += alpha p, r -= alpha q; p = r + beta p
+        const int nq = spmm_wide(c, c->A, k, pp, q, part, true);
+        reduce_parts(c, nq, k, part, qq);
+        cg_wr(c, n, k, gamma, qq, act, x, pp, r, q);
+        coldots(c, n, k, r, r, gnew, part);
+        cgls_p(c, n, k, gnew, gamma, act, r, pp);
+        std::swap(gamma, gnew);
+        ++it;
+        if (it % 16 == 0) {
+          any = update_active(gamma);
+          if (verbose && now_s() - last_print > 2.0) {
+            std::fprintf(stderr, "[nsp] refine (CG) it %lld\n", (long long)it);
+            std::fflush(stderr);
+            last_print = now_s();
+          }
+        }
+        continue;
+      }
       // q = A p with its column norms fused; r = A^T s likewise
       const int nq = spmm_wide(c, c->A, k, pp, q, part);
       reduce_parts(c, nq, k, part, qq);
@@ -572,7 +609,7 @@ struct Refiner {
       ++it;
       if (it % 16 == 0) {
         coldots(c, m, k, sv, sv, sn2, part);
-        any = update_active();
+        any = update_active(sn2);
         if (verbose && now_s() - last_print > 2.0) {
           int na = 0;
           double mx = 0.0;
