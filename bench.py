@@ -254,6 +254,30 @@ def mixed_vs_fp64(name="zipf400k", max_dim=256, eps=1e-2):
             "speedup_mixed": runs[0]["s"] / runs[1]["s"]}
 
 
+def backward_at_scale(ctx, n, nnz, v, tol=1e-10):
+    """The backward pass after the timed solve.
+
+    L = ||P X||_F^2 for a seeded Gaussian X (n x 8), G_s V = X (X^T V); the
+    library returns dL/dA for every stored value (range CG on A^T A, then the
+    SDDMM).  Its parity with the dense closed form is tested on the 300 x 280
+    instance; here it is timed at the bench workload's size.
+    """
+    import torch
+    from workloads import generators as G
+
+    x = torch.from_numpy(np.ascontiguousarray(G.gaussian_matrix(n, 8, seed=5))).cuda()
+    gsv = x @ (x.T @ v)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    grad, iters = ctx.backward(gsv, tol=tol)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    g = grad.double()
+    return {"loss": "||P X||_F^2, X seeded N(0,1) n x 8", "cg_tol": tol, "cg_iters": iters,
+            "s": t1 - t0, "grad_norm": float(torch.linalg.norm(g)),
+            "finite": bool(torch.isfinite(g).all()), "nnz": nnz, "rhs_columns": int(v.shape[1])}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -273,6 +297,7 @@ def main():
                     help="comma-separated large matrices for the SpMV HBM measurement ('none' to skip)")
     ap.add_argument("--mixed-workload", default="zipf400k",
                     help="Laplacian for the mixed-vs-FP64 comparison ('none' to skip)")
+    ap.add_argument("--no-backward", action="store_true", help="skip the backward pass after the solve")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run the plain copy that scales the rocprofv3 byte counters")
     args = ap.parse_args()
@@ -345,7 +370,7 @@ def main():
         "accuracy": {"nullity": st["nullity"], "nullity_exact": v0.shape[1],
                      "rel_resid_fro": st["rel_resid_fro"], "max_sin_angle": sine,
                      "orth_err_fro": st["orth_err_fro"]},
-        "solver": {k: st[k] for k in ("matvecs", "restarts", "reorths", "refine_iters",
+        "solver": {k: st[k] for k in ("matvecs", "restarts", "reorths", "refine_iters", "refine_defl",
                                       "t_lanczos_s", "t_restart_s", "t_refine_s", "theta_next")},
     }
     esize = 4 if args.prec == "mixed" else 8
@@ -372,6 +397,9 @@ def main():
         for r in sp:
             print(f"[bench] spmv {json.dumps(r)}", file=sys.stderr, flush=True)
         line["spmv_hbm"] = sp
+    if not args.no_backward and not partial:
+        line["backward"] = backward_at_scale(ctx, c.n, c.nnz, v)
+        print(f"[bench] backward {json.dumps(line['backward'])}", file=sys.stderr, flush=True)
     if args.mixed_workload != "none":
         line["mixed_vs_fp64"] = mixed_vs_fp64(args.mixed_workload)
     if not args.no_cpu_baseline:

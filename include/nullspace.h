@@ -137,6 +137,7 @@ typedef struct {
                               return at once), ms                                    */
   int64_t ro_samples;      /* profile: number of sampled steps                         */
   int64_t ro_active;       /* profile: how many of them reorthogonalised               */
+  int64_t refine_defl;     /* Ritz vectors deflating the refinement's CGLS (0: none)  */
 } nsp_stats;
 
 /* Fill *p with defaults: eps = 1e-3 (Sec. 5.3), d = 1, max_dim = 64,

@@ -79,6 +79,7 @@ class Stats(ctypes.Structure):
         ("ro_idle_ms", ctypes.c_double),
         ("ro_samples", ctypes.c_int64),
         ("ro_active", ctypes.c_int64),
+        ("refine_defl", ctypes.c_int64),
     ]
 
     def as_dict(self) -> dict:

@@ -72,6 +72,7 @@ struct DBuf {
 constexpr int kMaxD = 8;            // largest supported block size
 constexpr int kRedBlocks = 512;     // grid cap of kernels that write per-block partials
 constexpr int kWideBlocks = 1024;   // grid cap of the many-column SpMM (its partials: x k)
+constexpr int kDeflMax = 256;       // deflation vectors of the refinement (at most)
 constexpr int kXcds = 8;            // accelerator complex dies; workgroups go round-robin over them
 constexpr int kStreamBlocks = 2048; // grid cap of the streaming SpMV
 constexpr int64_t kStreamMinNnz = 1 << 21;  // smaller matrices use the lanes-per-row kernels
@@ -168,6 +169,8 @@ struct nsp_ctx {
 
   // result
   nsp::DBuf V;              // n x N column-major FP64 (final basis)
+  nsp::DBuf Wd;             // n x defl_r column-major FP64: the Ritz vectors just above
+  int32_t defl_r = 0;       // the null cluster, deflation space of the refinement
   int32_t nullity = 0;
   int state = 0;            // 0 = initialised, 1 = basis available
   std::vector<double> ritz; // last Ritz values (host)

@@ -82,6 +82,32 @@ void sgemm(nsp_ctx* c, rocblas_operation ta, rocblas_operation tb, int64_t m, in
 
 // symmetric eigen-decomposition on the device (FP64): A (k x k) is replaced by
 // its eigenvectors, w receives the eigenvalues ascending.
+// out (m1 x m2, column-major) = A B^T for column-major A (m1 x rows, ld lda)
+// and B (m2 x rows, ld ldb): a long inner dimension with a small output, as in
+// the Gram and projection products of the refinement and backward.  One GEMM
+// would run on a few workgroups, so the rows are cut into chunks computed by
+// one strided-batched GEMM and the partial products are summed in chunk order.
+void dgemm_nt_long(nsp_ctx* c, int64_t m1, int64_t m2, int64_t rows, const double* a, int64_t lda,
+                   const double* b, int64_t ldb, double* out, DBuf& work) {
+  const int64_t nch = std::min<int64_t>(64, std::max<int64_t>(1, rows / 2048));
+  if (nch == 1) {
+    dgemm(c, rocblas_operation_none, rocblas_operation_transpose, m1, m2, rows, 1.0, a, lda, b, ldb,
+          0.0, out, m1);
+    return;
+  }
+  const int64_t cs = rows / nch, rem = rows - cs * nch, np = nch + (rem > 0 ? 1 : 0);
+  double* part = alloc_as<double>(work, (size_t)(np * m1 * m2));
+  const double one = 1.0, zero = 0.0;
+  NSP_BLAS(rocblas_dgemm_strided_batched(c->blas, rocblas_operation_none, rocblas_operation_transpose,
+                                         (rocblas_int)m1, (rocblas_int)m2, (rocblas_int)cs, &one, a,
+                                         (rocblas_int)lda, cs * lda, b, (rocblas_int)ldb, cs * ldb,
+                                         &zero, part, (rocblas_int)m1, m1 * m2, (rocblas_int)nch));
+  if (rem)
+    dgemm(c, rocblas_operation_none, rocblas_operation_transpose, m1, m2, rem, 1.0, a + cs * nch * lda,
+          lda, b + cs * nch * ldb, ldb, 0.0, part + nch * m1 * m2, m1);
+  reduce_parts(c, (int)np, (int)(m1 * m2), part, out);
+}
+
 void syevd(nsp_ctx* c, int k, double* a, double* w, DBuf& ework, DBuf& info) {
   double* e = alloc_as<double>(ework, k);
   rocblas_int* inf = alloc_as<rocblas_int>(info, 1);
@@ -449,19 +475,36 @@ struct Lanczos {
   }
 
   // V = Z(:, 0:K) V_Z(:, 0:N) in FP64, column-major n x N
+  // out (n x cols, FP64) = Z V_Z(:, col0 : col0 + cols)
+  void ritz_vectors(int col0, int cols, double* out) {
+    if constexpr (sizeof(VT) == 8) {
+      dgemm(c, rocblas_operation_none, rocblas_operation_none, n, cols, K, 1.0, (const double*)Z, ldz,
+            T + (size_t)col0 * K, K, 0.0, out, n);
+    } else {
+      float* vz = alloc_as<float>(b_vzf, (size_t)K * cols);
+      convert<double, float>(c, (int64_t)K * cols, T + (size_t)col0 * K, vz);
+      float* tmp = alloc_as<float>(b_tmpv, (size_t)n * cols);
+      sgemm(c, rocblas_operation_none, rocblas_operation_none, n, cols, K, 1.0f, (const float*)Z, ldz,
+            vz, K, 0.0f, tmp, n);
+      convert<float, double>(c, (int64_t)n * cols, tmp, out);
+    }
+  }
+
   void extract(int nul) {
     double* v = alloc_as<double>(c->V, (size_t)n * std::max(nul, 1));
+    c->defl_r = 0;
     if (nul == 0) return;
-    if constexpr (sizeof(VT) == 8) {
-      dgemm(c, rocblas_operation_none, rocblas_operation_none, n, nul, K, 1.0, (const double*)Z, ldz,
-            T, K, 0.0, v, n);
-    } else {
-      float* vz = alloc_as<float>(b_vzf, (size_t)K * nul);
-      convert<double, float>(c, (int64_t)K * nul, T, vz);
-      float* tmp = alloc_as<float>(b_tmpv, (size_t)n * nul);
-      sgemm(c, rocblas_operation_none, rocblas_operation_none, n, nul, K, 1.0f, (const float*)Z, ldz,
-            vz, K, 0.0f, tmp, n);
-      convert<float, double>(c, (int64_t)n * nul, tmp, v);
+    ritz_vectors(0, nul, v);
+    // The next Ritz vectors (smallest nonzero part of the spectrum) deflate the
+    // refinement's CGLS: they are the directions it converges slowest along.
+    if (c->prm.refine && !c->sym) {
+      const int64_t budget = (int64_t)1 << 29;  // bytes for each of its four n x r blocks
+      const int r = (int)std::min<int64_t>({(int64_t)kDeflMax, (int64_t)K - nul - d,
+                                           budget / (8 * std::max<int64_t>(n, m))});
+      if (r >= 8) {
+        ritz_vectors(nul, r, alloc_as<double>(c->Wd, (size_t)n * r));
+        c->defl_r = r;
+      }
     }
   }
 };
@@ -475,13 +518,73 @@ struct Refiner {
   int64_t n, m;
   int k;
   DBuf b_vr, b_u, b_x, b_s, b_r, b_p, b_q, b_small, b_small2, b_part, b_dots, b_act, b_info, b_e;
+  DBuf b_long;  // partial products of dgemm_nt_long
 
   Refiner(nsp_ctx* ctx, int nul) : c(ctx), n(ctx->n), m(ctx->m), k(nul) {}
+
+  // Deflation space of the CGLS (normal form), from the Ritz vectors just
+  // above the null cluster: after a Rayleigh-Ritz rotation with A^T A,
+  // W^T A^T A W = Lambda.  Kept as row-major blocks: W (n x rd), AW (m x rd),
+  // AWs = AW Lambda^-1 (m x rd) and MWs = A^T AWs (n x rd).  Deflated CG
+  // (x0 = W Lambda^-1 W^T b, search directions made A^T A-orthogonal to W)
+  // then converges at the rate of the spectrum above the deflated part.
+  int rd = 0;
+  double *dW = nullptr, *dAW = nullptr, *dAWs = nullptr, *dMWs = nullptr;
+  DBuf b_dw0, b_daw0, b_dw, b_daw, b_daws, b_dmws, b_dmu, b_dS, b_dl, b_dei, b_dinf, b_dU, b_dUL;
+
+  void setup_deflation() {
+    const int r = c->defl_r;
+    if (r <= 0) return;
+    double* w0 = alloc_as<double>(b_dw0, (size_t)n * r);
+    colmajor_to_rows(c, n, r, c->Wd.as<double>(), n, w0);
+    double* aw0 = alloc_as<double>(b_daw0, (size_t)m * r);
+    spmm_wide(c, c->A, r, w0, aw0);
+    double* S = alloc_as<double>(b_dS, (size_t)r * r);
+    dgemm_nt_long(c, r, r, m, aw0, r, aw0, r, S, b_long);
+    double* lam = alloc_as<double>(b_dl, r);
+    syevd(c, r, S, lam, b_dei, b_dinf);
+    std::vector<double> hl(r), hu((size_t)r * r);
+    NSP_HIP(hipMemcpy(hl.data(), lam, sizeof(double) * r, hipMemcpyDeviceToHost));
+    NSP_HIP(hipMemcpy(hu.data(), S, sizeof(double) * r * r, hipMemcpyDeviceToHost));
+    const double lmax = hl[r - 1];
+    std::vector<int> keep;
+    for (int i = 0; i < r; ++i)
+      if (std::isfinite(hl[i]) && hl[i] > 1e-12 * lmax) keep.push_back(i);
+    const int rk = (int)keep.size();
+    if (rk == 0) return;
+    std::vector<double> uk((size_t)r * rk), ul((size_t)r * rk);
+    for (int j = 0; j < rk; ++j)
+      for (int i = 0; i < r; ++i) {
+        uk[i + (size_t)j * r] = hu[i + (size_t)keep[j] * r];
+        ul[i + (size_t)j * r] = hu[i + (size_t)keep[j] * r] / hl[keep[j]];
+      }
+    double* du = alloc_as<double>(b_dU, (size_t)r * rk);
+    double* dul = alloc_as<double>(b_dUL, (size_t)r * rk);
+    NSP_HIP(hipMemcpy(du, uk.data(), sizeof(double) * uk.size(), hipMemcpyHostToDevice));
+    NSP_HIP(hipMemcpy(dul, ul.data(), sizeof(double) * ul.size(), hipMemcpyHostToDevice));
+    // rotated blocks (column-major views X_cm = rows^T): W_cm = U^T W0_cm, ...
+    dW = alloc_as<double>(b_dw, (size_t)n * rk);
+    dAW = alloc_as<double>(b_daw, (size_t)m * rk);
+    dAWs = alloc_as<double>(b_daws, (size_t)m * rk);
+    dMWs = alloc_as<double>(b_dmws, (size_t)n * rk);
+    dgemm(c, rocblas_operation_transpose, rocblas_operation_none, rk, n, r, 1.0, du, r, w0, r, 0.0, dW, rk);
+    dgemm(c, rocblas_operation_transpose, rocblas_operation_none, rk, m, r, 1.0, du, r, aw0, r, 0.0, dAW, rk);
+    dgemm(c, rocblas_operation_transpose, rocblas_operation_none, rk, m, r, 1.0, dul, r, aw0, r, 0.0, dAWs, rk);
+    spmm_wide(c, c->AT, rk, dAWs, dMWs);
+    rd = rk;
+  }
+
+  // p -= W Lambda^-1 (A^T A W)^T r  (column-major views: mu = r_cm MWs_cm^T)
+  void deflate_direction(const double* r, double* p) {
+    double* mu = alloc_as<double>(b_dmu, (size_t)k * rd);
+    dgemm_nt_long(c, k, rd, n, r, k, dMWs, rd, mu, b_long);
+    dgemm(c, rocblas_operation_none, rocblas_operation_none, k, n, rd, -1.0, mu, k, dW, rd, 1.0, p, k);
+  }
 
   // row-major n x k  <->  column-major k x n view with ld k
   void gram_rows(const double* a, int64_t rows, double* g) {
     // G = A^T A for row-major A (rows x k): column-major view Acm (k x rows)
-    dgemm(c, rocblas_operation_none, rocblas_operation_transpose, k, k, rows, 1.0, a, k, a, k, 0.0, g, k);
+    dgemm_nt_long(c, k, k, rows, a, k, a, k, g, b_long);
   }
 
   void cholqr(double* vr) {
@@ -530,8 +633,17 @@ struct Refiner {
     NSP_HIP(hipMemsetAsync(x, 0, sizeof(double) * n * k, c->stream));
     spmm_wide(c, c->A, k, vr, sv);
     if (!c->sym) {
+      setup_deflation();
+      if (rd > 0) {
+        // x0 = W Lambda^-1 (A W)^T s0, s = s0 - A x0
+        double* mu = alloc_as<double>(b_dmu, (size_t)k * rd);
+        dgemm_nt_long(c, k, rd, m, sv, k, dAWs, rd, mu, b_long);
+        dgemm(c, rocblas_operation_none, rocblas_operation_none, k, n, rd, 1.0, mu, k, dW, rd, 0.0, x, k);
+        dgemm(c, rocblas_operation_none, rocblas_operation_none, k, m, rd, -1.0, mu, k, dAW, rd, 1.0, sv, k);
+      }
       spmm_wide(c, c->AT, k, sv, r);
       NSP_HIP(hipMemcpyAsync(pp, r, sizeof(double) * n * k, hipMemcpyDeviceToDevice, c->stream));
+      if (rd > 0) deflate_direction(r, pp);
       coldots(c, n, k, r, r, gamma, part);
     }
     coldots(c, m, k, sv, sv, sn2, part);
@@ -605,6 +717,7 @@ struct Refiner {
       const int nr = spmm_wide(c, c->AT, k, sv, r, part);
       reduce_parts(c, nr, k, part, gnew);
       cgls_p(c, n, k, gnew, gamma, act, r, pp);
+      if (rd > 0) deflate_direction(r, pp);
       std::swap(gamma, gnew);  // the new gamma is the next iteration's old one
       ++it;
       if (it % 16 == 0) {
@@ -622,6 +735,7 @@ struct Refiner {
       }
     }
     st.refine_iters = it;
+    st.refine_defl = rd;
     sub_inplace(c, n * k, vr, x);
     // Step 3: orthonormalise (Cholesky QR twice), residual and orthogonality
     cholqr(vr);
@@ -703,67 +817,122 @@ void run_backward(nsp_ctx* c, const double* GsV, int64_t ld, double* grad, doubl
     NSP_HIP(hipStreamSynchronize(c->stream));
   }
   // R = G - V (V^T G)
+  DBuf b_long;
   double* mm = alloc_as<double>(b_mm, (size_t)k * k);
-  dgemm(c, rocblas_operation_none, rocblas_operation_transpose, k, k, n, 1.0, vr, k, r, k, 0.0, mm, k);
+  dgemm_nt_long(c, k, k, n, vr, k, r, k, mm, b_long);
   dgemm(c, rocblas_operation_transpose, rocblas_operation_none, k, n, k, -1.0, mm, k, vr, k, 1.0, r, k);
-  double* w = alloc_as<double>(b_w, (size_t)n * k);
-  double* pp = alloc_as<double>(b_p, (size_t)n * k);
-  double* q = alloc_as<double>(b_q, (size_t)n * k);
-  double* y = alloc_as<double>(b_y, (size_t)m * k);
-  double* dots = alloc_as<double>(b_dots, (size_t)3 * k);
-  double* part = alloc_as<double>(b_part, (size_t)coldots_parts(std::max(n, m)) * k);
-  int* act = alloc_as<int>(b_act, k);
-  double *rr = dots, *pq = dots + k, *rnew = dots + 2 * k;
-  NSP_HIP(hipMemsetAsync(w, 0, sizeof(double) * n * k, c->stream));
-  NSP_HIP(hipMemcpyAsync(pp, r, sizeof(double) * n * k, hipMemcpyDeviceToDevice, c->stream));
-  coldots(c, n, k, r, r, rr, part);
-  std::vector<double> r0(k), hr(k);
-  std::vector<int> ha(k);
-  NSP_HIP(hipMemcpyAsync(c->pin_d, rr, sizeof(double) * k, hipMemcpyDeviceToHost, c->stream));
+  // The solve only needs the range of R: R^T R = Y S^2 Y^T, keep the kr
+  // directions with s^2 > 1e-13 s_max^2 (the eigenvalues of the Gram matrix
+  // carry an absolute error of a few u s_max^2, so smaller ones are noise),
+  // U = (I - V V^T) R Y_r S_r^{-1}, solve A^T A W_U = U and recombine
+  // W = W_U S_r Y_r^T.  A loss of low rank (e.g. ||P X||_F^2 with X of a few
+  // columns) needs only that many CG columns.
+  DBuf b_eg, b_ew, b_ei, b_einfo, b_u, b_cr;
+  double* eg = alloc_as<double>(b_eg, (size_t)k * k);
+  double* ew = alloc_as<double>(b_ew, (size_t)k);
+  dgemm_nt_long(c, k, k, n, r, k, r, k, eg, b_long);
+  syevd(c, k, eg, ew, b_ei, b_einfo);
+  std::vector<double> lam(k), yv((size_t)k * k);
+  NSP_HIP(hipMemcpy(lam.data(), ew, sizeof(double) * k, hipMemcpyDeviceToHost));
+  NSP_HIP(hipMemcpy(yv.data(), eg, sizeof(double) * k * k, hipMemcpyDeviceToHost));
+  for (double v : lam)
+    if (!std::isfinite(v)) throw Error(NSP_ERR_NONFINITE, "non-finite value in G_s V");
+  const double lmax = std::max(lam[k - 1], 0.0);
+  int kr = 0;
+  while (kr < k && lam[k - 1 - kr] > 1e-13 * lmax && lam[k - 1 - kr] > 0.0) ++kr;
+  if (kr == 0) {  // R = 0: the loss does not move the null space
+    if (c->nnz) NSP_HIP(hipMemsetAsync(grad, 0, sizeof(double) * c->nnz, c->stream));
+    NSP_HIP(hipStreamSynchronize(c->stream));
+    return;
+  }
+  // Ys = Y_r S_r^{-1} (k x kr) and C = S_r Y_r^T (kr x k), column-major
+  std::vector<double> ys((size_t)k * kr), cr((size_t)kr * k);
+  for (int j = 0; j < kr; ++j) {
+    const int col = k - 1 - j;
+    const double sv = std::sqrt(lam[col]);
+    for (int i = 0; i < k; ++i) {
+      ys[i + (size_t)j * k] = yv[i + (size_t)col * k] / sv;
+      cr[j + (size_t)i * kr] = sv * yv[i + (size_t)col * k];
+    }
+  }
+  double* ysd = alloc_as<double>(b_eg, (size_t)k * kr);
+  double* crd = alloc_as<double>(b_cr, (size_t)kr * k);
+  NSP_HIP(hipMemcpy(ysd, ys.data(), sizeof(double) * ys.size(), hipMemcpyHostToDevice));
+  NSP_HIP(hipMemcpy(crd, cr.data(), sizeof(double) * cr.size(), hipMemcpyHostToDevice));
+  // U (row-major n x kr) = R Ys: column-major views Ucm (kr x n) = Ys^T Rcm
+  double* u = alloc_as<double>(b_u, (size_t)n * kr);
+  dgemm(c, rocblas_operation_transpose, rocblas_operation_none, kr, n, k, 1.0, ysd, k, r, k, 0.0, u, kr);
+  NSP_HIP(hipMemcpyAsync(r, u, sizeof(double) * n * kr, hipMemcpyDeviceToDevice, c->stream));
+  const int kc = kr;  // CG columns
+  {
+    // U -= V (V^T U): rounding in R leaves null-space components CG cannot reduce
+    double* vu = alloc_as<double>(b_mm, (size_t)k * kc);
+    dgemm_nt_long(c, k, kc, n, vr, k, r, kc, vu, b_long);
+    dgemm(c, rocblas_operation_transpose, rocblas_operation_none, kc, n, k, -1.0, vu, k, vr, k, 1.0, r, kc);
+  }
+  double* w = alloc_as<double>(b_w, (size_t)n * kc);
+  double* pp = alloc_as<double>(b_p, (size_t)n * kc);
+  double* q = alloc_as<double>(b_q, (size_t)n * kc);
+  double* y = alloc_as<double>(b_y, (size_t)m * std::max(kc, k));
+  double* dots = alloc_as<double>(b_dots, (size_t)3 * kc);
+  double* part = alloc_as<double>(b_part, (size_t)coldots_parts(std::max(n, m)) * kc);
+  int* act = alloc_as<int>(b_act, kc);
+  double *rr = dots, *pq = dots + kc, *rnew = dots + 2 * kc;
+  NSP_HIP(hipMemsetAsync(w, 0, sizeof(double) * n * kc, c->stream));
+  NSP_HIP(hipMemcpyAsync(pp, r, sizeof(double) * n * kc, hipMemcpyDeviceToDevice, c->stream));
+  coldots(c, n, kc, r, r, rr, part);
+  std::vector<double> r0(kc), hr(kc);
+  std::vector<int> ha(kc);
+  NSP_HIP(hipMemcpyAsync(c->pin_d, rr, sizeof(double) * kc, hipMemcpyDeviceToHost, c->stream));
   NSP_HIP(hipStreamSynchronize(c->stream));
-  std::copy(c->pin_d, c->pin_d + k, r0.begin());
+  std::copy(c->pin_d, c->pin_d + kc, r0.begin());
   bool any = false;
-  for (int j = 0; j < k; ++j) {
+  for (int j = 0; j < kc; ++j) {
     r0[j] = std::sqrt(r0[j]);
     ha[j] = r0[j] > 0.0 ? 1 : 0;
     any |= ha[j] != 0;
   }
   std::copy(ha.begin(), ha.end(), c->pin_i);
-  NSP_HIP(hipMemcpyAsync(act, c->pin_i, sizeof(int) * k, hipMemcpyHostToDevice, c->stream));
+  NSP_HIP(hipMemcpyAsync(act, c->pin_i, sizeof(int) * kc, hipMemcpyHostToDevice, c->stream));
   NSP_HIP(hipStreamSynchronize(c->stream));
+  double* mv = alloc_as<double>(b_mm, (size_t)k * kc);
   int64_t it = 0;
   while (any && it < max_iter) {
-    spmm_wide(c, c->A, k, pp, y);
-    spmm_wide(c, c->AT, k, y, q);
-    coldots(c, n, k, pp, q, pq, part);
-    cg_wr(c, n, k, rr, pq, act, w, pp, r, q);
-    coldots(c, n, k, r, r, rnew, part);
-    cgls_p(c, n, k, rnew, rr, act, r, pp);
-    NSP_HIP(hipMemcpyAsync(rr, rnew, sizeof(double) * k, hipMemcpyDeviceToDevice, c->stream));
+    // q = A^T (A p); p^T q = ||A p||^2 comes fused with the first product
+    const int ny = spmm_wide(c, c->A, kc, pp, y, part);
+    reduce_parts(c, ny, kc, part, pq);
+    spmm_wide(c, c->AT, kc, y, q);
+    cg_wr(c, n, kc, rr, pq, act, w, pp, r, q);
+    coldots(c, n, kc, r, r, rnew, part);
+    cgls_p(c, n, kc, rnew, rr, act, r, pp);
+    std::swap(rr, rnew);  // the new r^T r is the next iteration's old one
     ++it;
     if (it % 16 == 0) {
       // re-project the residual onto range(A^T): V is a null basis only to
       // rounding accuracy, and A^T A cannot reduce a residual component in
       // null(A) (a no-op in exact arithmetic, where r stays in the range)
-      dgemm(c, rocblas_operation_none, rocblas_operation_transpose, k, k, n, 1.0, vr, k, r, k, 0.0, mm, k);
-      dgemm(c, rocblas_operation_transpose, rocblas_operation_none, k, n, k, -1.0, mm, k, vr, k, 1.0, r, k);
-      coldots(c, n, k, r, r, rr, part);
-      NSP_HIP(hipMemcpyAsync(c->pin_d, rr, sizeof(double) * k, hipMemcpyDeviceToHost, c->stream));
+      dgemm_nt_long(c, k, kc, n, vr, k, r, kc, mv, b_long);
+      dgemm(c, rocblas_operation_transpose, rocblas_operation_none, kc, n, k, -1.0, mv, k, vr, k, 1.0, r, kc);
+      coldots(c, n, kc, r, r, rr, part);
+      NSP_HIP(hipMemcpyAsync(c->pin_d, rr, sizeof(double) * kc, hipMemcpyDeviceToHost, c->stream));
       NSP_HIP(hipStreamSynchronize(c->stream));
-      std::copy(c->pin_d, c->pin_d + k, hr.begin());
+      std::copy(c->pin_d, c->pin_d + kc, hr.begin());
       any = false;
-      for (int j = 0; j < k; ++j) {
+      for (int j = 0; j < kc; ++j) {
         if (!std::isfinite(hr[j])) throw Error(NSP_ERR_NONFINITE, "non-finite value in backward CG");
         ha[j] = std::sqrt(hr[j]) > tol * r0[j] ? 1 : 0;
         any |= ha[j] != 0;
       }
       std::copy(ha.begin(), ha.end(), c->pin_i);
-      NSP_HIP(hipMemcpyAsync(act, c->pin_i, sizeof(int) * k, hipMemcpyHostToDevice, c->stream));
+      NSP_HIP(hipMemcpyAsync(act, c->pin_i, sizeof(int) * kc, hipMemcpyHostToDevice, c->stream));
       NSP_HIP(hipStreamSynchronize(c->stream));
     }
   }
-  // U = A W, grad_p = -2 <U_i, V_j>
-  spmm_wide(c, c->A, k, w, y);
+  // W = W_U C (row-major n x k): Wcm (k x n) = C^T W_Ucm; the buffer u is free now
+  double* wf = alloc_as<double>(b_u, (size_t)n * k);
+  dgemm(c, rocblas_operation_transpose, rocblas_operation_none, k, n, kc, 1.0, crd, kc, w, kc, 0.0, wf, k);
+  // Y = A W, grad_p = -2 <Y_i, V_j>
+  spmm_wide(c, c->A, k, wf, y);
   {
     // gradient per stored nonzero, then back to the caller's order
     DBuf b_gs;

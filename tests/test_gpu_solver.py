@@ -89,6 +89,36 @@ def test_restart_state_planted_vs_oracle_nullity():
         assert st["nullity"] == r["N"] == 6
 
 
+@pytest.mark.parametrize("kind", ["rank2", "fullrank"])
+def test_fd_instance_backward_other_right_hand_sides(kind):
+    """Range reduction of G_s V: a rank-2 loss and a full-rank symmetric G_s."""
+    import torch
+    from oracle import backward as bw
+    from tests.gpu_util import context
+
+    c = G.fd_instance()
+    a = c.to_scipy()
+    ad = a.toarray()
+    s = np.linalg.svd(ad, compute_uv=False)
+    smin = s[-9]
+    print(f"[solver] fd300 backward {kind}", flush=True)
+    ctx, dv, om = context(c, 0.1 * smin ** 2, d=1, max_dim=64, tol_abs_resid=1e-12 * smin,
+                          tol_rel_resid=0.0)
+    assert ctx.lanczos_run()["nullity"] == 8
+    v = _basis(ctx)
+    if kind == "rank2":
+        gs = bw.gs_pxf(G.gaussian_matrix(c.n, 2, seed=6))
+    else:
+        h = G.gaussian_matrix(c.n, c.n, seed=7)
+        gs = h + h.T
+    gsv = gs @ v
+    grad, it = ctx.backward(torch.from_numpy(np.ascontiguousarray(gsv)).cuda(), tol=1e-13)
+    grad = grad.cpu().numpy()
+    rows = np.repeat(np.arange(c.m), np.diff(c.rowptr))
+    ref = bw.dense_grad(ad, 8, gs, rows, c.colind)
+    assert np.linalg.norm(grad - ref) <= 1e-6 * np.linalg.norm(ref)
+
+
 def test_fd_instance_backward_matches_dense_gradient():
     import torch
     from oracle import backward as bw
