@@ -214,8 +214,12 @@ nsp_status nullspace_ritz_eig(nsp_ctx* ctx, int32_t K, int32_t kk, const double*
  *  grad_vals  [nnz], device, out: dL/d vals in A's CSR order,
  *             grad_p = -2 <(A W)_i, V_j> for the stored entry p = (i, j), where
  *             W = (A^T A)^+ (I - V V^T) G_s V is computed by CG on A^T A
- *             restricted to range(A^T).
- *  tol        relative CG residual target per column (e.g. 1e-12).
+ *             restricted to range(A^T), for the range of the right-hand side
+ *             only (its directions with singular values above 3e-7 of the
+ *             largest), deflated by the Ritz vectors the refinement used.
+ *  tol        relative CG residual target per column (e.g. 1e-10).  With
+ *             deflation the attainable level is about 1e-12: smaller values
+ *             are raised to 1e-12.
  *  max_iter   CG iteration cap; the call returns NSP_ERR_NOCONV if reached.
  *  iters      host out (nullable): CG iterations used. */
 nsp_status backward(nsp_ctx* ctx, const double* GsV, int64_t ld, double* grad_vals, double tol,

@@ -171,6 +171,11 @@ struct nsp_ctx {
   nsp::DBuf V;              // n x N column-major FP64 (final basis)
   nsp::DBuf Wd;             // n x defl_r column-major FP64: the Ritz vectors just above
   int32_t defl_r = 0;       // the null cluster, deflation space of the refinement
+  // the deflation space after its Rayleigh-Ritz rotation with A^T A (W^T A^T A W =
+  // Lambda), row-major blocks: W, Ws = W Lambda^-1, MWs = A^T A W Lambda^-1 (n x df_r),
+  // AW, AWs = A W Lambda^-1 (m x df_r); shared by the refinement and backward
+  nsp::DBuf dfW, dfWs, dfMWs, dfAW, dfAWs;
+  int32_t df_r = 0;
   int32_t nullity = 0;
   int state = 0;            // 0 = initialised, 1 = basis available
   std::vector<double> ritz; // last Ritz values (host)

@@ -493,6 +493,7 @@ struct Lanczos {
   void extract(int nul) {
     double* v = alloc_as<double>(c->V, (size_t)n * std::max(nul, 1));
     c->defl_r = 0;
+    c->df_r = 0;
     if (nul == 0) return;
     ritz_vectors(0, nul, v);
     // The next Ritz vectors (smallest nonzero part of the spectrum) deflate the
@@ -510,6 +511,60 @@ struct Lanczos {
 };
 
 // ---------------------------------------------------------------------------
+// Deflation space shared by the refinement and the backward pass (normal
+// form): the Ritz vectors the last Lanczos cycle left just above the null
+// cluster (c->Wd), rotated by a Rayleigh-Ritz step with A^T A so that
+// W^T A^T A W = Lambda; their Ritz values below 1e-12 of the largest are
+// dropped.  Built once per solve.
+// ---------------------------------------------------------------------------
+void build_deflation(nsp_ctx* c) {
+  if (c->df_r > 0 || c->defl_r <= 0) return;
+  const int64_t n = c->n, m = c->m;
+  const int r = c->defl_r;
+  DBuf b_w0, b_aw0, b_S, b_l, b_ei, b_inf, b_U, b_UL, b_long;
+  double* w0 = alloc_as<double>(b_w0, (size_t)n * r);
+  colmajor_to_rows(c, n, r, c->Wd.as<double>(), n, w0);
+  double* aw0 = alloc_as<double>(b_aw0, (size_t)m * r);
+  spmm_wide(c, c->A, r, w0, aw0);
+  double* S = alloc_as<double>(b_S, (size_t)r * r);
+  dgemm_nt_long(c, r, r, m, aw0, r, aw0, r, S, b_long);
+  double* lam = alloc_as<double>(b_l, r);
+  syevd(c, r, S, lam, b_ei, b_inf);
+  std::vector<double> hl(r), hu((size_t)r * r);
+  NSP_HIP(hipMemcpy(hl.data(), lam, sizeof(double) * r, hipMemcpyDeviceToHost));
+  NSP_HIP(hipMemcpy(hu.data(), S, sizeof(double) * r * r, hipMemcpyDeviceToHost));
+  const double lmax = hl[r - 1];
+  std::vector<int> keep;
+  for (int i = 0; i < r; ++i)
+    if (std::isfinite(hl[i]) && hl[i] > 1e-12 * lmax) keep.push_back(i);
+  const int rk = (int)keep.size();
+  if (rk == 0) return;
+  std::vector<double> uk((size_t)r * rk), ul((size_t)r * rk);
+  for (int j = 0; j < rk; ++j)
+    for (int i = 0; i < r; ++i) {
+      uk[i + (size_t)j * r] = hu[i + (size_t)keep[j] * r];
+      ul[i + (size_t)j * r] = hu[i + (size_t)keep[j] * r] / hl[keep[j]];
+    }
+  double* du = alloc_as<double>(b_U, (size_t)r * rk);
+  double* dul = alloc_as<double>(b_UL, (size_t)r * rk);
+  NSP_HIP(hipMemcpy(du, uk.data(), sizeof(double) * uk.size(), hipMemcpyHostToDevice));
+  NSP_HIP(hipMemcpy(dul, ul.data(), sizeof(double) * ul.size(), hipMemcpyHostToDevice));
+  // rotated blocks, column-major views (X_cm = row-major X transposed): X_cm = U^T X0_cm
+  double* w = alloc_as<double>(c->dfW, (size_t)n * rk);
+  double* ws = alloc_as<double>(c->dfWs, (size_t)n * rk);
+  double* aw = alloc_as<double>(c->dfAW, (size_t)m * rk);
+  double* aws = alloc_as<double>(c->dfAWs, (size_t)m * rk);
+  double* mws = alloc_as<double>(c->dfMWs, (size_t)n * rk);
+  dgemm(c, rocblas_operation_transpose, rocblas_operation_none, rk, n, r, 1.0, du, r, w0, r, 0.0, w, rk);
+  dgemm(c, rocblas_operation_transpose, rocblas_operation_none, rk, n, r, 1.0, dul, r, w0, r, 0.0, ws, rk);
+  dgemm(c, rocblas_operation_transpose, rocblas_operation_none, rk, m, r, 1.0, du, r, aw0, r, 0.0, aw, rk);
+  dgemm(c, rocblas_operation_transpose, rocblas_operation_none, rk, m, r, 1.0, dul, r, aw0, r, 0.0, aws, rk);
+  spmm_wide(c, c->AT, rk, aws, mws);
+  NSP_HIP(hipStreamSynchronize(c->stream));
+  c->df_r = rk;
+}
+
+// ---------------------------------------------------------------------------
 // FP64 refinement: Rayleigh-Ritz with A^T A, CGLS projection onto null(A),
 // Cholesky QR twice, residual and orthogonality checks.
 // ---------------------------------------------------------------------------
@@ -522,56 +577,22 @@ struct Refiner {
 
   Refiner(nsp_ctx* ctx, int nul) : c(ctx), n(ctx->n), m(ctx->m), k(nul) {}
 
-  // Deflation space of the CGLS (normal form), from the Ritz vectors just
-  // above the null cluster: after a Rayleigh-Ritz rotation with A^T A,
-  // W^T A^T A W = Lambda.  Kept as row-major blocks: W (n x rd), AW (m x rd),
-  // AWs = AW Lambda^-1 (m x rd) and MWs = A^T AWs (n x rd).  Deflated CG
-  // (x0 = W Lambda^-1 W^T b, search directions made A^T A-orthogonal to W)
-  // then converges at the rate of the spectrum above the deflated part.
+  // Deflation space of the CGLS (normal form): the Ritz vectors just above the
+  // null cluster (build_deflation).  Deflated CG (x0 = W Lambda^-1 W^T b,
+  // search directions kept A^T A-orthogonal to W) then converges at the rate
+  // of the spectrum above the deflated part.
   int rd = 0;
   double *dW = nullptr, *dAW = nullptr, *dAWs = nullptr, *dMWs = nullptr;
-  DBuf b_dw0, b_daw0, b_dw, b_daw, b_daws, b_dmws, b_dmu, b_dS, b_dl, b_dei, b_dinf, b_dU, b_dUL;
+  DBuf b_dmu;
 
   void setup_deflation() {
-    const int r = c->defl_r;
-    if (r <= 0) return;
-    double* w0 = alloc_as<double>(b_dw0, (size_t)n * r);
-    colmajor_to_rows(c, n, r, c->Wd.as<double>(), n, w0);
-    double* aw0 = alloc_as<double>(b_daw0, (size_t)m * r);
-    spmm_wide(c, c->A, r, w0, aw0);
-    double* S = alloc_as<double>(b_dS, (size_t)r * r);
-    dgemm_nt_long(c, r, r, m, aw0, r, aw0, r, S, b_long);
-    double* lam = alloc_as<double>(b_dl, r);
-    syevd(c, r, S, lam, b_dei, b_dinf);
-    std::vector<double> hl(r), hu((size_t)r * r);
-    NSP_HIP(hipMemcpy(hl.data(), lam, sizeof(double) * r, hipMemcpyDeviceToHost));
-    NSP_HIP(hipMemcpy(hu.data(), S, sizeof(double) * r * r, hipMemcpyDeviceToHost));
-    const double lmax = hl[r - 1];
-    std::vector<int> keep;
-    for (int i = 0; i < r; ++i)
-      if (std::isfinite(hl[i]) && hl[i] > 1e-12 * lmax) keep.push_back(i);
-    const int rk = (int)keep.size();
-    if (rk == 0) return;
-    std::vector<double> uk((size_t)r * rk), ul((size_t)r * rk);
-    for (int j = 0; j < rk; ++j)
-      for (int i = 0; i < r; ++i) {
-        uk[i + (size_t)j * r] = hu[i + (size_t)keep[j] * r];
-        ul[i + (size_t)j * r] = hu[i + (size_t)keep[j] * r] / hl[keep[j]];
-      }
-    double* du = alloc_as<double>(b_dU, (size_t)r * rk);
-    double* dul = alloc_as<double>(b_dUL, (size_t)r * rk);
-    NSP_HIP(hipMemcpy(du, uk.data(), sizeof(double) * uk.size(), hipMemcpyHostToDevice));
-    NSP_HIP(hipMemcpy(dul, ul.data(), sizeof(double) * ul.size(), hipMemcpyHostToDevice));
-    // rotated blocks (column-major views X_cm = rows^T): W_cm = U^T W0_cm, ...
-    dW = alloc_as<double>(b_dw, (size_t)n * rk);
-    dAW = alloc_as<double>(b_daw, (size_t)m * rk);
-    dAWs = alloc_as<double>(b_daws, (size_t)m * rk);
-    dMWs = alloc_as<double>(b_dmws, (size_t)n * rk);
-    dgemm(c, rocblas_operation_transpose, rocblas_operation_none, rk, n, r, 1.0, du, r, w0, r, 0.0, dW, rk);
-    dgemm(c, rocblas_operation_transpose, rocblas_operation_none, rk, m, r, 1.0, du, r, aw0, r, 0.0, dAW, rk);
-    dgemm(c, rocblas_operation_transpose, rocblas_operation_none, rk, m, r, 1.0, dul, r, aw0, r, 0.0, dAWs, rk);
-    spmm_wide(c, c->AT, rk, dAWs, dMWs);
-    rd = rk;
+    build_deflation(c);
+    rd = c->df_r;
+    if (rd == 0) return;
+    dW = c->dfW.as<double>();
+    dAW = c->dfAW.as<double>();
+    dAWs = c->dfAWs.as<double>();
+    dMWs = c->dfMWs.as<double>();
   }
 
   // p -= W Lambda^-1 (A^T A W)^T r  (column-major views: mu = r_cm MWs_cm^T)
@@ -661,17 +682,28 @@ struct Refiner {
     if (!std::isfinite(tau)) tau = 1e-10 * c->normA_fro / rk;
     std::vector<double> hs(k);
     std::vector<int> ha(k);
-    // per column ||A v_j||^2 (the residual norms) -> active flags
+    // per column ||A v_j||^2 (the residual norms) -> active flags.  A run whose
+    // largest residual has not dropped by 1% within 4096 iterations has
+    // reached its attainable accuracy and stops (the residual check reports it).
+    double best = std::numeric_limits<double>::infinity();
+    int64_t last_gain = 0, it_now = 0;
     auto update_active = [&](const double* res2) -> bool {
       NSP_HIP(hipMemcpyAsync(c->pin_d, res2, sizeof(double) * k, hipMemcpyDeviceToHost, c->stream));
       NSP_HIP(hipStreamSynchronize(c->stream));
       std::copy(c->pin_d, c->pin_d + k, hs.begin());
       bool any = false;
+      double mx = 0.0;
       for (int j = 0; j < k; ++j) {
         if (!std::isfinite(hs[j])) throw Error(NSP_ERR_NONFINITE, "non-finite value in refinement");
         ha[j] = std::sqrt(hs[j]) > tau ? 1 : 0;
         any |= ha[j] != 0;
+        if (ha[j]) mx = std::max(mx, std::sqrt(hs[j]));
       }
+      if (mx < 0.99 * best) {
+        best = mx;
+        last_gain = it_now;
+      }
+      if (any && it_now - last_gain > 4096) any = false;
       std::copy(ha.begin(), ha.end(), c->pin_i);
       NSP_HIP(hipMemcpyAsync(act, c->pin_i, sizeof(int) * k, hipMemcpyHostToDevice, c->stream));
       NSP_HIP(hipStreamSynchronize(c->stream));
@@ -701,6 +733,7 @@ struct Refiner {
         std::swap(gamma, gnew);
         ++it;
         if (it % 16 == 0) {
+          it_now = it;
           any = update_active(gamma);
           if (verbose && now_s() - last_print > 2.0) {
             std::fprintf(stderr, "[nsp] refine (CG) it %lld\n", (long long)it);
@@ -722,6 +755,7 @@ struct Refiner {
       ++it;
       if (it % 16 == 0) {
         coldots(c, m, k, sv, sv, sn2, part);
+        it_now = it;
         any = update_active(sn2);
         if (verbose && now_s() - last_print > 2.0) {
           int na = 0;
@@ -878,14 +912,41 @@ void run_backward(nsp_ctx* c, const double* GsV, int64_t ld, double* grad, doubl
   double* part = alloc_as<double>(b_part, (size_t)coldots_parts(std::max(n, m)) * kc);
   int* act = alloc_as<int>(b_act, kc);
   double *rr = dots, *pq = dots + kc, *rnew = dots + 2 * kc;
-  NSP_HIP(hipMemsetAsync(w, 0, sizeof(double) * n * kc, c->stream));
-  NSP_HIP(hipMemcpyAsync(pp, r, sizeof(double) * n * kc, hipMemcpyDeviceToDevice, c->stream));
+  // the tolerance is relative to the right-hand side's column norms
   coldots(c, n, kc, r, r, rr, part);
   std::vector<double> r0(kc), hr(kc);
   std::vector<int> ha(kc);
   NSP_HIP(hipMemcpyAsync(c->pin_d, rr, sizeof(double) * kc, hipMemcpyDeviceToHost, c->stream));
   NSP_HIP(hipStreamSynchronize(c->stream));
   std::copy(c->pin_d, c->pin_d + kc, r0.begin());
+  // Deflated CG with the Ritz vectors above the null cluster (as in the
+  // refinement): x0 = W Lambda^-1 W^T b, r0 = b - A^T A x0, directions kept
+  // A^T A-orthogonal to W.
+  build_deflation(c);
+  const int rd = c->df_r;
+  if (rd > 0) tol = std::max(tol, 1e-12);  // the deflated recurrence's attainable level
+  DBuf b_mu;
+  double* mu = rd > 0 ? alloc_as<double>(b_mu, (size_t)kc * rd) : nullptr;
+  auto deflate_direction = [&](const double* res, double* dir) {
+    dgemm_nt_long(c, kc, rd, n, res, kc, c->dfMWs.as<double>(), rd, mu, b_long);
+    dgemm(c, rocblas_operation_none, rocblas_operation_none, kc, n, rd, -1.0, mu, kc,
+          c->dfW.as<double>(), rd, 1.0, dir, kc);
+  };
+  if (rd > 0) {
+    dgemm_nt_long(c, kc, rd, n, r, kc, c->dfW.as<double>(), rd, mu, b_long);
+    dgemm(c, rocblas_operation_none, rocblas_operation_none, kc, n, rd, 1.0, mu, kc,
+          c->dfWs.as<double>(), rd, 0.0, w, kc);
+    // r = b - A^T (A x0) with the SpMV pair (not through the stored A^T A W,
+    // whose rounding would cap the attainable residual at u kappa(A^T A))
+    spmm_wide(c, c->A, kc, w, y);
+    spmm_wide(c, c->AT, kc, y, q);
+    sub_inplace(c, n * kc, r, q);
+  } else {
+    NSP_HIP(hipMemsetAsync(w, 0, sizeof(double) * n * kc, c->stream));
+  }
+  NSP_HIP(hipMemcpyAsync(pp, r, sizeof(double) * n * kc, hipMemcpyDeviceToDevice, c->stream));
+  if (rd > 0) deflate_direction(r, pp);
+  coldots(c, n, kc, r, r, rr, part);
   bool any = false;
   for (int j = 0; j < kc; ++j) {
     r0[j] = std::sqrt(r0[j]);
@@ -905,6 +966,7 @@ void run_backward(nsp_ctx* c, const double* GsV, int64_t ld, double* grad, doubl
     cg_wr(c, n, kc, rr, pq, act, w, pp, r, q);
     coldots(c, n, kc, r, r, rnew, part);
     cgls_p(c, n, kc, rnew, rr, act, r, pp);
+    if (rd > 0) deflate_direction(r, pp);
     std::swap(rr, rnew);  // the new r^T r is the next iteration's old one
     ++it;
     if (it % 16 == 0) {
