@@ -555,36 +555,44 @@ __global__ __launch_bounds__(512) void k_ts_nn_v(const int* cond, int64_t n,
   const int lane = threadIdx.x % kWave, wid = threadIdx.x / kWave;
   const int64_t rb = (int64_t)blockIdx.x * TR;
   const int64_t r = rb + (int64_t)lane * RV;
-  const int per = (k + NW - 1) / NW;
-  const int jb = min(k, wid * per), je = min(k, jb + per);
   double acc[RV][NC];
 #pragma unroll
   for (int i = 0; i < RV; ++i)
 #pragma unroll
     for (int c = 0; c < NC; ++c) acc[i][c] = 0.0;
+  // Columns go from the last to the first in groups of UN dealt round-robin
+  // to the waves, so the whole grid sweeps Z downwards together: the
+  // projection kernel just read Z upwards, and its most recent columns are the
+  // ones still held in the memory-side cache.  UN loads in flight per wave.
+  constexpr int UN = 4;
   if (r < n) {
-    int j = jb;
-    for (; j + 4 <= je; j += 4) {
-      double zv[4][RV];
+    for (int g = wid;; g += NW) {
+      const int jhi = k - UN * g;
+      if (jhi <= 0) break;
+      if (jhi >= UN) {
+        const int j = jhi - UN;
+        double zv[UN][RV];
 #pragma unroll
-      for (int u = 0; u < 4; ++u) load_rows<VT>(z + (int64_t)(j + u) * ldz, r, n, zv[u]);
+        for (int u = 0; u < UN; ++u) load_rows<VT>(z + (int64_t)(j + u) * ldz, r, n, zv[u]);
 #pragma unroll
-      for (int u = 0; u < 4; ++u)
+        for (int u = 0; u < UN; ++u)
 #pragma unroll
-        for (int c = 0; c < NC; ++c) {
-          const double hv = h[(int64_t)(j + u) * NC + c];
+          for (int c = 0; c < NC; ++c) {
+            const double hv = h[(int64_t)(j + u) * NC + c];
 #pragma unroll
-          for (int i = 0; i < RV; ++i) acc[i][c] = fma(zv[u][i], hv, acc[i][c]);
+            for (int i = 0; i < RV; ++i) acc[i][c] = fma(zv[u][i], hv, acc[i][c]);
+          }
+      } else {
+        for (int j = 0; j < jhi; ++j) {
+          double zv[RV];
+          load_rows<VT>(z + (int64_t)j * ldz, r, n, zv);
+#pragma unroll
+          for (int c = 0; c < NC; ++c) {
+            const double hv = h[(int64_t)j * NC + c];
+#pragma unroll
+            for (int i = 0; i < RV; ++i) acc[i][c] = fma(zv[i], hv, acc[i][c]);
+          }
         }
-    }
-    for (; j < je; ++j) {
-      double zv[RV];
-      load_rows<VT>(z + (int64_t)j * ldz, r, n, zv);
-#pragma unroll
-      for (int c = 0; c < NC; ++c) {
-        const double hv = h[(int64_t)j * NC + c];
-#pragma unroll
-        for (int i = 0; i < RV; ++i) acc[i][c] = fma(zv[i], hv, acc[i][c]);
       }
     }
   }
