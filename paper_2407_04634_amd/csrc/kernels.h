@@ -49,7 +49,7 @@ void scale_block2(nsp_ctx* c, int d, int64_t n, const double* part_g2, int npart
 void w_reset(nsp_ctx* c, int col0, int ncols, double u_d, double* w, int ldw);
 
 // dense: tall-skinny projection pair (one CGS pass) and final scaling
-int64_t ts_chunk_rows(int64_t n, int k, int nc);
+int64_t ts_chunk_rows(int64_t n, int k, int nc, int esize = 8);
 int64_t ts_part_c_len(int64_t n, int nc);
 template <typename VT>
 void ts_project(nsp_ctx* c, const int* cond, int d, int na, int64_t n, const VT* z, int64_t ldz,

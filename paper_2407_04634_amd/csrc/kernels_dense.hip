@@ -374,9 +374,13 @@ struct CPair {
   }
 };
 
-template <int NC> struct TsShape {
-  static constexpr int JW = NC >= 16 ? 1 : (NC >= 8 ? 2 : (NC >= 4 ? 4 : 8));  // basis columns per wave
-  static constexpr int JB = 4 * JW;                                            // basis columns per block
+// Basis columns per wave (JW) and per block (JB) of the projection kernel.
+// FP32 rows come four per 16-byte load, so half as many columns keep the
+// register footprint (and the occupancy) of the FP64 kernel.
+template <int NC, int ESIZE = 8> struct TsShape {
+  static constexpr int JW8 = NC >= 16 ? 1 : (NC >= 8 ? 2 : (NC >= 4 ? 4 : 8));
+  static constexpr int JW = ESIZE == 4 && JW8 > 1 ? JW8 / 2 : JW8;
+  static constexpr int JB = 4 * JW;
 };
 
 // Rows one lane loads at once from a basis column: 16 bytes per load.
@@ -407,12 +411,12 @@ __global__ __launch_bounds__(kThreads) void k_ts_tn(const int* cond, int64_t n, 
                                                     const VT* __restrict__ z, int64_t ldz, int k,
                                                     CPair<VT, DA, NA> cc, double* __restrict__ hpart) {
   constexpr int NC = DA * NA;
-  constexpr int JW = TsShape<NC>::JW;
+  constexpr int JW = TsShape<NC, sizeof(VT)>::JW;
   if (cond && *cond == 0) return;
   const int lane = threadIdx.x % kWave, wid = threadIdx.x / kWave;
   const int64_t r0 = (int64_t)blockIdx.x * chunk;
   const int64_t r1 = min(n, r0 + chunk);
-  const int j0 = blockIdx.y * TsShape<NC>::JB + wid * JW;
+  const int j0 = blockIdx.y * TsShape<NC, sizeof(VT)>::JB + wid * JW;
   const int jn = max(0, min(JW, k - j0));
   double acc[JW][NC];
 #pragma unroll
@@ -425,10 +429,21 @@ __global__ __launch_bounds__(kThreads) void k_ts_tn(const int* cond, int64_t n, 
   if (jn > 0) {
     for (int64_t r = r0 + (int64_t)lane * RV; r < r1; r += kWave * RV) {
       double cv[RV][NC];
+      if constexpr (DA == 1) {
+        // C columns are plain vectors: the same 16-byte row loads as Z
 #pragma unroll
-      for (int i = 0; i < RV; ++i)
+        for (int c = 0; c < NC; ++c) {
+          double t[RV];
+          load_rows<VT>(c == 0 ? cc.a0 : cc.a1, r, r1, t);
 #pragma unroll
-        for (int c = 0; c < NC; ++c) cv[i][c] = r + i < r1 ? (double)cc.get(r + i, c) : 0.0;
+          for (int i = 0; i < RV; ++i) cv[i][c] = t[i];
+        }
+      } else {
+#pragma unroll
+        for (int i = 0; i < RV; ++i)
+#pragma unroll
+          for (int c = 0; c < NC; ++c) cv[i][c] = r + i < r1 ? (double)cc.get(r + i, c) : 0.0;
+      }
       double zv[JW][RV];
 #pragma unroll
       for (int q = 0; q < JW; ++q) {
@@ -972,8 +987,9 @@ void w_reset(nsp_ctx* c, int col0, int ncols, double u_d, double* w, int ldw) {
 // at least 1024 rows (so each lane accumulates >= 16 rows before the wave sum).
 // Row chunk of the H = Z^T C kernel: about 2048 blocks over (chunks x column
 // groups), at least 1024 rows, a multiple of 256 rows (aligned vector loads).
-int64_t ts_chunk_rows(int64_t n, int k, int nc) {
-  const int jb = nc >= 16 ? 4 : (nc >= 8 ? 8 : (nc >= 4 ? 16 : 32));
+int64_t ts_chunk_rows(int64_t n, int k, int nc, int esize) {
+  int jb = nc >= 16 ? 4 : (nc >= 8 ? 8 : (nc >= 4 ? 16 : 32));
+  if (esize == 4 && jb > 4) jb /= 2;  // TsShape<NC, 4>::JB
   const int64_t col_groups = std::max<int64_t>(1, (k + jb - 1) / jb);
   const int64_t chunks = std::max<int64_t>(1, 2048 / col_groups);
   int64_t rows = (n + chunks - 1) / chunks;
@@ -990,9 +1006,9 @@ static void ts_proj_t(nsp_ctx* c, const int* cond, int64_t n, const VT* z, int64
   constexpr int TR = ts_nn_rows<VT, NC>();
   const unsigned nnblocks = (unsigned)((n + TR - 1) / TR);
   if (k > 0) {
-    const int64_t chunk = ts_chunk_rows(n, k, NC);
+    const int64_t chunk = ts_chunk_rows(n, k, NC, (int)sizeof(VT));
     const unsigned nchunks = (unsigned)((n + chunk - 1) / chunk);
-    const unsigned gy = (unsigned)((k + TsShape<NC>::JB - 1) / TsShape<NC>::JB);
+    const unsigned gy = (unsigned)((k + TsShape<NC, sizeof(VT)>::JB - 1) / TsShape<NC, sizeof(VT)>::JB);
     k_ts_tn<VT, DA, NA><<<dim3(nchunks, gy), kThreads, 0, c->stream>>>(cond, n, chunk, z, ldz, k, cc,
                                                                         hpart);
     if (ev_tn) NSP_HIP(hipEventRecord(ev_tn, c->stream));

@@ -220,7 +220,7 @@ struct Lanczos {
     H = alloc_as<double>(b_H, (size_t)(K + d) * 2 * d);
     int64_t maxchunks = 1;
     for (int nc : {d, 2 * d}) {
-      const int64_t chunk = ts_chunk_rows(n, 1, nc);
+      const int64_t chunk = ts_chunk_rows(n, 1, nc, (int)sizeof(VT));
       maxchunks = std::max(maxchunks, (n + chunk - 1) / chunk);
     }
     hpart = alloc_as<double>(b_hpart, (size_t)maxchunks * (K + d) * 2 * d);
@@ -629,7 +629,10 @@ struct Refiner {
     c->pin_d = c->pind.ensure(std::max<size_t>((size_t)c->prm.max_dim + 16, (size_t)k * (k + 1) + 16));
     c->pin_i = c->pini.ensure(std::max<size_t>(64, (size_t)k + 16));
     double* vr = alloc_as<double>(b_vr, (size_t)n * k);
-    double* u = alloc_as<double>(b_u, (size_t)m * k);
+    // the symmetric form's CG needs fewer blocks: A V and the final residual
+    // share the buffer of q
+    double* q = alloc_as<double>(b_q, (size_t)m * k);
+    double* u = c->sym ? q : alloc_as<double>(b_u, (size_t)m * k);
     colmajor_to_rows(c, n, k, c->V.as<double>(), n, vr);
     // Step 1: Rayleigh-Ritz with the unperturbed A^T A on span(V)
     spmm_wide(c, c->A, k, vr, u);
@@ -643,10 +646,9 @@ struct Refiner {
     NSP_HIP(hipMemcpyAsync(vr, vnew, sizeof(double) * n * k, hipMemcpyDeviceToDevice, c->stream));
     // Step 2: CGLS for x = A^+ A v per column, x_0 = 0; s = A v - A x = A (v - x)
     double* x = alloc_as<double>(b_x, (size_t)n * k);
-    double* sv = alloc_as<double>(b_s, (size_t)m * k);
+    double* sv = c->sym ? q : alloc_as<double>(b_s, (size_t)m * k);
     double* r = alloc_as<double>(b_r, (size_t)n * k);
     double* pp = alloc_as<double>(b_p, (size_t)n * k);
-    double* q = alloc_as<double>(b_q, (size_t)m * k);
     double* dots = alloc_as<double>(b_dots, (size_t)4 * k);  // gamma, qq, gnew, snorm2
     double* part = alloc_as<double>(b_part, (size_t)coldots_parts(std::max(n, m)) * k);
     int* act = alloc_as<int>(b_act, k);
@@ -813,6 +815,10 @@ void solve(nsp_ctx* c) {
     lz.run();
   }
   if (c->prm.refine && c->nullity > 0) {
+    // the Lanczos basis is not needed any more: give its memory to the
+    // refinement's blocks (n x N each); a new lanczos_run allocates it again
+    c->Z.release();
+    c->Z2.release();
     Refiner rf(c, c->nullity);
     rf.run();
   } else if (c->nullity > 0) {
