@@ -45,10 +45,16 @@ TRAFFIC = {
 # sigma_min comes from dense SVD on same-shaped probes (planted) or the known
 # smallest Laplacian eigenvalue (er20).
 WORKLOADS = {
-    "er20": dict(gen=("er20",), eps=0.1 * 0.36330958416634257 ** 2, max_dim=64,
+    "er20": dict(gen=("er20",), eps=0.1 * 0.36330958416634257 ** 2, max_dim=64, op="normal",
                  desc="Laplacian of 20 disjoint G(100, 6/99) components, n=2000, nullity 20"),
-    "planted50k": dict(gen=("planted50k",), eps=2e-6, max_dim=1024,
+    "planted50k": dict(gen=("planted50k",), eps=2e-6, max_dim=1024, op="normal",
                        desc="planted A=[B, BR], m=n=50000, B 8 N(0,1)/col, R 4 N(0,1)/col, nullity 200"),
+    # the Laplacians in the symmetric form B = L + eps D (Sec. 5.1); eps well below
+    # the smallest nonzero Laplacian eigenvalue (0.35 and 0.74 on these instances)
+    "zipf400k": dict(gen=("zipf400k",), eps=1e-2, max_dim=256, op="sym",
+                     desc="Laplacian of 100 components, Zipf sizes, mean degree 10, n=400000, nullity 100"),
+    "zipf4m": dict(gen=("zipf4m",), eps=1e-2, max_dim=2048, op="sym",
+                   desc="Laplacian of 1000 components, Zipf sizes, mean degree 10, n=4000000, nullity 1000"),
 }
 
 
@@ -143,13 +149,18 @@ def spmv_pair_bytes(m, n, nnz, d, esize):
     return a, at
 
 
-def kernel_rooflines(st, m, n, nnz, d, esize):
+def kernel_rooflines(st, m, n, nnz, d, esize, sym=False, stream=False):
     """Per-kernel achieved GB/s from the solver's HIP-event samples (profile mode)."""
     a_b, at_b = spmv_pair_bytes(m, n, nnz, d, esize)
+    k1 = "k_csr_stream" if stream else "k_spmm"
+    k2 = "k_csr_stream" if stream else "k_spmmT_step"
     out = []
     if st.get("spmv_samples", 0) > 0:
-        out.append(("k_spmm (y = A x)", st["t_spmv_a_us"], a_b))
-        out.append(("k_spmmT_step (P = A^T y + eps D x - Xp Gamma^T)", st["t_spmv_at_us"], at_b))
+        if sym:  # one product with A per step, fused with the recurrence
+            out.append((f"{k2} (P = A x + eps D x - Xp Gamma^T)", st["t_spmv_at_us"], at_b))
+        else:
+            out.append((f"{k1} (y = A x)", st["t_spmv_a_us"], a_b))
+            out.append((f"{k2} (P = A^T y + eps D x - Xp Gamma^T)", st["t_spmv_at_us"], at_b))
     na = st.get("ro_active", 0)
     if na > 0:
         # launches at steps whose W-recurrence flag was clear return at once; the
@@ -310,7 +321,7 @@ def main():
         sys.exit(2)
 
     import torch
-    from paper_2407_04634_amd import Context, PREC_FP64, PREC_MIXED
+    from paper_2407_04634_amd import Context, OP_NORMAL, OP_SYM, PREC_FP64, PREC_MIXED
     from workloads import generators as G
 
     wl = WORKLOADS[args.workload]
@@ -327,7 +338,8 @@ def main():
     ctx = Context(rp, ci, va, c.m, c.n, D=dv, Omega=om, eps=eps, d=args.d, max_dim=max_dim,
                   prec=PREC_MIXED if args.prec == "mixed" else PREC_FP64, tol_angle=1e-9,
                   tol_rel_resid=1e-10, max_matvec=20_000_000, max_cycles=args.max_cycles,
-                  refine=0 if args.no_refine else 1, profile=args.profile)
+                  refine=0 if args.no_refine else 1, profile=args.profile,
+                  op=OP_SYM if wl["op"] == "sym" else OP_NORMAL)
     partial = args.max_cycles > 0 or args.no_refine
     for w in range(args.warmup):
         st = ctx.lanczos_run(allow_noconv=partial)
@@ -365,7 +377,8 @@ def main():
         "dtype": "f64" if args.prec == "fp64" else "f32+f64",
         "data": "synthetic, seeded",
         "config": {"workload": wl["desc"], "name": args.workload, "d": args.d, "max_dim": max_dim,
-                   "eps": eps, "precision": args.prec},
+                   "eps": eps, "precision": args.prec,
+                   "operator": "B = L + eps D" if wl["op"] == "sym" else "B = A^T A + eps D"},
         "valid": valid,
         "accuracy": {"nullity": st["nullity"], "nullity_exact": v0.shape[1],
                      "rel_resid_fro": st["rel_resid_fro"], "max_sin_angle": sine,
@@ -374,13 +387,14 @@ def main():
                                       "t_lanczos_s", "t_restart_s", "t_refine_s", "theta_next")},
     }
     esize = 4 if args.prec == "mixed" else 8
-    kr = kernel_rooflines(st, c.m, c.n, c.nnz, args.d, esize)
+    kr = kernel_rooflines(st, c.m, c.n, c.nnz, args.d, esize, sym=wl["op"] == "sym",
+                          stream=c.nnz >= 1 << 21)
     if kr:
         # dominant kernel: the largest total time over the run (SpMV pair every
         # step, reorthogonalisation pair at the flagged steps)
         steps = st["matvecs"] / args.d
         frac = st["ro_active"] / max(1, st["ro_samples"])
-        weight = [steps if r["kernel"].startswith("k_spmm") else steps * frac for r in kr]
+        weight = [steps * frac if r["kernel"].startswith("k_ts_") else steps for r in kr]
         dom = max(zip(kr, weight), key=lambda t: t[0]["avg_us"] * t[1])[0]
         tr = TRAFFIC.get((args.workload, args.d, args.prec, dom["kernel"].split()[0]))
         line["roofline"] = {"kernel": dom["kernel"], "bound": "hbm", "achieved": dom["achieved_gbs"],
