@@ -56,6 +56,12 @@ def planted_basis(r: sp.spmatrix) -> np.ndarray:
     return q
 
 
+def column_scaled_basis(v: np.ndarray, s: np.ndarray) -> np.ndarray:
+    """Orthonormal basis of null(A S) = S^{-1} null(A), S = diag(s), from one of null(A)."""
+    q, _ = np.linalg.qr(np.asarray(v, dtype=np.float64) / np.asarray(s)[:, None])
+    return q
+
+
 # --------------------------------------------------------------------------
 # dense SVD (tiny inputs)
 # --------------------------------------------------------------------------

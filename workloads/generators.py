@@ -146,6 +146,20 @@ def planted_nullity(m: int = 50000, n: int = 50000, nullity: int = 200, per_col_
     return CSR.from_scipy(a, {"kind": "planted", "R": r.tocsc(), "nullity": nullity, "seed": seed})
 
 
+def column_scaled(c: CSR, decades: float, seed: int) -> CSR:
+    """A S with S = diag(10^u_j), u_j iid uniform on [-decades/2, decades/2].
+
+    Columns measured in unrelated units are the usual source of such scaling;
+    null(A S) = S^{-1} null(A), so ``meta['col_scale']`` (the diagonal of S) and
+    the base matrix's metadata give the exact null space.
+    """
+    rng = _rng(seed, 9)
+    s = 10.0 ** rng.uniform(-decades / 2.0, decades / 2.0, c.n)
+    meta = dict(c.meta)
+    meta["col_scale"] = s
+    return CSR(c.m, c.n, c.rowptr.copy(), c.colind.copy(), c.vals * s[c.colind], meta)
+
+
 # ---------------------------------------------------------------------------
 # Workload 3: coboundary (edge-vertex incidence) of a random geometric graph
 # ---------------------------------------------------------------------------
@@ -274,6 +288,10 @@ def config(name: str, scale: str = "full") -> CSR:
     if name == "planted200k":
         return (planted_nullity(4000, 4000, 8, seed=BASE_SEED + 5) if small
                 else planted_nullity(200000, 200000, 64, seed=BASE_SEED + 5))
+    if name == "planted20k_scaled":  # columns spread over two decades
+        base = (planted_nullity(2000, 2000, 10, seed=BASE_SEED + 7) if small
+                else planted_nullity(20000, 20000, 50, seed=BASE_SEED + 7))
+        return column_scaled(base, 2.0, BASE_SEED + 7)
     if name == "fd300":
         return fd_instance()
     raise KeyError(name)
