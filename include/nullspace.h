@@ -69,6 +69,19 @@ typedef enum {
                         is the caller's promise; the null space is then null(A).  */
 } nsp_op;
 
+typedef enum {
+  NSP_PRECOND_NONE = 0,   /* Lanczos on B as given by op                              */
+  NSP_PRECOND_JACOBI = 1  /* outer preconditioning (Sec. 4.4, "Outer preconditioning")
+                             with the diagonal P_R = diag(p): Lanczos on
+                             B_R = P_R^{-1} A^T A P_R^{-T} + eps D (NSP_OP_NORMAL,
+                             p_j = ||A e_j||_2) or P_R^{-1} A P_R^{-T} + eps D
+                             (NSP_OP_SYM, p_j = sqrt(A_jj)); p_j = 1 where that is
+                             0.  The Lanczos basis approximates null(A P_R^{-T}) =
+                             P_R^T null(A); V = P_R^{-T} V_R, orthonormalised, is
+                             what extract_basis returns.  Undoes column scaling
+                             exactly (A S has the same B_R as A for diagonal S > 0). */
+} nsp_precond;
+
 /* Solver parameters (host struct).  nsp_default_params() fills defaults. */
 typedef struct {
   double eps;            /* perturbation strength eps > 0 (Eq. "defB"); the paper's
@@ -101,6 +114,11 @@ typedef struct {
                             operator up to renumbering.  Every argument and result
                             of the API stays in the caller's order.  0: keep it.   */
   int32_t op;            /* nsp_op: operator form, NSP_OP_NORMAL by default           */
+  int32_t precond;       /* nsp_precond: NSP_PRECOND_NONE by default. With
+                            NSP_PRECOND_JACOBI, eps, the 3 eps nullity threshold,
+                            ||B||, the Ritz values and apply_op refer to B_R, the
+                            refinement works on A P_R^{-T}, and rel_resid_fro is
+                            ||A V||_F / ||A||_F of the returned basis.               */
   uint64_t seed;         /* seed of the built-in Philox4x32-10 draws of D and Omega,
                             used only when the caller passes D or Omega as NULL       */
 } nsp_params;
@@ -143,7 +161,8 @@ typedef struct {
 /* Fill *p with defaults: eps = 1e-3 (Sec. 5.3), d = 1, max_dim = 64,
    max_matvec = 10^7, ro_tol = 0, prec = FP64, refine = 1, tol_rel_resid = 1e-10,
    tol_abs_resid = 0, tol_angle = 1e-9, max_refine_iter = 10^6, max_cycles = 0,
-   profile = 0, seed = 20240704. */
+   profile = 0, reorder = 1, op = NSP_OP_NORMAL, precond = NSP_PRECOND_NONE,
+   seed = 20240704. */
 void nsp_default_params(nsp_params* p);
 
 /* Create a solver context for A (m x n, nnz stored entries, CSR).
@@ -167,7 +186,8 @@ nsp_status nullspace_init(nsp_ctx** out, int64_t m, int64_t n, int64_t nnz,
                           void* stream);
 
 /* Y = B X for ncols >= 1 columns: A^T (A X) + eps D X (Sec. 1.2), or
- * A X + eps D X with NSP_OP_SYM.
+ * A X + eps D X with NSP_OP_SYM; with NSP_PRECOND_JACOBI the preconditioned
+ * operator B_R the solver iterates with.
  *  X [n x ncols], ld ldx >= n; Y [n x ncols], ld ldy >= n; device, FP64.
  *  Uses the FP64 values regardless of the precision mode.  X and Y must not
  *  overlap.  Allowed in any state after init. */
@@ -221,7 +241,11 @@ nsp_status nullspace_ritz_eig(nsp_ctx* ctx, int32_t K, int32_t kk, const double*
  *             deflation the attainable level is about 1e-12: smaller values
  *             are raised to 1e-12.
  *  max_iter   CG iteration cap; the call returns NSP_ERR_NOCONV if reached.
- *  iters      host out (nullable): CG iterations used. */
+ *  iters      host out (nullable): CG iterations used.
+ * With NSP_PRECOND_JACOBI (normal form) the CG runs on the preconditioned
+ * normal equations: A W = (A P_R^{-T}) X with (A P_R^{-T})^T (A P_R^{-T}) X =
+ * P_R^{-1} (I - V V^T) G_s V, which gives the same A W.  NSP_ERR_ARG for the
+ * preconditioned symmetric form. */
 nsp_status backward(nsp_ctx* ctx, const double* GsV, int64_t ld, double* grad_vals, double tol,
                     int64_t max_iter, int64_t* iters);
 

@@ -15,4 +15,6 @@ from ._lib import (  # noqa: F401
     PREC_MIXED,
     OP_NORMAL,
     OP_SYM,
+    PRECOND_NONE,
+    PRECOND_JACOBI,
 )

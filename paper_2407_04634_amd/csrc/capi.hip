@@ -61,6 +61,8 @@ void validate_params(const nsp_params* p, int64_t n) {
   NSP_REQUIRE(p->max_cycles >= 0, "max_cycles must be >= 0");
   NSP_REQUIRE(p->reorder == 0 || p->reorder == 1, "reorder must be 0 or 1");
   NSP_REQUIRE(p->op == NSP_OP_NORMAL || p->op == NSP_OP_SYM, "op must be NSP_OP_NORMAL or NSP_OP_SYM");
+  NSP_REQUIRE(p->precond == NSP_PRECOND_NONE || p->precond == NSP_PRECOND_JACOBI,
+              "precond must be NSP_PRECOND_NONE or NSP_PRECOND_JACOBI");
 }
 
 }  // namespace
@@ -85,6 +87,7 @@ void nsp_default_params(nsp_params* p) {
   p->profile = 0;
   p->reorder = 1;
   p->op = NSP_OP_NORMAL;
+  p->precond = NSP_PRECOND_NONE;
   p->seed = 20240704ull;
 }
 
@@ -124,6 +127,8 @@ nsp_status nullspace_init(nsp_ctx** out, int64_t m, int64_t n, int64_t nnz, cons
     nsp::prepare_matrix(c, rowptr, colind, vals);
     nsp::init_random(c, D, Omega);
     nsp::matrix_norms(c);
+    nsp::precondition(c);
+    if (c->precond) nsp::matrix_norms(c);  // of the preconditioned matrix
     NSP_HIP(hipStreamSynchronize(c->stream));
   });
   if (st != NSP_OK) {
@@ -255,6 +260,8 @@ nsp_status backward(nsp_ctx* ctx, const double* GsV, int64_t ld, double* grad_va
     NSP_REQUIRE(grad_vals != nullptr || ctx->nnz == 0, "grad_vals must not be NULL");
     NSP_REQUIRE(ctx->nullity == 0 || (GsV != nullptr && ld >= ctx->n), "GsV must be n x N, ld >= n");
     NSP_REQUIRE(tol > 0.0 && max_iter > 0, "tol and max_iter must be positive");
+    NSP_REQUIRE(!(ctx->precond && ctx->sym),
+                "backward does not support the preconditioned symmetric form");
     enter(ctx);
     nsp::run_backward(ctx, GsV, ld, grad_vals, tol, max_iter, iters);
     leave(ctx);

@@ -148,6 +148,12 @@ struct nsp_ctx {
   double normA1_inf = 0.0;  // ||A||_1 * ||A||_inf
   double normA_inf = 0.0;   // ||A||_inf (bounds ||A||_2 when A is symmetric)
   bool sym = false;         // B = A + eps D (NSP_OP_SYM)
+  // outer preconditioning with P_R = diag(pdiag) (NSP_PRECOND_JACOBI): the stored
+  // values are those of A P_R^{-T} (or P_R^{-1} A P_R^{-T}); normA_fro is then the
+  // norm of that matrix and normA_fro_orig the caller's ||A||_F
+  bool precond = false;
+  nsp::DBuf pdiag;          // p in the library's order of the unknowns
+  double normA_fro_orig = 0.0;
   double maxD = 1.0;        // max of the perturbation diagonal
 
   // perturbation diagonal and start block
@@ -169,6 +175,7 @@ struct nsp_ctx {
 
   // result
   nsp::DBuf V;              // n x N column-major FP64 (final basis)
+  nsp::DBuf Vs;             // preconditioned runs: orthonormal basis of null(A P_R^{-T})
   nsp::DBuf Wd;             // n x defl_r column-major FP64: the Ritz vectors just above
   int32_t defl_r = 0;       // the null cluster, deflation space of the refinement
   // the deflation space after its Rayleigh-Ritz rotation with A^T A (W^T A^T A W =
@@ -202,6 +209,9 @@ void scatter_rows(nsp_ctx* c, int64_t n, int ncols, const int32_t* idx, const do
 void scatter_vals(nsp_ctx* c, const double* src, double* dst);
 void init_random(nsp_ctx* c, const double* D, const double* Omega);
 double matrix_norms(nsp_ctx* c);
+// NSP_PRECOND_JACOBI: p from the stored matrix, stored values -> those of the
+// preconditioned matrix (FP32 copies included); call after matrix_norms
+void precondition(nsp_ctx* c);
 
 // apply_op helper: Y = B X (FP64, column-major, ld)
 void apply_b_colmajor(nsp_ctx* c, const double* X, int64_t ldx, double* Y, int64_t ldy, int ncols);

@@ -93,5 +93,7 @@ void cgls_p(nsp_ctx* c, int64_t n, int k, const double* gnew, const double* gamm
 void cg_wr(nsp_ctx* c, int64_t n, int k, const double* rr, const double* pq, const int* active,
            double* w, const double* p, double* r, const double* q);
 void sub_inplace(nsp_ctx* c, int64_t cnt, double* x, const double* y);
+// x(i, :) /= s[i] (divide) or *= s[i], x row-major rows x k
+void scale_rows(nsp_ctx* c, int64_t rows, int k, const double* s, bool divide, double* x);
 
 }  // namespace nsp

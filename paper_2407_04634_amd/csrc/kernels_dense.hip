@@ -894,6 +894,15 @@ __global__ void k_sub(int64_t cnt, double* __restrict__ x, const double* __restr
   if (i < cnt) x[i] -= y[i];
 }
 
+// x(i, :) /= s[i] or *= s[i] for a row-major rows x k block
+__global__ void k_scale_rows(int64_t rows, int k, const double* __restrict__ s, bool divide,
+                             double* __restrict__ x) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= rows * k) return;
+  const double f = s[t / k];
+  x[t] = divide ? x[t] / f : x[t] * f;
+}
+
 // ===========================================================================
 // host launchers
 // ===========================================================================
@@ -1179,6 +1188,12 @@ void cg_wr(nsp_ctx* c, int64_t n, int k, const double* rr, const double* pq, con
 void sub_inplace(nsp_ctx* c, int64_t cnt, double* x, const double* y) {
   if (cnt <= 0) return;
   k_sub<<<nblk(cnt, 256), 256, 0, c->stream>>>(cnt, x, y);
+  NSP_HIP(hipGetLastError());
+}
+
+void scale_rows(nsp_ctx* c, int64_t rows, int k, const double* s, bool divide, double* x) {
+  if (rows * k <= 0) return;
+  k_scale_rows<<<nblk(rows * k, 256), 256, 0, c->stream>>>(rows, k, s, divide, x);
   NSP_HIP(hipGetLastError());
 }
 

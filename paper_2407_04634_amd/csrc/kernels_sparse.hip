@@ -959,6 +959,68 @@ double matrix_norms(nsp_ctx* c) {
   return c->normA_fro;
 }
 
+// ---------------------------------------------------------------------------
+// Outer preconditioning with a diagonal P_R = diag(p) (Sec. 4.4): the Cholesky
+// factor of M = A^T A (normal form) or M = A (symmetric form) with every
+// off-diagonal entry dropped, p_j = sqrt(M_jj), and p_j = 1 where M_jj is not
+// positive.  Row j of the stored A^T is column j of A.
+// ---------------------------------------------------------------------------
+__global__ void k_jacobi_diag(int64_t n, const int32_t* __restrict__ rp,
+                              const int32_t* __restrict__ ci, const double* __restrict__ val,
+                              bool sym, double* __restrict__ p) {
+  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= n) return;
+  double s = 0.0;
+  for (int32_t q = rp[j]; q < rp[j + 1]; ++q) {
+    if (sym) {
+      if (ci[q] == j) s += val[q];
+    } else {
+      s = fma(val[q], val[q], s);
+    }
+  }
+  p[j] = s > 0.0 ? sqrt(s) : 1.0;
+}
+
+// val(i, j) /= p[j] (cols) and /= p[i] (rows) over a CSR
+__global__ void k_scale_vals(int64_t rows, const int32_t* __restrict__ rp,
+                             const int32_t* __restrict__ ci, const double* __restrict__ p,
+                             bool by_row, bool by_col, double* __restrict__ val) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= rows) return;
+  const double pr = by_row ? p[i] : 1.0;
+  for (int32_t q = rp[i]; q < rp[i + 1]; ++q) {
+    double v = val[q] / pr;
+    if (by_col) v /= p[ci[q]];
+    val[q] = v;
+  }
+}
+
+void precondition(nsp_ctx* c) {
+  c->normA_fro_orig = c->normA_fro;
+  if (c->prm.precond == NSP_PRECOND_NONE) return;
+  const int64_t m = c->m, n = c->n, nnz = c->nnz;
+  c->pdiag.alloc(sizeof(double) * n);
+  double* p = c->pdiag.as<double>();
+  k_jacobi_diag<<<nblocks(n, kThreads), kThreads, 0, c->stream>>>(n, c->AT.rowptr, c->AT.colind,
+                                                                   c->AT.val, c->sym, p);
+  NSP_HIP(hipGetLastError());
+  if (nnz) {
+    // A P^{-T}: columns of A, rows of A^T; P^{-1} A P^{-T}: both sides
+    k_scale_vals<<<nblocks(m, kThreads), kThreads, 0, c->stream>>>(m, c->A.rowptr, c->A.colind, p,
+                                                                    c->sym, true, c->valsA.as<double>());
+    k_scale_vals<<<nblocks(n, kThreads), kThreads, 0, c->stream>>>(n, c->AT.rowptr, c->AT.colind, p,
+                                                                    true, c->sym, c->valsT.as<double>());
+    NSP_HIP(hipGetLastError());
+    if (c->A.val32) {
+      k_to_f32<<<nblocks(nnz, kThreads), kThreads, 0, c->stream>>>(nnz, c->A.val, c->vals32.as<float>());
+      k_to_f32<<<nblocks(nnz, kThreads), kThreads, 0, c->stream>>>(nnz, c->AT.val, c->valsT32.as<float>());
+      NSP_HIP(hipGetLastError());
+    }
+  }
+  c->precond = true;
+  NSP_HIP(hipStreamSynchronize(c->stream));
+}
+
 // Y = B X for column-major FP64 X, Y (apply_op).  Columns go through the
 // row-interleaved path in chunks of at most 8.
 void apply_b_colmajor(nsp_ctx* c, const double* X, int64_t ldx, double* Y, int64_t ldy, int ncols) {

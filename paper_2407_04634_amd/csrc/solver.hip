@@ -564,6 +564,32 @@ void build_deflation(nsp_ctx* c) {
   c->df_r = rk;
 }
 
+// V <- V R^{-1}, R^T R = V^T V (Cholesky QR) for a row-major n x k block V
+void cholqr_rows(nsp_ctx* c, double* vr, int64_t n, int k, DBuf& b_g, DBuf& b_info, DBuf& b_long) {
+  double* g = alloc_as<double>(b_g, (size_t)k * k);
+  rocblas_int* inf = alloc_as<rocblas_int>(b_info, 1);
+  dgemm_nt_long(c, k, k, n, vr, k, vr, k, g, b_long);
+  NSP_BLAS(rocsolver_dpotrf(c->blas, rocblas_fill_upper, k, g, k, inf));
+  NSP_HIP(hipMemcpyAsync(c->pin_i + 8, inf, sizeof(rocblas_int), hipMemcpyDeviceToHost, c->stream));
+  NSP_HIP(hipStreamSynchronize(c->stream));
+  if (c->pin_i[8] != 0) throw Error(NSP_ERR_BREAKDOWN, "refined basis lost rank (Cholesky QR failed)");
+  // V <- V R^{-1}: in the column-major view Vcm = V^T: Vcm <- R^{-T} Vcm
+  const double one = 1.0;
+  NSP_BLAS(rocblas_dtrsm(c->blas, rocblas_side_left, rocblas_fill_upper, rocblas_operation_transpose,
+                         rocblas_diagonal_non_unit, k, (rocblas_int)n, &one, g, k, vr, k));
+}
+
+// Outer preconditioning (Sec. 4.4): vr holds an orthonormal basis V_R of
+// null(A P_R^{-T}) (row-major n x k).  V_R is kept for the backward pass and vr
+// becomes P_R^{-T} V_R, orthonormalised (Cholesky QR twice).
+void unprecondition(nsp_ctx* c, double* vr, int k, DBuf& b_g, DBuf& b_info, DBuf& b_long) {
+  const int64_t n = c->n;
+  rows_to_colmajor(c, n, k, vr, alloc_as<double>(c->Vs, (size_t)n * k), n);
+  scale_rows(c, n, k, c->pdiag.as<double>(), true, vr);
+  cholqr_rows(c, vr, n, k, b_g, b_info, b_long);
+  cholqr_rows(c, vr, n, k, b_g, b_info, b_long);
+}
+
 // ---------------------------------------------------------------------------
 // FP64 refinement: Rayleigh-Ritz with A^T A, CGLS projection onto null(A),
 // Cholesky QR twice, residual and orthogonality checks.
@@ -608,19 +634,7 @@ struct Refiner {
     dgemm_nt_long(c, k, k, rows, a, k, a, k, g, b_long);
   }
 
-  void cholqr(double* vr) {
-    double* g = alloc_as<double>(b_small, (size_t)k * k);
-    rocblas_int* inf = alloc_as<rocblas_int>(b_info, 1);
-    gram_rows(vr, n, g);
-    NSP_BLAS(rocsolver_dpotrf(c->blas, rocblas_fill_upper, k, g, k, inf));
-    NSP_HIP(hipMemcpyAsync(c->pin_i + 8, inf, sizeof(rocblas_int), hipMemcpyDeviceToHost, c->stream));
-    NSP_HIP(hipStreamSynchronize(c->stream));
-    if (c->pin_i[8] != 0) throw Error(NSP_ERR_BREAKDOWN, "refined basis lost rank (Cholesky QR failed)");
-    // V <- V R^{-1}: in the column-major view Vcm = V^T: Vcm <- R^{-T} Vcm
-    const double one = 1.0;
-    NSP_BLAS(rocblas_dtrsm(c->blas, rocblas_side_left, rocblas_fill_upper, rocblas_operation_transpose,
-                           rocblas_diagonal_non_unit, k, (rocblas_int)n, &one, g, k, vr, k));
-  }
+  void cholqr(double* vr) { cholqr_rows(c, vr, n, k, b_small, b_info, b_long); }
 
   void run() {
     nsp_params& p = c->prm;
@@ -776,7 +790,16 @@ struct Refiner {
     // Step 3: orthonormalise (Cholesky QR twice), residual and orthogonality
     cholqr(vr);
     cholqr(vr);
-    spmm_wide(c, c->A, k, vr, u);
+    const double* vres = vr;
+    if (c->precond) {
+      unprecondition(c, vr, k, b_small, b_info, b_long);
+      // A V = (A P^{-T}) (P^T V); P (A P^{-T} ...) for the symmetric form
+      NSP_HIP(hipMemcpyAsync(x, vr, sizeof(double) * n * k, hipMemcpyDeviceToDevice, c->stream));
+      scale_rows(c, n, k, c->pdiag.as<double>(), false, x);
+      vres = x;
+    }
+    spmm_wide(c, c->A, k, vres, u);
+    if (c->precond && c->sym) scale_rows(c, m, k, c->pdiag.as<double>(), false, u);
     coldots(c, m, k, u, u, sn2, part);
     double* g = alloc_as<double>(b_small, (size_t)k * k);
     gram_rows(vr, n, g);
@@ -793,7 +816,7 @@ struct Refiner {
         const double e = hg[i + (size_t)j * k] - (i == j ? 1.0 : 0.0);
         oe += e * e;
       }
-    st.rel_resid_fro = c->normA_fro > 0 ? std::sqrt(res2) / c->normA_fro : std::sqrt(res2);
+    st.rel_resid_fro = c->normA_fro_orig > 0 ? std::sqrt(res2) / c->normA_fro_orig : std::sqrt(res2);
     st.orth_err_fro = std::sqrt(oe);
     rows_to_colmajor(c, n, k, vr, c->V.as<double>(), n);
     NSP_HIP(hipStreamSynchronize(c->stream));
@@ -822,6 +845,15 @@ void solve(nsp_ctx* c) {
     Refiner rf(c, c->nullity);
     rf.run();
   } else if (c->nullity > 0) {
+    if (c->precond) {
+      const int k = c->nullity;
+      DBuf b_vr, b_g, b_info, b_long;
+      double* vr = alloc_as<double>(b_vr, (size_t)c->n * k);
+      colmajor_to_rows(c, c->n, k, c->V.as<double>(), c->n, vr);
+      unprecondition(c, vr, k, b_g, b_info, b_long);
+      rows_to_colmajor(c, c->n, k, vr, c->V.as<double>(), c->n);
+      NSP_HIP(hipStreamSynchronize(c->stream));
+    }
     // orthonormality / residual of the unrefined basis are still reported
     c->stats.rel_resid_fro = -1.0;
     c->stats.orth_err_fro = -1.0;
@@ -910,6 +942,17 @@ void run_backward(nsp_ctx* c, const double* GsV, int64_t ld, double* grad, doubl
     dgemm_nt_long(c, k, kc, n, vr, k, r, kc, vu, b_long);
     dgemm(c, rocblas_operation_transpose, rocblas_operation_none, kc, n, k, -1.0, vu, k, vr, k, 1.0, r, kc);
   }
+  // Outer preconditioning: A^T A W = U is P (A P^{-T})^T (A P^{-T}) P^T W = U, so
+  // the CG solves for X = P^T W with right-hand side P^{-1} U and keeps its
+  // residual orthogonal to null(A P^{-T}) = span(V_R); A W = (A P^{-T}) X.
+  const double* vrange = vr;
+  DBuf b_vs;
+  if (c->precond) {
+    double* vs = alloc_as<double>(b_vs, (size_t)n * k);
+    colmajor_to_rows(c, n, k, c->Vs.as<double>(), n, vs);
+    scale_rows(c, n, kc, c->pdiag.as<double>(), true, r);
+    vrange = vs;
+  }
   double* w = alloc_as<double>(b_w, (size_t)n * kc);
   double* pp = alloc_as<double>(b_p, (size_t)n * kc);
   double* q = alloc_as<double>(b_q, (size_t)n * kc);
@@ -979,8 +1022,9 @@ void run_backward(nsp_ctx* c, const double* GsV, int64_t ld, double* grad, doubl
       // re-project the residual onto range(A^T): V is a null basis only to
       // rounding accuracy, and A^T A cannot reduce a residual component in
       // null(A) (a no-op in exact arithmetic, where r stays in the range)
-      dgemm_nt_long(c, k, kc, n, vr, k, r, kc, mv, b_long);
-      dgemm(c, rocblas_operation_transpose, rocblas_operation_none, kc, n, k, -1.0, mv, k, vr, k, 1.0, r, kc);
+      dgemm_nt_long(c, k, kc, n, vrange, k, r, kc, mv, b_long);
+      dgemm(c, rocblas_operation_transpose, rocblas_operation_none, kc, n, k, -1.0, mv, k, vrange, k, 1.0,
+            r, kc);
       coldots(c, n, kc, r, r, rr, part);
       NSP_HIP(hipMemcpyAsync(c->pin_d, rr, sizeof(double) * kc, hipMemcpyDeviceToHost, c->stream));
       NSP_HIP(hipStreamSynchronize(c->stream));
@@ -997,6 +1041,7 @@ void run_backward(nsp_ctx* c, const double* GsV, int64_t ld, double* grad, doubl
     }
   }
   // W = W_U C (row-major n x k): Wcm (k x n) = C^T W_Ucm; the buffer u is free now
+  // (preconditioned: X = X_U C, and A W = (A P^{-T}) X below)
   double* wf = alloc_as<double>(b_u, (size_t)n * k);
   dgemm(c, rocblas_operation_transpose, rocblas_operation_none, k, n, kc, 1.0, crd, kc, w, kc, 0.0, wf, k);
   // Y = A W, grad_p = -2 <Y_i, V_j>

@@ -39,3 +39,30 @@ def test_default_params_and_binding_symbols():
     p = _lib.default_params()
     assert p.d == 1 and p.max_dim == 64 and abs(p.eps - 1e-3) < 1e-18 and p.refine == 1
     assert set(_lib.EXPORTS) <= set(_declared()) | {"nsp_default_params"}
+
+
+def test_binding_structs_match_the_header_layout(tmp_path):
+    """Offsets and sizes of nsp_params / nsp_stats as the C compiler lays them out."""
+    import shutil
+    import subprocess
+
+    from paper_2407_04634_amd import _lib
+
+    if shutil.which("gcc") is None:
+        pytest.skip("gcc not available")
+    lines = ["#include <stdio.h>", "#include <stddef.h>", '#include "nullspace.h"', "int main(void) {"]
+    for cname, py in (("nsp_params", _lib.Params), ("nsp_stats", _lib.Stats)):
+        lines.append(f'printf("{cname} size %zu\\n", sizeof({cname}));')
+        for f, _ in py._fields_:
+            lines.append(f'printf("{cname} {f} %zu\\n", offsetof({cname}, {f}));')
+    lines += ["return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split("\n")
+    got = {tuple(l.split()[:2]): int(l.split()[2]) for l in out if l}
+    for cname, py in (("nsp_params", _lib.Params), ("nsp_stats", _lib.Stats)):
+        assert got[(cname, "size")] == ctypes.sizeof(py)
+        for f, _ in py._fields_:
+            assert got[(cname, f)] == getattr(py, f).offset, (cname, f)

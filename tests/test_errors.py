@@ -35,6 +35,7 @@ def _init(**kw):
     (dict(prec=7), "precision"),
     (dict(op=5), "op must be"),
     (dict(reorder=3), "reorder"),
+    (dict(precond=2), "precond must be"),
     (dict(op=1, m=120, n=100), "square"),
 ])
 def test_invalid_arguments_are_rejected(kw, msg):

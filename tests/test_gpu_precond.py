@@ -1,0 +1,156 @@
+"""Outer preconditioning with the diagonal P_R (Sec. 4.4) on the GPU vs the oracle and closed forms."""
+import numpy as np
+import pytest
+
+from oracle import exact, lanczos
+from oracle import operator as op
+from oracle import precond as pc
+from workloads import generators as G
+
+pytestmark = pytest.mark.gpu
+
+U = 2.0 ** -52
+
+
+def _smin(a_dense, nullity):
+    s = np.sort(np.linalg.svd(a_dense, compute_uv=False))
+    return s[nullity]
+
+
+@pytest.mark.parametrize("form", ["normal", "sym"])
+def test_apply_op_precond_matches_oracle(form):
+    import torch
+    from paper_2407_04634_amd import OP_NORMAL, OP_SYM, PRECOND_JACOBI
+    from tests.gpu_util import context
+
+    c = G.config("planted20k_scaled", "small") if form == "normal" else G.config("er20")
+    a = c.to_scipy()
+    eps = 1e-3
+    print(f"[precond] apply_op {form}", flush=True)
+    ctx, dv, _ = context(c, eps, op=OP_NORMAL if form == "normal" else OP_SYM, precond=PRECOND_JACOBI)
+    p = pc.jacobi_diagonal(a, form)
+    x = np.random.default_rng(0).standard_normal((c.n, 3))
+    y = ctx.apply_op(torch.from_numpy(x).cuda()).cpu().numpy()
+    ref = pc.apply_b_outer(a, p, eps, dv, x, form)
+    ar = abs(pc.preconditioned_matrix(a, p, form))
+    mag = (ar.T @ (ar @ np.abs(x)) if form == "normal" else ar @ np.abs(x)) + eps * dv[:, None] * np.abs(x)
+    k = 16 + 2 * int(np.diff(a.indptr).max()) + 2 * int(np.diff(a.tocsc().indptr).max())
+    assert np.all(np.abs(y - ref) <= k * U * mag)
+    ctx.close()
+
+
+def test_first_cycle_ritz_values_precond_match_oracle():
+    from paper_2407_04634_amd import PRECOND_JACOBI
+    from tests.gpu_util import context
+
+    c = G.config("planted20k_scaled", "small")
+    a = c.to_scipy()
+    p = pc.jacobi_diagonal(a)
+    ar = pc.preconditioned_matrix(a, p)
+    eps = 0.1 * _smin(ar.toarray(), 10) ** 2
+    print("[precond] first cycle", flush=True)
+    ctx, dv, om = context(c, eps, max_dim=64, refine=0, max_cycles=1, precond=PRECOND_JACOBI)
+    ctx.lanczos_run(allow_noconv=True)
+    th = np.array(ctx.ritz_values())
+    r = lanczos.algorithm2(ar, eps, dv, om, 64, max_cycles=1)
+    assert th.shape == r["theta"].shape
+    assert np.max(np.abs(th - r["theta"])) < 1e-9 * op.norm_upper_bound_ata(ar)
+
+
+@pytest.mark.parametrize("prec,refine_on", [(0, 1), (1, 1), (0, 0)])
+def test_column_scaled_planted_nullity_and_subspace(prec, refine_on):
+    """Two decades of column scaling: the preconditioned solve recovers the
+    closed-form null space S^{-1} range([-R; I]) of A S."""
+    from paper_2407_04634_amd import PRECOND_JACOBI
+    from tests.gpu_util import context
+
+    c = G.config("planted20k_scaled", "small")
+    a = c.to_scipy()
+    ar = pc.preconditioned_matrix(a, pc.jacobi_diagonal(a))
+    smin = _smin(ar.toarray(), 10)
+    eps = 0.1 * smin ** 2
+    print(f"[precond] scaled planted prec={prec} refine={refine_on}", flush=True)
+    ctx, dv, om = context(c, eps, max_dim=128, prec=prec, refine=refine_on, precond=PRECOND_JACOBI)
+    st = ctx.lanczos_run()
+    assert st["nullity"] == 10
+    v = ctx.extract_basis().cpu().numpy()
+    v0 = exact.column_scaled_basis(exact.planted_basis(c.meta["R"]), c.meta["col_scale"])
+    assert exact.orth_error_fro(v) <= 1e-12
+    if refine_on:
+        assert exact.max_angle_sine(v, v0) <= 1e-8
+        assert st["rel_resid_fro"] <= 1e-8
+        afro = np.sqrt(np.sum(a.data ** 2))
+        assert abs(np.linalg.norm(a @ v) / afro - st["rel_resid_fro"]) <= 1e-2 * st["rel_resid_fro"] + 1e-13
+    else:
+        # Ritz vectors v_R of B_R with Ritz values theta < 3 eps have
+        # ||A P^{-T} v_R||^2 <= theta; V = P^{-T} V_R R^{-1} with ||R^{-1}|| <= max p
+        pmax = pc.jacobi_diagonal(a).max()
+        assert np.linalg.norm(a @ v) <= 1.01 * np.sqrt(3 * eps * 10) * pmax
+    # same nullity as the oracle's Algorithm 2 on A P^{-T} with the same D and Omega
+    r = lanczos.algorithm2(ar, eps, dv, om, 128)
+    assert r["N"] == st["nullity"]
+
+
+def test_er20_sym_precond():
+    """Symmetric form with p = sqrt(deg): Lanczos on the normalised Laplacian; the
+    indicators come back after P^{-T}."""
+    from paper_2407_04634_amd import OP_SYM, PRECOND_JACOBI
+    from tests.gpu_util import context
+
+    c = G.config("er20")
+    a = c.to_scipy()
+    ar = pc.preconditioned_matrix(a, pc.jacobi_diagonal(a, "sym"), "sym").toarray()
+    lam = np.sort(np.linalg.eigvalsh(ar))
+    eps = 0.1 * lam[20]
+    print("[precond] er20 sym", flush=True)
+    ctx, dv, om = context(c, eps, max_dim=64, op=OP_SYM, precond=PRECOND_JACOBI)
+    st = ctx.lanczos_run()
+    assert st["nullity"] == 20
+    v = ctx.extract_basis().cpu().numpy()
+    assert exact.max_angle_sine(v, exact.indicator_basis(c.meta["labels"])) <= 1e-8
+    assert st["rel_resid_fro"] <= 1e-8
+    r = lanczos.algorithm2(pc.preconditioned_matrix(a, pc.jacobi_diagonal(a, "sym"), "sym"), eps, dv, om,
+                           64, op="sym")
+    assert r["N"] == 20
+
+
+def test_backward_precond_matches_dense_gradient():
+    """The gradient does not depend on P_R: the preconditioned CG gives the dense
+    closed-form gradient, on a column-scaled copy of the finite-difference instance."""
+    import torch
+    from oracle import backward as bw
+    from paper_2407_04634_amd import PRECOND_JACOBI
+    from tests.gpu_util import context
+
+    c = G.column_scaled(G.fd_instance(), 2.0, 21)
+    a = c.to_scipy()
+    ad = a.toarray()
+    ar = pc.preconditioned_matrix(a, pc.jacobi_diagonal(a)).toarray()
+    smin = _smin(ar, 8)
+    print("[precond] fd300 scaled backward", flush=True)
+    ctx, dv, om = context(c, 0.1 * smin ** 2, d=1, max_dim=64, tol_abs_resid=1e-12 * smin,
+                          tol_rel_resid=0.0, precond=PRECOND_JACOBI)
+    assert ctx.lanczos_run()["nullity"] == 8
+    v = ctx.extract_basis().cpu().numpy()
+    x = G.gaussian_matrix(c.n, 8, seed=5)
+    gsv = bw.gsv_pxf(v, x)
+    grad, it = ctx.backward(torch.from_numpy(gsv).cuda(), tol=1e-13)
+    grad = grad.cpu().numpy()
+    rows = np.repeat(np.arange(c.m), np.diff(c.rowptr))
+    ref = bw.dense_grad(ad, 8, bw.gs_pxf(x), rows, c.colind)
+    assert np.linalg.norm(grad - ref) <= 1e-6 * np.linalg.norm(ref)
+
+
+def test_backward_rejects_preconditioned_symmetric_form():
+    import torch
+    from paper_2407_04634_amd import OP_SYM, PRECOND_JACOBI, NspError
+    from tests.gpu_util import context
+
+    c = G.config("er20")
+    print("[precond] sym backward rejected", flush=True)
+    ctx, _, _ = context(c, 0.03, max_dim=64, op=OP_SYM, precond=PRECOND_JACOBI)
+    ctx.lanczos_run()
+    g = torch.zeros((c.n, ctx.nullity()), dtype=torch.float64, device="cuda")
+    with pytest.raises(NspError) as e:
+        ctx.backward(g)
+    assert "preconditioned symmetric" in str(e.value)
