@@ -265,6 +265,60 @@ def mixed_vs_fp64(name="zipf400k", max_dim=256, eps=1e-2):
             "speedup_mixed": runs[0]["s"] / runs[1]["s"]}
 
 
+def precond_vs_plain(name="planted20k_scaled", eps_pre=3.4e-8, eps_plain=2.2e-8, budget_factor=5):
+    """Outer preconditioning with the diagonal P_R (Sec. 4.4) against none.
+
+    A planted matrix whose columns are scaled over two decades (A S, S diagonal):
+    the Jacobi P_R undoes the scaling.  eps is 0.1 sigma_min^2 of the matrix each
+    run iterates with (A P_R^{-T}: sigma^2 ~ 3.4e-7; A S: sigma^2 ~ 2.2e-7, from
+    theta_next - eps max D of earlier runs).  The preconditioned solve is refined
+    and checked against the closed-form null space S^{-1} range([-R; I]); the
+    plain one gets budget_factor times the preconditioned run's matvecs (no
+    refinement) and reports how much of the null space it found.
+    """
+    import torch
+    from paper_2407_04634_amd import Context, PRECOND_JACOBI, PRECOND_NONE
+    from oracle import exact
+    from workloads import generators as G
+
+    c = G.config(name)
+    v0 = torch.from_numpy(exact.column_scaled_basis(exact.planted_basis(c.meta["R"]),
+                                                    c.meta["col_scale"])).cuda()
+    rp, ci, va = (torch.from_numpy(c.rowptr).cuda(), torch.from_numpy(c.colind).cuda(),
+                  torch.from_numpy(c.vals).cuda())
+    dv = torch.from_numpy(G.perturbation_diagonal(c.n, 1)).cuda()
+    om = torch.from_numpy(np.ascontiguousarray(G.gaussian_start_block(c.n, 1, 1))).cuda()
+    runs = []
+    budget = 20_000_000
+    for pre in ("jacobi", "none"):
+        jac = pre == "jacobi"
+        kw = dict(eps=eps_pre, max_dim=512, refine=1, max_matvec=budget) if jac else \
+            dict(eps=eps_plain, max_dim=1024, refine=0, max_matvec=budget)
+        ctx = Context(rp, ci, va, c.m, c.n, D=dv, Omega=om, d=1, tol_angle=1e-9, tol_rel_resid=1e-10,
+                      precond=PRECOND_JACOBI if jac else PRECOND_NONE, **kw)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        st = ctx.lanczos_run(allow_noconv=True)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        v = ctx.extract_basis().contiguous()
+        sine = max_sine(v, v0) if v.shape[1] == v0.shape[1] else None
+        runs.append({"precond": pre, "s": t1 - t0, "status": st["status"], "nullity": st["nullity"],
+                     "matvecs": st["matvecs"], "eps": kw["eps"], "max_dim": kw["max_dim"],
+                     "norm_b": st["norm_b"], "theta_next": st["theta_next"],
+                     "refine_iters": st["refine_iters"], "max_sin_angle": sine,
+                     "rel_resid_fro": st["rel_resid_fro"] if jac else None,
+                     "valid": bool(jac and st["nullity"] == v0.shape[1] and sine is not None
+                                   and sine <= 1e-8 and st["rel_resid_fro"] <= 1e-8)})
+        print(f"[bench] precond_vs_plain {json.dumps(runs[-1])}", file=sys.stderr, flush=True)
+        ctx.close()
+        if jac:
+            budget = budget_factor * st["matvecs"]
+    return {"workload": name, "n": c.n, "nnz": c.nnz, "nullity": v0.shape[1],
+            "desc": "planted A=[B, BR] (n=20000, nullity 50) times a diagonal S with log10 S ~ U[-1, 1]",
+            "runs": runs}
+
+
 def backward_at_scale(ctx, n, nnz, v, tol=1e-10):
     """The backward pass after the timed solve.
 
@@ -308,6 +362,8 @@ def main():
                     help="comma-separated large matrices for the SpMV HBM measurement ('none' to skip)")
     ap.add_argument("--mixed-workload", default="zipf400k",
                     help="Laplacian for the mixed-vs-FP64 comparison ('none' to skip)")
+    ap.add_argument("--precond-workload", default="planted20k_scaled",
+                    help="column-scaled instance for the Jacobi-preconditioned vs plain comparison; 'none' skips")
     ap.add_argument("--no-backward", action="store_true", help="skip the backward pass after the solve")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run the plain copy that scales the rocprofv3 byte counters")
@@ -416,6 +472,8 @@ def main():
         print(f"[bench] backward {json.dumps(line['backward'])}", file=sys.stderr, flush=True)
     if args.mixed_workload != "none":
         line["mixed_vs_fp64"] = mixed_vs_fp64(args.mixed_workload)
+    if args.precond_workload != "none":
+        line["precond_vs_plain"] = precond_vs_plain(args.precond_workload)
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(c, eps, args.d, max_dim, st)
     print(json.dumps(line), flush=True)
