@@ -75,48 +75,80 @@ __device__ double fro(int k, const double* a) {
 __device__ void wrec_block(const WArgs& a, double gi, double* red) {
   const int t = threadIdx.x, ell = a.ell, l0 = a.l0;
   const int lane = t % kWave, wid = t / kWave, nw = blockDim.x / kWave;
-  double* w = a.w;
   const int ldw = a.ldw;
-  auto W = [&](int k, int j) -> double& { return w[k + (int64_t)j * ldw]; };
-  double s = 0.0;
-  for (int i = 1 + t; i <= l0; i += blockDim.x) s += W(i, ell) * a.n_f[i];
-  s = wave_sum(s);
-  if (lane == 0) red[wid] = s;
-  __syncthreads();
-  double sum_f = 0.0;
-  for (int q = 0; q < nw; ++q) sum_f += red[q];
-  __syncthreads();
-  double mx = 0.0;
-  for (int k = 1 + t; k <= ell; k += blockDim.x) {
-    double v;
-    if (k == ell) {
-      v = a.u_d;
-    } else if (k <= l0) {
-      v = gi * (W(k, ell) * (a.n_theta[k] + a.n_xi[ell]) + W(l0 + 1, ell) * a.n_f[k] +
-                W(k, ell - 1) * a.n_gam[ell - 1] + 2.0 * a.u_d);
-    } else if (k == l0 + 1) {
-      double acc = W(k, ell) * (a.n_xi[k] + a.n_xi[ell]) + sum_f + 2.0 * a.u_d;
-      if (k < ell - 1) acc += W(k + 1, ell) * a.n_gam[k] + W(k, ell - 1) * a.n_gam[ell - 1];
-      v = gi * acc;
-    } else {
-      double acc = W(k, ell) * (a.n_xi[k] + a.n_xi[ell]) + W(k - 1, ell) * a.n_gam[k - 1] + 2.0 * a.u_d;
-      if (k < ell - 1) acc += W(k + 1, ell) * a.n_gam[k] + W(k, ell - 1) * a.n_gam[ell - 1];
-      v = gi * acc;
+  // columns ell-1, ell (read) and ell+1 (written) of W are disjoint
+  const double* __restrict__ wc = a.w + (int64_t)ell * ldw;
+  const double* __restrict__ wp = a.w + (int64_t)(ell - 1) * ldw;
+  double* __restrict__ wn = a.w + (int64_t)(ell + 1) * ldw;
+  const double w_top = wc[l0 + 1], nxi_l = a.n_xi[ell], ngam_lm = a.n_gam[ell - 1];
+  __shared__ double s_top[5];  // inputs of row l0+1, which needs the sum over the kept rows
+  // Rows k = 1..ell, R per thread per pass: every load of a pass is issued
+  // before the first store, so a pass costs one memory round trip.
+  constexpr int R = 4;
+  double sum_f = 0.0, mx = 0.0;
+  for (int base = 1; base <= ell; base += R * (int)blockDim.x) {
+    double wk[R], wkm[R], wkp[R], wpr[R], nt[R], nf[R], nx[R], ng[R], ngm[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const int k = base + t + r * (int)blockDim.x;
+      if (k <= ell) {
+        wk[r] = wc[k]; wkm[r] = wc[k - 1]; wkp[r] = wc[k + 1]; wpr[r] = wp[k];
+        nt[r] = a.n_theta[k]; nf[r] = a.n_f[k]; nx[r] = a.n_xi[k]; ng[r] = a.n_gam[k];
+        ngm[r] = a.n_gam[k - 1];
+      }
     }
-    W(k, ell + 1) = v;
-    if (k < ell) mx = (v == v) ? fmax(mx, v) : INFINITY;  // a NaN bound forces a reorthogonalisation
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const int k = base + t + r * (int)blockDim.x;
+      if (k > ell) continue;
+      double v;
+      if (k == ell) {
+        v = a.u_d;
+      } else if (k <= l0) {
+        sum_f += wk[r] * nf[r];
+        v = gi * (wk[r] * (nt[r] + nxi_l) + w_top * nf[r] + wpr[r] * ngam_lm + 2.0 * a.u_d);
+      } else if (k == l0 + 1) {
+        s_top[0] = wk[r]; s_top[1] = nx[r]; s_top[2] = wkp[r]; s_top[3] = ng[r]; s_top[4] = wpr[r];
+        continue;  // finished below, once sum_f is known
+      } else {
+        double acc = wk[r] * (nx[r] + nxi_l) + wkm[r] * ngm[r] + 2.0 * a.u_d;
+        if (k < ell - 1) acc += wkp[r] * ng[r] + wpr[r] * ngam_lm;
+        v = gi * acc;
+      }
+      wn[k] = v;
+      if (k < ell) mx = (v == v) ? fmax(mx, v) : INFINITY;  // a NaN bound forces a reorthogonalisation
+    }
   }
+  sum_f = wave_sum(sum_f);
 #pragma unroll
   for (int off = kWave / 2; off > 0; off >>= 1) mx = fmax(mx, __shfl_xor(mx, off, kWave));
-  if (lane == 0) red[wid] = mx;
+  if (lane == 0) {
+    red[wid] = sum_f;
+    red[nw + wid] = mx;
+  }
   __syncthreads();
-  double m = 0.0;
-  for (int q = 0; q < nw; ++q) m = fmax(m, red[q]);
-  const bool need = m > a.u_ro;
+  if (t == 0) {
+    double sf = 0.0, m = 0.0;
+    for (int q = 0; q < nw; ++q) {
+      sf += red[q];
+      m = fmax(m, red[nw + q]);
+    }
+    const int k = l0 + 1;
+    if (k < ell) {
+      double acc = s_top[0] * (s_top[1] + nxi_l) + sf + 2.0 * a.u_d;
+      if (k < ell - 1) acc += s_top[2] * s_top[3] + s_top[4] * ngam_lm;
+      const double v = gi * acc;
+      wn[k] = v;
+      m = (v == v) ? fmax(m, v) : INFINITY;
+    }
+    red[0] = m;
+  }
   __syncthreads();
+  const bool need = red[0] > a.u_ro;
   if (need) {
-    for (int k = 1 + t; k < ell; k += blockDim.x) W(k, ell) = a.u_d;
-    for (int k = 1 + t; k <= ell; k += blockDim.x) W(k, ell + 1) = a.u_d;
+    double* wcw = a.w + (int64_t)ell * ldw;
+    for (int k = 1 + t; k < ell; k += blockDim.x) wcw[k] = a.u_d;
+    for (int k = 1 + t; k <= ell; k += blockDim.x) wn[k] = a.u_d;
   }
   if (t == 0) {
     a.flags[0] = need ? 1 : 0;
@@ -356,7 +388,7 @@ __global__ void k_w_reset(int col0, int ncols, double u_d, double* w, int ldw) {
 // ---------------------------------------------------------------------------
 // Tall-skinny pair of the (partial) reorthogonalisation, classical
 // Gram-Schmidt (Sec. 4.2):
-//   H = Z^T C   (k x NC)  k_ts_tn writes per-row-chunk partials, k_reduce_cols sums them
+//   H = Z^T C   (k x NC)  k_ts_tn: per-row-chunk partials, summed by the last block of each column group
 //   C = C - Z H           k_ts_nn
 // C is NC columns held as NA row-interleaved arrays of DA columns each
 // (NC = NA * DA): for the reorthogonalisation of [Q_ell, Q_ell+1] NA = 2.
@@ -405,11 +437,16 @@ __device__ __forceinline__ void load_rows(const VT* __restrict__ p, int64_t r, i
   }
 }
 
-// grid (row chunks, column groups); wave w of a block owns JW columns, lanes stride rows
+// grid (row chunks, column groups); wave w of a block owns JW columns, lanes
+// stride rows.  The block of a column group that finishes last (arrival
+// counter per group) sums the group's partials over the row chunks in chunk
+// order into h: deterministic, and no separate reduction launch.
 template <typename VT, int DA, int NA>
 __global__ __launch_bounds__(kThreads) void k_ts_tn(const int* cond, int64_t n, int64_t chunk,
                                                     const VT* __restrict__ z, int64_t ldz, int k,
-                                                    CPair<VT, DA, NA> cc, double* __restrict__ hpart) {
+                                                    CPair<VT, DA, NA> cc, double* __restrict__ hpart,
+                                                    unsigned* __restrict__ arrive,
+                                                    double* __restrict__ h) {
   constexpr int NC = DA * NA;
   constexpr int JW = TsShape<NC, sizeof(VT)>::JW;
   if (cond && *cond == 0) return;
@@ -467,25 +504,27 @@ __global__ __launch_bounds__(kThreads) void k_ts_tn(const int* cond, int64_t n, 
       const double v = wave_sum(acc[q][c]);
       if (lane == 0 && q < jn) hpart[((int64_t)blockIdx.x * k + j0 + q) * NC + c] = v;
     }
-}
-
-// out[v] = sum_b part[b * nv + v]  (fixed order); 32 values x 8 part-groups per block
-__global__ __launch_bounds__(256) void k_reduce_cols(const int* cond, int nparts, int nv,
-                                                     const double* __restrict__ part,
-                                                     double* __restrict__ out) {
-  if (cond && *cond == 0) return;
-  __shared__ double sm[256];
-  const int vl = threadIdx.x % 32, g = threadIdx.x / 32;
-  const int v = blockIdx.x * 32 + vl;
-  double s = 0.0;
-  if (v < nv)
-    for (int b = g; b < nparts; b += 8) s += part[(size_t)b * nv + v];
-  sm[threadIdx.x] = s;
-  __syncthreads();
-  if (g == 0 && v < nv) {
-    double r = 0.0;
-    for (int q = 0; q < 8; ++q) r += sm[q * 32 + vl];
-    out[v] = r;
+  if (!last_block_arrives(arrive + blockIdx.y, gridDim.x)) return;
+  constexpr int JB = TsShape<NC, sizeof(VT)>::JB;
+  constexpr int G = kThreads / 64;  // chunk subsets summed side by side
+  __shared__ double red[kThreads];
+  const int jg = blockIdx.y * JB;
+  const int nv = min(JB, k - jg) * NC;
+  const int vl = threadIdx.x % 64, g = threadIdx.x / 64;
+  for (int v0 = 0; v0 < nv; v0 += 64) {
+    const int v = v0 + vl;
+    double s = 0.0;
+    if (v < nv)
+      for (int b = g; b < (int)gridDim.x; b += G) s += hpart[((int64_t)b * k + jg) * NC + v];
+    red[threadIdx.x] = s;
+    __syncthreads();
+    if (g == 0 && v < nv) {
+      double r = 0.0;
+#pragma unroll
+      for (int q = 0; q < G; ++q) r += red[q * 64 + vl];
+      h[(int64_t)jg * NC + v] = r;
+    }
+    __syncthreads();
   }
 }
 
@@ -1018,11 +1057,10 @@ static void ts_proj_t(nsp_ctx* c, const int* cond, int64_t n, const VT* z, int64
     const int64_t chunk = ts_chunk_rows(n, k, NC, (int)sizeof(VT));
     const unsigned nchunks = (unsigned)((n + chunk - 1) / chunk);
     const unsigned gy = (unsigned)((k + TsShape<NC, sizeof(VT)>::JB - 1) / TsShape<NC, sizeof(VT)>::JB);
-    k_ts_tn<VT, DA, NA><<<dim3(nchunks, gy), kThreads, 0, c->stream>>>(cond, n, chunk, z, ldz, k, cc,
-                                                                        hpart);
+    if (gy > (unsigned)kArriveMax) throw Error(NSP_ERR_ARG, "too many basis columns for the projection");
+    k_ts_tn<VT, DA, NA><<<dim3(nchunks, gy), kThreads, 0, c->stream>>>(
+        cond, n, chunk, z, ldz, k, cc, hpart, c->arrive.as<unsigned>(), h);
     if (ev_tn) NSP_HIP(hipEventRecord(ev_tn, c->stream));
-    k_reduce_cols<<<nblk((int64_t)k * NC, 32), 256, 0, c->stream>>>(cond, (int)nchunks, k * NC,
-                                                                    hpart, h);
   } else if (ev_tn) {
     NSP_HIP(hipEventRecord(ev_tn, c->stream));
   }
