@@ -37,6 +37,8 @@ TRAFFIC = {
     # FETCH_SIZE 152725 KiB x 2.0 + WRITE_SIZE 794 KiB x 1.0 per launch that
     # reorthogonalised, against 306.9 MB algorithmic in the same 40-cycle run
     ("planted50k", 1, "fp64", "k_ts_nn_v"): {"ratio": 1.022},
+    # FETCH_SIZE 160715 KiB x 2.0 + WRITE_SIZE (partials) 612 KiB, against 306.1 MB
+    ("planted50k", 1, "fp64", "k_ts_tn"): {"ratio": 1.077},
 }
 
 # eps = c * sigma_min(A)^2 with c ~ 0.1 (Remark after Thm. "thmmain" asks for c < 1/3);
@@ -163,7 +165,7 @@ def kernel_rooflines(st, m, n, nnz, d, esize, sym=False, stream=False):
     if na > 0:
         # launches at steps whose W-recurrence flag was clear return at once; the
         # figures below are per launch that reorthogonalised
-        out.append(("k_ts_tn (H = Z^T [q_l, q_l+1], partials summed in-kernel)", st["ro_tn_ms"] / na * 1e3,
+        out.append(("k_ts_tn (H = Z^T [q_l, q_l+1], per-chunk partials)", st["ro_tn_ms"] / na * 1e3,
                     st["ro_tn_bytes"] / na))
         out.append(("k_ts_nn_v ([q_l, q_l+1] -= Z H, fused Gram)", st["ro_nn_ms"] / na * 1e3,
                     st["ro_nn_bytes"] / na))

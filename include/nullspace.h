@@ -145,9 +145,8 @@ typedef struct {
   double t_spmv_at_us;     /* profile: mean duration of one fused A^T launch (us)       */
   int64_t spmv_samples;    /* profile: number of timed launch pairs                     */
   double ro_tn_ms;         /* profile: summed duration of the sampled projection
-                              launches H = Z^T [Q_l, Q_l+1] (their partial sums are
-                              reduced inside the launch) at steps that
-                              reorthogonalised, ms                                   */
+                              launches H = Z^T [Q_l, Q_l+1] (partials per row chunk)
+                              at steps that reorthogonalised, ms                      */
   double ro_tn_bytes;      /* ... their algorithmic bytes, (k n + 2 d n) elements each */
   double ro_nn_ms;         /* profile: same for the updates [Q_l, Q_l+1] -= Z H, ms   */
   double ro_nn_bytes;      /* ... (k n + 4 d n) elements each                          */

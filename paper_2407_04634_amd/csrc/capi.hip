@@ -124,8 +124,6 @@ nsp_status nullspace_init(nsp_ctx** out, int64_t m, int64_t n, int64_t nnz, cons
     c->part_xi.alloc(sizeof(double) * (nsp::kStreamBlocks + 1) * nsp::kMaxD * nsp::kMaxD);
     c->part_g.alloc(sizeof(double) * nsp::kRedBlocks * nsp::kMaxD * nsp::kMaxD);
     c->part_g2.alloc(sizeof(double) * nsp::kRedBlocks * nsp::kMaxD * nsp::kMaxD);
-    c->arrive.alloc(sizeof(unsigned) * nsp::kArriveMax);
-    NSP_HIP(hipMemsetAsync(c->arrive.p, 0, sizeof(unsigned) * nsp::kArriveMax, c->stream));
     nsp::prepare_matrix(c, rowptr, colind, vals);
     nsp::init_random(c, D, Omega);
     nsp::matrix_norms(c);

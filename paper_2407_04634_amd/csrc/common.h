@@ -70,7 +70,6 @@ struct DBuf {
 };
 
 constexpr int kMaxD = 8;            // largest supported block size
-constexpr int kArriveMax = 4096;   // arrival counters of the in-kernel reductions
 constexpr int kRedBlocks = 512;     // grid cap of kernels that write per-block partials
 constexpr int kWideBlocks = 1024;   // grid cap of the many-column SpMM (its partials: x k)
 constexpr int kDeflMax = 256;       // deflation vectors of the refinement (at most)
@@ -173,7 +172,6 @@ struct nsp_ctx {
   nsp::DBuf flags;          // device ints: [0] reorth flag, [1] breakdown, [2] nonfinite,
                             // [3] reorth event counter
   nsp::DBuf part_xi, part_g, part_g2, part_c;  // per-block partials of the step reductions
-  nsp::DBuf arrive;         // kArriveMax unsigned arrival counters (zero between launches)
 
   // result
   nsp::DBuf V;              // n x N column-major FP64 (final basis)

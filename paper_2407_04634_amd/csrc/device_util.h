@@ -1,6 +1,5 @@
-// Device helpers: wavefront / block reductions, fixed-order sums of per-block
-// partials, and the arrival test of kernels whose last block finishes a
-// reduction.
+// Device helpers: wavefront / block reductions and fixed-order sums of
+// per-block partials written by an earlier kernel.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -70,26 +69,6 @@ __device__ __forceinline__ void reduce_partials(const double* __restrict__ part,
     res[t] = r;
   }
   __syncthreads();
-}
-
-// Arrival test for a reduction finished inside the kernel: every block calls it
-// after writing its partials; it returns true in exactly one block, the last
-// of ``nblocks`` to arrive at ``counter``, whose threads then see every other
-// block's partials (device-scope release before the count, acquire after it).
-// That block resets the counter for the next launch.  Counters start at 0.
-__device__ __forceinline__ bool last_block_arrives(unsigned* counter, unsigned nblocks) {
-  __shared__ unsigned s_last;
-  __threadfence();
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    const unsigned prev = atomicAdd(counter, 1u);
-    s_last = prev == nblocks - 1 ? 1u : 0u;
-    if (s_last) atomicExch(counter, 0u);
-  }
-  __syncthreads();
-  const bool last = s_last != 0;
-  if (last) __threadfence();
-  return last;
 }
 
 }  // namespace nsp

@@ -388,7 +388,7 @@ __global__ void k_w_reset(int col0, int ncols, double u_d, double* w, int ldw) {
 // ---------------------------------------------------------------------------
 // Tall-skinny pair of the (partial) reorthogonalisation, classical
 // Gram-Schmidt (Sec. 4.2):
-//   H = Z^T C   (k x NC)  k_ts_tn: per-row-chunk partials, summed by the last block of each column group
+//   H = Z^T C   (k x NC)  k_ts_tn writes per-row-chunk partials, k_reduce_cols sums them
 //   C = C - Z H           k_ts_nn
 // C is NC columns held as NA row-interleaved arrays of DA columns each
 // (NC = NA * DA): for the reorthogonalisation of [Q_ell, Q_ell+1] NA = 2.
@@ -437,16 +437,11 @@ __device__ __forceinline__ void load_rows(const VT* __restrict__ p, int64_t r, i
   }
 }
 
-// grid (row chunks, column groups); wave w of a block owns JW columns, lanes
-// stride rows.  The block of a column group that finishes last (arrival
-// counter per group) sums the group's partials over the row chunks in chunk
-// order into h: deterministic, and no separate reduction launch.
+// grid (row chunks, column groups); wave w of a block owns JW columns, lanes stride rows
 template <typename VT, int DA, int NA>
 __global__ __launch_bounds__(kThreads) void k_ts_tn(const int* cond, int64_t n, int64_t chunk,
                                                     const VT* __restrict__ z, int64_t ldz, int k,
-                                                    CPair<VT, DA, NA> cc, double* __restrict__ hpart,
-                                                    unsigned* __restrict__ arrive,
-                                                    double* __restrict__ h) {
+                                                    CPair<VT, DA, NA> cc, double* __restrict__ hpart) {
   constexpr int NC = DA * NA;
   constexpr int JW = TsShape<NC, sizeof(VT)>::JW;
   if (cond && *cond == 0) return;
@@ -504,27 +499,25 @@ __global__ __launch_bounds__(kThreads) void k_ts_tn(const int* cond, int64_t n, 
       const double v = wave_sum(acc[q][c]);
       if (lane == 0 && q < jn) hpart[((int64_t)blockIdx.x * k + j0 + q) * NC + c] = v;
     }
-  if (!last_block_arrives(arrive + blockIdx.y, gridDim.x)) return;
-  constexpr int JB = TsShape<NC, sizeof(VT)>::JB;
-  constexpr int G = kThreads / 64;  // chunk subsets summed side by side
-  __shared__ double red[kThreads];
-  const int jg = blockIdx.y * JB;
-  const int nv = min(JB, k - jg) * NC;
-  const int vl = threadIdx.x % 64, g = threadIdx.x / 64;
-  for (int v0 = 0; v0 < nv; v0 += 64) {
-    const int v = v0 + vl;
-    double s = 0.0;
-    if (v < nv)
-      for (int b = g; b < (int)gridDim.x; b += G) s += hpart[((int64_t)b * k + jg) * NC + v];
-    red[threadIdx.x] = s;
-    __syncthreads();
-    if (g == 0 && v < nv) {
-      double r = 0.0;
-#pragma unroll
-      for (int q = 0; q < G; ++q) r += red[q * 64 + vl];
-      h[(int64_t)jg * NC + v] = r;
-    }
-    __syncthreads();
+}
+
+// out[v] = sum_b part[b * nv + v]  (fixed order); 32 values x 8 part-groups per block
+__global__ __launch_bounds__(256) void k_reduce_cols(const int* cond, int nparts, int nv,
+                                                     const double* __restrict__ part,
+                                                     double* __restrict__ out) {
+  if (cond && *cond == 0) return;
+  __shared__ double sm[256];
+  const int vl = threadIdx.x % 32, g = threadIdx.x / 32;
+  const int v = blockIdx.x * 32 + vl;
+  double s = 0.0;
+  if (v < nv)
+    for (int b = g; b < nparts; b += 8) s += part[(size_t)b * nv + v];
+  sm[threadIdx.x] = s;
+  __syncthreads();
+  if (g == 0 && v < nv) {
+    double r = 0.0;
+    for (int q = 0; q < 8; ++q) r += sm[q * 32 + vl];
+    out[v] = r;
   }
 }
 
@@ -1057,10 +1050,11 @@ static void ts_proj_t(nsp_ctx* c, const int* cond, int64_t n, const VT* z, int64
     const int64_t chunk = ts_chunk_rows(n, k, NC, (int)sizeof(VT));
     const unsigned nchunks = (unsigned)((n + chunk - 1) / chunk);
     const unsigned gy = (unsigned)((k + TsShape<NC, sizeof(VT)>::JB - 1) / TsShape<NC, sizeof(VT)>::JB);
-    if (gy > (unsigned)kArriveMax) throw Error(NSP_ERR_ARG, "too many basis columns for the projection");
-    k_ts_tn<VT, DA, NA><<<dim3(nchunks, gy), kThreads, 0, c->stream>>>(
-        cond, n, chunk, z, ldz, k, cc, hpart, c->arrive.as<unsigned>(), h);
+    k_ts_tn<VT, DA, NA><<<dim3(nchunks, gy), kThreads, 0, c->stream>>>(cond, n, chunk, z, ldz, k, cc,
+                                                                        hpart);
     if (ev_tn) NSP_HIP(hipEventRecord(ev_tn, c->stream));
+    k_reduce_cols<<<nblk((int64_t)k * NC, 32), 256, 0, c->stream>>>(cond, (int)nchunks, k * NC,
+                                                                    hpart, h);
   } else if (ev_tn) {
     NSP_HIP(hipEventRecord(ev_tn, c->stream));
   }

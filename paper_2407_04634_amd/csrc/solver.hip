@@ -226,7 +226,6 @@ struct Lanczos {
     hpart = alloc_as<double>(b_hpart, (size_t)maxchunks * (K + d) * 2 * d);
     flags = alloc_as<int>(c->flags, 8);
     NSP_HIP(hipMemsetAsync(flags, 0, sizeof(int) * 8, c->stream));
-    NSP_HIP(hipMemsetAsync(c->arrive.p, 0, sizeof(unsigned) * kArriveMax, c->stream));
     NSP_HIP(hipMemsetAsync(W, 0, sizeof(double) * ldw * ldw, c->stream));
     NSP_HIP(hipMemsetAsync(nrm_theta, 0, sizeof(double) * nb, c->stream));
     NSP_HIP(hipMemsetAsync(nrm_f, 0, sizeof(double) * nb, c->stream));
