@@ -470,6 +470,13 @@ def main():
     if not args.no_backward and not partial:
         line["backward"] = backward_at_scale(ctx, c.n, c.nnz, v)
         print(f"[bench] backward {json.dumps(line['backward'])}", file=sys.stderr, flush=True)
+    # new values for the same pattern (an optimisation loop's next step): the
+    # same values again, so the cost is the refresh alone (drops the basis)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ctx.update_values(va)
+    torch.cuda.synchronize()
+    line["update_values_ms"] = (time.perf_counter() - t0) * 1e3
     if args.mixed_workload != "none":
         line["mixed_vs_fp64"] = mixed_vs_fp64(args.mixed_workload)
     if args.precond_workload != "none":

@@ -168,8 +168,8 @@ void nsp_default_params(nsp_params* p);
 /* Create a solver context for A (m x n, nnz stored entries, CSR).
  *  rowptr  [m+1] int64, device; rowptr[0] = 0, non-decreasing, rowptr[m] = nnz.
  *  colind  [nnz] int32, device; 0 <= colind < n.
- *  vals    [nnz] float64, device; must stay valid and unchanged until destroy
- *          (the context keeps the pointer, and copies it for A^T).
+ *  vals    [nnz] float64, device; copied into the library's own (reordered)
+ *          copies of A and A^T during the call.
  *  D       [n] float64, device or NULL: the perturbation diagonal (entries in
  *          [0,1]); NULL -> drawn with Philox4x32-10 (Salmon et al., SC'11) from
  *          p->seed.  Copied.
@@ -226,6 +226,18 @@ nsp_status nullspace_ritz_values(nsp_ctx* ctx, double* theta, int32_t cap, int32
 nsp_status nullspace_ritz_eig(nsp_ctx* ctx, int32_t K, int32_t kk, const double* theta,
                               const double* f, const double* alpha, const double* beta,
                               double* evals, double* evecs);
+
+/* New values of A for the same sparsity pattern (optimisation loops that
+ * change A between solves).  vals [nnz] float64, device, in the caller's CSR
+ * order of nullspace_init; copied during the call.  Reuses the locality order,
+ * the stored transpose and the value permutations built at init (no host
+ * work), then redoes what init does with values: the NSP_OP_SYM value check,
+ * the FP32 copies, the norms and the Jacobi P_R.  D, Omega and the parameters
+ * stay.  The previous basis is dropped: extract_basis and backward need a new
+ * lanczos_run.  Errors: NSP_ERR_ARG (NULL, or asymmetric values with
+ * NSP_OP_SYM), NSP_ERR_NONFINITE (a NaN or Inf value); apply_op and
+ * lanczos_run then return NSP_ERR_STATE until a call with valid values. */
+nsp_status nullspace_update_values(nsp_ctx* ctx, const double* vals);
 
 /* Backward pass for a loss L(P), P = V V^T, with V from extract_basis.
  *  GsV        [n x N], ld >= n, device: G_s V where G_s is the symmetric part

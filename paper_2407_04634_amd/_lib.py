@@ -90,7 +90,8 @@ class Stats(ctypes.Structure):
 
 EXPORTS = ["nsp_default_params", "nullspace_init", "apply_op", "lanczos_run", "nullspace_nullity",
            "extract_basis", "nullspace_ritz_values", "nullspace_ritz_eig", "backward",
-           "nullspace_destroy", "nullspace_last_error", "nullspace_locality_order"]
+           "nullspace_destroy", "nullspace_last_error", "nullspace_locality_order",
+           "nullspace_update_values"]
 
 _lib = None
 
@@ -120,9 +121,10 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.nullspace_last_error.argtypes = []
     lib.nullspace_last_error.restype = ctypes.c_char_p
     lib.nullspace_locality_order.argtypes = [i64, i64, vp, vp, vp, vp]
+    lib.nullspace_update_values.argtypes = [vp, vp]
     for name in ("nullspace_init", "apply_op", "lanczos_run", "nullspace_nullity", "extract_basis",
                  "nullspace_ritz_values", "nullspace_ritz_eig", "backward",
-                 "nullspace_locality_order"):
+                 "nullspace_locality_order", "nullspace_update_values"):
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -244,6 +246,13 @@ class Context:
                                          _ptr(f) if kk else None, _ptr(alpha), _ptr(beta), _ptr(ev),
                                          _ptr(vec)))
         return ev, vec.t()
+
+    def update_values(self, vals: torch.Tensor):
+        """New values of A (same pattern, caller's CSR order); the basis is dropped."""
+        _dev(vals, torch.float64, "vals")
+        if vals.numel() != self.nnz:
+            raise ValueError("vals must hold nnz values")
+        _check(load().nullspace_update_values(self._h, _ptr(vals)))
 
     def backward(self, gsv: torch.Tensor, tol: float = 1e-12, max_iter: int = 10 ** 6):
         """grad w.r.t. A's stored values for G_s V (n x N), via the library's CG + SDDMM."""

@@ -146,6 +146,7 @@ nsp_status apply_op(nsp_ctx* ctx, const double* X, int64_t ldx, double* Y, int64
     NSP_REQUIRE(ncols >= 1, "ncols must be >= 1");
     NSP_REQUIRE(X != nullptr && Y != nullptr, "X and Y must not be NULL");
     NSP_REQUIRE(ldx >= ctx->n && ldy >= ctx->n, "leading dimensions must be >= n");
+    if (!ctx->values_ok) throw nsp::Error(NSP_ERR_STATE, "the last nullspace_update_values failed");
     enter(ctx);
     nsp::apply_b_colmajor(ctx, X, ldx, Y, ldy, ncols);
     leave(ctx);
@@ -155,6 +156,7 @@ nsp_status apply_op(nsp_ctx* ctx, const double* X, int64_t ldx, double* Y, int64
 nsp_status lanczos_run(nsp_ctx* ctx, nsp_stats* st) {
   nsp_status s = guarded([&] {
     NSP_REQUIRE(ctx != nullptr, "ctx must not be NULL");
+    if (!ctx->values_ok) throw nsp::Error(NSP_ERR_STATE, "the last nullspace_update_values failed");
     enter(ctx);
     nsp::solve(ctx);
     leave(ctx);
@@ -248,6 +250,24 @@ nsp_status nullspace_ritz_eig(nsp_ctx* ctx, int32_t K, int32_t kk, const double*
     }
     nsp::eig_work_delete(w);
     if (ctx->pin_i[0] != 0) throw nsp::Error(NSP_ERR_HIP, "tridiagonal eigensolver failed");
+    leave(ctx);
+  });
+}
+
+nsp_status nullspace_update_values(nsp_ctx* ctx, const double* vals) {
+  return guarded([&] {
+    NSP_REQUIRE(ctx != nullptr, "ctx must not be NULL");
+    NSP_REQUIRE(vals != nullptr || ctx->nnz == 0, "vals must not be NULL");
+    enter(ctx);
+    // the previous basis and deflation space belong to the old values
+    ctx->state = 0;
+    ctx->nullity = 0;
+    ctx->defl_r = 0;
+    ctx->df_r = 0;
+    ctx->ritz.clear();
+    ctx->values_ok = false;
+    nsp::refresh_values(ctx, vals);
+    ctx->values_ok = true;
     leave(ctx);
   });
 }

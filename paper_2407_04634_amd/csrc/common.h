@@ -185,6 +185,7 @@ struct nsp_ctx {
   int32_t df_r = 0;
   int32_t nullity = 0;
   int state = 0;            // 0 = initialised, 1 = basis available
+  bool values_ok = true;    // false after a rejected nullspace_update_values
   std::vector<double> ritz; // last Ritz values (host)
   nsp_stats stats{};
 };
@@ -212,6 +213,10 @@ double matrix_norms(nsp_ctx* c);
 // NSP_PRECOND_JACOBI: p from the stored matrix, stored values -> those of the
 // preconditioned matrix (FP32 copies included); call after matrix_norms
 void precondition(nsp_ctx* c);
+void check_symmetric_values(nsp_ctx* c);
+void copy_f32(nsp_ctx* c);
+// nullspace_update_values: new values, same pattern (caller's order)
+void refresh_values(nsp_ctx* c, const double* vals);
 
 // apply_op helper: Y = B X (FP64, column-major, ld)
 void apply_b_colmajor(nsp_ctx* c, const double* X, int64_t ldx, double* Y, int64_t ldy, int ncols);

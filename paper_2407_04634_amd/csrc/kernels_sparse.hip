@@ -808,18 +808,7 @@ void prepare_matrix(nsp_ctx* c, const int64_t* rowptr64, const int32_t* colind, 
     // values checked on the device below
     NSP_REQUIRE(rp32 == rpt && std::equal(ci2.begin(), ci2.begin() + nnz, cit.begin()),
                 "op = NSP_OP_SYM needs a structurally symmetric A");
-    if (nnz) {
-      DBuf flag;
-      flag.alloc(sizeof(int));
-      NSP_HIP(hipMemsetAsync(flag.p, 0, sizeof(int), c->stream));
-      k_values_differ<<<nblocks(nnz, kThreads), kThreads, 0, c->stream>>>(
-          nnz, c->valsA.as<double>(), c->valsT.as<double>(), flag.as<int>());
-      NSP_HIP(hipGetLastError());
-      int hflag = 0;
-      NSP_HIP(hipMemcpyAsync(&hflag, flag.p, sizeof(int), hipMemcpyDeviceToHost, c->stream));
-      NSP_HIP(hipStreamSynchronize(c->stream));
-      NSP_REQUIRE(hflag == 0, "op = NSP_OP_SYM needs A(i,j) == A(j,i) for every stored entry");
-    }
+    check_symmetric_values(c);
   }
   c->sym = sym;
   c->reordered = re;
@@ -836,12 +825,57 @@ void prepare_matrix(nsp_ctx* c, const int64_t* rowptr64, const int32_t* colind, 
   if (c->prm.prec == NSP_PREC_MIXED && nnz) {
     c->vals32.alloc(sizeof(float) * nnz);
     c->valsT32.alloc(sizeof(float) * nnz);
-    k_to_f32<<<nblocks(nnz, kThreads), kThreads, 0, c->stream>>>(nnz, c->A.val, c->vals32.as<float>());
-    k_to_f32<<<nblocks(nnz, kThreads), kThreads, 0, c->stream>>>(nnz, c->AT.val, c->valsT32.as<float>());
-    NSP_HIP(hipGetLastError());
     c->A.val32 = c->vals32.as<float>();
     c->AT.val32 = c->valsT32.as<float>();
+    copy_f32(c);
   }
+  NSP_HIP(hipStreamSynchronize(c->stream));
+}
+
+// Stored A and A^T must hold equal mirrored values (symmetric form); the
+// patterns were compared on the host in prepare_matrix.
+void check_symmetric_values(nsp_ctx* c) {
+  const int64_t nnz = c->nnz;
+  if (!nnz) return;
+  DBuf flag;
+  flag.alloc(sizeof(int));
+  NSP_HIP(hipMemsetAsync(flag.p, 0, sizeof(int), c->stream));
+  k_values_differ<<<nblocks(nnz, kThreads), kThreads, 0, c->stream>>>(
+      nnz, c->valsA.as<double>(), c->valsT.as<double>(), flag.as<int>());
+  NSP_HIP(hipGetLastError());
+  int hflag = 0;
+  NSP_HIP(hipMemcpyAsync(&hflag, flag.p, sizeof(int), hipMemcpyDeviceToHost, c->stream));
+  NSP_HIP(hipStreamSynchronize(c->stream));
+  NSP_REQUIRE(hflag == 0, "op = NSP_OP_SYM needs A(i,j) == A(j,i) for every stored entry");
+}
+
+// FP32 copies of the stored values (mixed precision)
+void copy_f32(nsp_ctx* c) {
+  const int64_t nnz = c->nnz;
+  if (!nnz || !c->A.val32) return;
+  k_to_f32<<<nblocks(nnz, kThreads), kThreads, 0, c->stream>>>(nnz, c->A.val, c->vals32.as<float>());
+  k_to_f32<<<nblocks(nnz, kThreads), kThreads, 0, c->stream>>>(nnz, c->AT.val, c->valsT32.as<float>());
+  NSP_HIP(hipGetLastError());
+}
+
+// New values for the same pattern (caller's CSR order): through the value
+// permutations of prepare_matrix into the stored A and A^T, then the same
+// checks, FP32 copies, norms and preconditioning as at init.
+void refresh_values(nsp_ctx* c, const double* vals) {
+  const int64_t nnz = c->nnz;
+  if (nnz) {
+    k_gather_vals<<<nblocks(nnz, kThreads), kThreads, 0, c->stream>>>(
+        nnz, c->permA.as<int32_t>(), vals, c->valsA.as<double>());
+    k_gather_vals<<<nblocks(nnz, kThreads), kThreads, 0, c->stream>>>(
+        nnz, c->permT.as<int32_t>(), c->valsA.as<double>(), c->valsT.as<double>());
+    NSP_HIP(hipGetLastError());
+  }
+  if (c->sym) check_symmetric_values(c);
+  copy_f32(c);
+  c->precond = false;
+  matrix_norms(c);
+  precondition(c);
+  if (c->precond) matrix_norms(c);
   NSP_HIP(hipStreamSynchronize(c->stream));
 }
 
@@ -1011,11 +1045,7 @@ void precondition(nsp_ctx* c) {
     k_scale_vals<<<nblocks(n, kThreads), kThreads, 0, c->stream>>>(n, c->AT.rowptr, c->AT.colind, p,
                                                                     true, c->sym, c->valsT.as<double>());
     NSP_HIP(hipGetLastError());
-    if (c->A.val32) {
-      k_to_f32<<<nblocks(nnz, kThreads), kThreads, 0, c->stream>>>(nnz, c->A.val, c->vals32.as<float>());
-      k_to_f32<<<nblocks(nnz, kThreads), kThreads, 0, c->stream>>>(nnz, c->AT.val, c->valsT32.as<float>());
-      NSP_HIP(hipGetLastError());
-    }
+    copy_f32(c);
   }
   c->precond = true;
   NSP_HIP(hipStreamSynchronize(c->stream));
