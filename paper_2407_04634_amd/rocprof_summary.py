@@ -1,6 +1,7 @@
 """Summarise rocprofv3 CSV output (kernel statistics and per-dispatch counters).
 
     python -m paper_2407_04634_amd.rocprof_summary OUTDIR [--kernel REGEX] [--top N] [--split-us T]
+                                                   [--grid-x X1,X2,...]
 
 OUTDIR is a rocprofv3 ``-d`` directory written with ``--output-format csv``.
 For ``*_kernel_stats.csv`` it prints calls, average and total duration per
@@ -62,13 +63,18 @@ def counters(path, pat, vmin=0.0):
     return "\n".join(lines)
 
 
-def trace_split(path, pat, split_us):
-    """Dispatches of the matching kernels split at ``split_us``: count and mean duration."""
+def trace_split(path, pat, split_us, grid_x=None):
+    """Dispatches of the matching kernels split at ``split_us``: count and mean duration.
+
+    ``grid_x`` (a set of work-item counts) keeps only dispatches whose grid has
+    that x extent, e.g. to separate one workload's launches from another's."""
     acc = defaultdict(lambda: [0, 0.0, 0, 0.0])
     with open(path) as f:
         for r in csv.DictReader(f):
             name = _find(r, "Kernel_Name", "KernelName", "Name")
             if pat and not re.search(pat, name):
+                continue
+            if grid_x and int(float(_find(r, "Grid_Size_X", "Grid_Size", "Grid_X"))) not in grid_x:
                 continue
             us = (float(_find(r, "End_Timestamp")) - float(_find(r, "Start_Timestamp"))) / 1e3
             a = acc[name]
@@ -78,7 +84,8 @@ def trace_split(path, pat, split_us):
             else:
                 a[2] += 1
                 a[3] += us
-    lines = [f"{'long':>9} {'avg_us':>9} {'short':>9} {'avg_us':>9}  kernel (split at {split_us} us)"]
+    lines = [f"{'long':>9} {'avg_us':>9} {'short':>9} {'avg_us':>9}  kernel (split at {split_us} us"
+             + (f", grid x in {sorted(grid_x)})" if grid_x else ")")]
     for name, (nl, tl, ns, ts) in sorted(acc.items()):
         lines.append(f"{nl:>9d} {tl / max(nl, 1):>9.2f} {ns:>9d} {ts / max(ns, 1):>9.2f}  {name[:150]}")
     return "\n".join(lines)
@@ -93,14 +100,17 @@ def main():
                     help="average counters only over dispatches whose value is at least this")
     ap.add_argument("--split-us", type=float, default=0.0,
                     help="also split the matching kernels' dispatches in *_kernel_trace.csv at this duration")
+    ap.add_argument("--grid-x", default="",
+                    help="comma-separated grid x extents (work-items) the split keeps")
     a = ap.parse_args()
+    gx = {int(v) for v in a.grid_x.split(",") if v} or None
     for p in sorted(glob.glob(os.path.join(a.outdir, "**", "*kernel_stats.csv"), recursive=True)):
         print(f"== {os.path.basename(p)}")
         print(kernel_stats(p, a.kernel, a.top))
     if a.split_us > 0:
         for p in sorted(glob.glob(os.path.join(a.outdir, "**", "*kernel_trace.csv"), recursive=True)):
             print(f"== {os.path.basename(p)}")
-            print(trace_split(p, a.kernel, a.split_us))
+            print(trace_split(p, a.kernel, a.split_us, gx))
     for p in sorted(glob.glob(os.path.join(a.outdir, "**", "*counter_collection.csv"), recursive=True)):
         print(f"== {os.path.basename(p)}")
         print(counters(p, a.kernel))
