@@ -18,3 +18,4 @@ from ._lib import (  # noqa: F401
     PRECOND_NONE,
     PRECOND_JACOBI,
 )
+from .autograd import NullSpaceFunction, null_space  # noqa: F401
