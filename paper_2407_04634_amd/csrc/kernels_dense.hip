@@ -410,7 +410,7 @@ struct CPair {
 // FP32 rows come four per 16-byte load, so half as many columns keep the
 // register footprint (and the occupancy) of the FP64 kernel.
 template <int NC, int ESIZE = 8> struct TsShape {
-  static constexpr int JW8 = NC >= 16 ? 1 : (NC >= 8 ? 2 : (NC >= 4 ? 4 : 8));
+  static constexpr int JW8 = NC >= 16 ? 1 : (NC >= 4 ? 4 : 8);
   static constexpr int JW = ESIZE == 4 && JW8 > 1 ? JW8 / 2 : JW8;
   static constexpr int JB = 4 * JW;
 };
@@ -419,6 +419,32 @@ template <int NC, int ESIZE = 8> struct TsShape {
 template <typename VT> struct RowVec;
 template <> struct RowVec<double> { static constexpr int R = 2; using T = double2; };
 template <> struct RowVec<float> { static constexpr int R = 4; using T = float4; };
+
+// The DA values of one row of a row-interleaved block (16-byte loads where the
+// row is a whole number of them; rows are 16-byte aligned then).
+template <typename VT, int DA>
+__device__ __forceinline__ void load_crow(const VT* __restrict__ p, double (&o)[DA]) {
+  if constexpr (sizeof(VT) == 8 && DA % 2 == 0) {
+#pragma unroll
+    for (int q = 0; q < DA / 2; ++q) {
+      const double2 t = reinterpret_cast<const double2*>(p)[q];
+      o[2 * q] = t.x;
+      o[2 * q + 1] = t.y;
+    }
+  } else if constexpr (sizeof(VT) == 4 && DA % 4 == 0) {
+#pragma unroll
+    for (int q = 0; q < DA / 4; ++q) {
+      const float4 t = reinterpret_cast<const float4*>(p)[q];
+      o[4 * q] = t.x;
+      o[4 * q + 1] = t.y;
+      o[4 * q + 2] = t.z;
+      o[4 * q + 3] = t.w;
+    }
+  } else {
+#pragma unroll
+    for (int c = 0; c < DA; ++c) o[c] = (double)p[c];
+  }
+}
 
 template <typename VT>
 __device__ __forceinline__ void load_rows(const VT* __restrict__ p, int64_t r, int64_t n,
@@ -472,9 +498,21 @@ __global__ __launch_bounds__(kThreads) void k_ts_tn(const int* cond, int64_t n, 
         }
       } else {
 #pragma unroll
-        for (int i = 0; i < RV; ++i)
+        for (int i = 0; i < RV; ++i) {
+          double t0[DA], t1[DA];
+          if (r + i < r1) {
+            load_crow<VT, DA>(cc.a0 + (r + i) * DA, t0);
+            if constexpr (NA == 2) load_crow<VT, DA>(cc.a1 + (r + i) * DA, t1);
+          } else {
 #pragma unroll
-          for (int c = 0; c < NC; ++c) cv[i][c] = r + i < r1 ? (double)cc.get(r + i, c) : 0.0;
+            for (int c = 0; c < DA; ++c) { t0[c] = 0.0; t1[c] = 0.0; }
+          }
+#pragma unroll
+          for (int c = 0; c < DA; ++c) {
+            cv[i][c] = t0[c];
+            if constexpr (NA == 2) cv[i][DA + c] = t1[c];
+          }
+        }
       }
       double zv[JW][RV];
 #pragma unroll
@@ -581,8 +619,14 @@ __global__ __launch_bounds__(kThreads) void k_ts_nn(const int* cond, int64_t n,
   }
 }
 
-// C -= Z H for NC <= 4.  A block owns 64 * RV consecutive rows (RV rows per
-// lane, one 16-byte load per basis column); its 8 waves split the k columns,
+// Waves per block of the update kernel: 8, or 4 where the per-wave partial
+// sums (NC x rows doubles each) would exceed 64 KB of LDS.
+template <typename VT, int NC> constexpr int ts_nn_waves() {
+  return 8 * NC * kWave * RowVec<VT>::R * 8 > 65536 ? 4 : 8;
+}
+
+// C -= Z H for NC <= 8.  A block owns 64 * RV consecutive rows (RV rows per
+// lane, one 16-byte load per basis column); its waves split the k columns,
 // unrolled by 4 so every wave keeps several loads in flight, and combine the
 // partial sums in LDS.  With GRAM it also writes the block's partial Gram
 // matrix of the updated rows.
@@ -594,12 +638,15 @@ __global__ __launch_bounds__(512) void k_ts_nn_v(const int* cond, int64_t n,
                                                  double* __restrict__ part_c) {
   constexpr int NC = DA * NA;
   constexpr int RV = RowVec<VT>::R;
-  constexpr int NW = 8;
+  constexpr int NW = ts_nn_waves<VT, NC>();
   constexpr int TR = kWave * RV;  // rows per block
-  static_assert(NC <= 4, "wide C uses k_ts_nn");
+  static_assert(NC <= 8, "wider C uses k_ts_nn");
   if (cond && *cond == 0) return;
   __shared__ double red[NW][NC][TR];
-  const int lane = threadIdx.x % kWave, wid = threadIdx.x / kWave;
+  // the wave index is uniform: said explicitly, the column indices and the
+  // H coefficients of a wave live in scalar registers (scalar loads)
+  const int lane = threadIdx.x % kWave;
+  const int wid = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
   const int64_t rb = (int64_t)blockIdx.x * TR;
   const int64_t r = rb + (int64_t)lane * RV;
   double acc[RV][NC];
@@ -649,14 +696,17 @@ __global__ __launch_bounds__(512) void k_ts_nn_v(const int* cond, int64_t n,
     for (int c = 0; c < NC; ++c) red[wid][c][lane * RV + i] = acc[i][c];
   __syncthreads();
   // thread t < TR finishes row rb + t
-  constexpr int NG = GRAM ? NC * NC : 1;
+  constexpr bool GSMALL = GRAM && NC <= 4;  // Gram in registers; wider C goes through LDS
+  constexpr int NG = GSMALL ? NC * NC : 1;
   double g[NG];
 #pragma unroll
   for (int i = 0; i < NG; ++i) g[i] = 0.0;
   const int t = threadIdx.x;
+  double o[NC];
+#pragma unroll
+  for (int c = 0; c < NC; ++c) o[c] = 0.0;
   if (t < TR && rb + t < n) {
     const int64_t row = rb + t;
-    double o[NC];
 #pragma unroll
     for (int c = 0; c < NC; ++c) {
       double sum = 0.0;
@@ -665,24 +715,39 @@ __global__ __launch_bounds__(512) void k_ts_nn_v(const int* cond, int64_t n,
       o[c] = (double)VT((double)cc.get(row, c) - sum);
       cc.set(row, c, VT(o[c]));
     }
-    if constexpr (GRAM) {
+    if constexpr (GSMALL) {
 #pragma unroll
       for (int a = 0; a < NC; ++a)
 #pragma unroll
         for (int b = 0; b < NC; ++b) g[a + b * NC] += o[a] * o[b];
     }
   }
-  if constexpr (GRAM) {
+  if constexpr (GSMALL) {
     __syncthreads();
     block_sum<NG>(g, &red[0][0][0]);  // reuses the LDS: needs NW * NG doubles
     if (threadIdx.x == 0)
 #pragma unroll
       for (int i = 0; i < NG; ++i) part_c[(size_t)blockIdx.x * NG + i] = g[i];
+  } else if constexpr (GRAM) {
+    // the block's updated rows go to LDS (NC x TR), then thread (a, b) sums
+    // entry (a, b) of their Gram matrix over the rows in order
+    __syncthreads();
+    double* ob = &red[0][0][0];
+    if (t < TR)
+#pragma unroll
+      for (int c = 0; c < NC; ++c) ob[c * TR + t] = o[c];
+    __syncthreads();
+    if (t < NC * NC) {
+      const int a = t % NC, b = t / NC;
+      double sg = 0.0;
+      for (int q = 0; q < TR; ++q) sg = fma(ob[a * TR + q], ob[b * TR + q], sg);
+      part_c[(size_t)blockIdx.x * NC * NC + t] = sg;
+    }
   }
 }
 
 // Rows per block of the C -= Z H kernel (and so the number of Gram partials).
-template <typename VT, int NC> constexpr int ts_nn_rows() { return NC <= 4 ? kWave * RowVec<VT>::R : kWave; }
+template <typename VT, int NC> constexpr int ts_nn_rows() { return NC <= 8 ? kWave * RowVec<VT>::R : kWave; }
 
 // One block: Gram of C from the partials, Cholesky; writes R^{-1} then R (NC x NC each).
 template <int NC>
@@ -703,7 +768,7 @@ __global__ __launch_bounds__(256) void k_ts_gramfin(const int* cond, int nparts,
 
 // C = C R^{-1} (NC columns), written back to the arrays and, if z0 is given,
 // to NC consecutive basis columns starting at z0.  With FUSED the block first
-// reduces the Gram partials of k_ts_nn itself and factors them (NC <= 4);
+// reduces the Gram partials of k_ts_nn_v itself and factors them (NC <= 8);
 // block 0 then stores R^{-1} and R in rinv.  Otherwise rinv comes from
 // k_ts_gramfin.
 template <typename VT, int DA, int NA, bool FUSED>
@@ -1029,7 +1094,7 @@ void w_reset(nsp_ctx* c, int col0, int ncols, double u_d, double* w, int ldw) {
 // Row chunk of the H = Z^T C kernel: about 2048 blocks over (chunks x column
 // groups), at least 1024 rows, a multiple of 256 rows (aligned vector loads).
 int64_t ts_chunk_rows(int64_t n, int k, int nc, int esize) {
-  int jb = nc >= 16 ? 4 : (nc >= 8 ? 8 : (nc >= 4 ? 16 : 32));
+  int jb = nc >= 16 ? 4 : (nc >= 4 ? 16 : 32);
   if (esize == 4 && jb > 4) jb /= 2;  // TsShape<NC, 4>::JB
   const int64_t col_groups = std::max<int64_t>(1, (k + jb - 1) / jb);
   const int64_t chunks = std::max<int64_t>(1, 2048 / col_groups);
@@ -1059,12 +1124,13 @@ static void ts_proj_t(nsp_ctx* c, const int* cond, int64_t n, const VT* z, int64
     NSP_HIP(hipEventRecord(ev_tn, c->stream));
   }
   if (ev_red) NSP_HIP(hipEventRecord(ev_red, c->stream));
-  if constexpr (NC <= 4) {
+  if constexpr (NC <= 8) {
+    constexpr int nt = ts_nn_waves<VT, NC>() * kWave;
     if (gram)
-      k_ts_nn_v<VT, DA, NA, true><<<nnblocks, 512, 0, c->stream>>>(cond, n, z, ldz, k, h, cc, part_c);
+      k_ts_nn_v<VT, DA, NA, true><<<nnblocks, nt, 0, c->stream>>>(cond, n, z, ldz, k, h, cc, part_c);
     else if (k > 0)
-      k_ts_nn_v<VT, DA, NA, false><<<nnblocks, 512, 0, c->stream>>>(cond, n, z, ldz, k, h, cc,
-                                                                    nullptr);
+      k_ts_nn_v<VT, DA, NA, false><<<nnblocks, nt, 0, c->stream>>>(cond, n, z, ldz, k, h, cc,
+                                                                   nullptr);
   } else {
     if (gram) {
       k_ts_nn<VT, DA, NA, true><<<nnblocks, kThreads, 0, c->stream>>>(cond, n, z, ldz, k, h, cc, part_c);
@@ -1087,7 +1153,7 @@ static void ts_scale_t(nsp_ctx* c, const int* cond, int64_t n, VT* a0, VT* a1, c
   constexpr int TR = ts_nn_rows<VT, NC>();
   const int nparts = (int)((n + TR - 1) / TR);
   const unsigned grid = cap_grid(n, kThreads, 2048);
-  if constexpr (NC <= 4)
+  if constexpr (NC <= 8)
     k_ts_scale<VT, DA, NA, true><<<grid, kThreads, 0, c->stream>>>(cond, n, cc, part_c, nparts, rinv,
                                                                    z0, ldz, c->flags.as<int>());
   else
