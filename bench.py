@@ -34,10 +34,10 @@ HBM_PEAK_GBS = 8000.0
 # commands is profiles/k_ts_nn_v_planted50k_traffic.md.  Keyed by (workload, d,
 # precision, kernel); an entry is dropped whenever that kernel changes.
 TRAFFIC = {
-    # FETCH_SIZE 152725 KiB x 2.0 + WRITE_SIZE 794 KiB x 1.0 per launch that
+    # FETCH_SIZE 152826 KiB x 2.0 + WRITE_SIZE 794 KiB x 1.0 per launch that
     # reorthogonalised, against 306.9 MB algorithmic in the same 40-cycle run
     ("planted50k", 1, "fp64", "k_ts_nn_v"): {"ratio": 1.022},
-    # FETCH_SIZE 160715 KiB x 2.0 + WRITE_SIZE (partials) 612 KiB, against 306.1 MB
+    # FETCH_SIZE 160701 KiB x 2.0 + WRITE_SIZE (partials) 612 KiB, against 306.1 MB
     ("planted50k", 1, "fp64", "k_ts_tn"): {"ratio": 1.077},
 }
 
