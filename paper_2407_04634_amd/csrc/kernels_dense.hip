@@ -412,7 +412,8 @@ struct CPair {
 template <int NC, int ESIZE = 8> struct TsShape {
   static constexpr int JW8 = NC >= 16 ? 1 : (NC >= 4 ? 4 : 8);
   static constexpr int JW = ESIZE == 4 && JW8 > 1 ? JW8 / 2 : JW8;
-  static constexpr int JB = 4 * JW;
+  static constexpr int NWT = 4;  // waves per block (8 measured slower: fewer, heavier blocks)
+  static constexpr int JB = NWT * JW;
 };
 
 // Rows one lane loads at once from a basis column: 16 bytes per load.
@@ -1095,7 +1096,7 @@ void w_reset(nsp_ctx* c, int col0, int ncols, double u_d, double* w, int ldw) {
 // groups), at least 1024 rows, a multiple of 256 rows (aligned vector loads).
 int64_t ts_chunk_rows(int64_t n, int k, int nc, int esize) {
   int jb = nc >= 16 ? 4 : (nc >= 4 ? 16 : 32);
-  if (esize == 4 && jb > 4) jb /= 2;  // TsShape<NC, 4>::JB
+  if (esize == 4 && nc < 16) jb /= 2;  // TsShape<NC, 4>::JB
   const int64_t col_groups = std::max<int64_t>(1, (k + jb - 1) / jb);
   const int64_t chunks = std::max<int64_t>(1, 2048 / col_groups);
   int64_t rows = (n + chunks - 1) / chunks;
@@ -1115,8 +1116,8 @@ static void ts_proj_t(nsp_ctx* c, const int* cond, int64_t n, const VT* z, int64
     const int64_t chunk = ts_chunk_rows(n, k, NC, (int)sizeof(VT));
     const unsigned nchunks = (unsigned)((n + chunk - 1) / chunk);
     const unsigned gy = (unsigned)((k + TsShape<NC, sizeof(VT)>::JB - 1) / TsShape<NC, sizeof(VT)>::JB);
-    k_ts_tn<VT, DA, NA><<<dim3(nchunks, gy), kThreads, 0, c->stream>>>(cond, n, chunk, z, ldz, k, cc,
-                                                                        hpart);
+    k_ts_tn<VT, DA, NA><<<dim3(nchunks, gy), TsShape<NC, sizeof(VT)>::NWT * kWave, 0, c->stream>>>(
+        cond, n, chunk, z, ldz, k, cc, hpart);
     if (ev_tn) NSP_HIP(hipEventRecord(ev_tn, c->stream));
     k_reduce_cols<<<nblk((int64_t)k * NC, 32), 256, 0, c->stream>>>(cond, (int)nchunks, k * NC,
                                                                     hpart, h);
