@@ -565,7 +565,9 @@ static int spmmT_step_d(nsp_ctx* c, const VT* y, const VT* x, const VT* xp, cons
   if constexpr (sizeof(VT) == 8) av = a.val; else av = a.val32;
   const int64_t groups = (a.rows + 0);
   unsigned grid = nblocks(groups * a.lpr, kThreads);
-  if (XI) grid = std::min<unsigned>(grid, (unsigned)kRedBlocks);
+  // d = 1: one pass over the rows (the next kernel sums up to kStreamBlocks
+  // scalar partials); wider blocks keep the grid (and their d x d partials) small
+  if (XI) grid = std::min<unsigned>(grid, (unsigned)(D == 1 ? kStreamBlocks : kRedBlocks));
 #define NSP_T_CASE(L)                                                                          \
   case L:                                                                                      \
     k_spmmT_step<VT, D, L, PREV, XI><<<grid, kThreads, 0, c->stream>>>(                        \
