@@ -171,10 +171,15 @@ void nsp_default_params(nsp_params* p);
  *  vals    [nnz] float64, device; copied into the library's own (reordered)
  *          copies of A and A^T during the call.
  *  D       [n] float64, device or NULL: the perturbation diagonal (entries in
- *          [0,1]); NULL -> drawn with Philox4x32-10 (Salmon et al., SC'11) from
- *          p->seed.  Copied.
+ *          [0,1]); NULL -> drawn with Philox4x32-10 (Salmon et al., SC'11):
+ *          (x0, x1, x2, x3) = Philox4x32-10(counter (i, 0, 0, 0), key
+ *          (seed mod 2^32, seed >> 32)), D_i = u53(x0, x1) with
+ *          u53(a, b) = ((a >> 5) 2^26 + (b >> 6)) 2^-53 in [0, 1).  Copied.
  *  Omega   [n x d] float64 column-major (ld = n), device or NULL: the Gaussian
- *          start block; NULL -> drawn with Philox + Box-Muller.  Copied.
+ *          start block; NULL -> Box-Muller on the same generator with counter
+ *          (i, j + 1, 0, 0) for column j: Omega(i, j) =
+ *          sqrt(-2 ln(1 - u53(x0, x1))) cos(2 pi u53(x2, x3)).  Copied.
+ *          Both are drawn in the caller's order of the unknowns.
  *  p       host parameters (copied).
  *  stream  hipStream_t to order all work on (NULL = default stream).
  * Builds the transposed CSR (A^T) once.  nnz must be < 2^31.
