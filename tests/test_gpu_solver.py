@@ -54,6 +54,22 @@ def test_er20_nullity_and_subspace(prec):
     assert exact.max_angle_sine(v, vr) <= 1e-8
 
 
+@pytest.mark.parametrize("d", [2, 4, 8])
+def test_er20_mixed_precision_block_sizes(d):
+    """FP32 storage with block sizes > 1 (the reorthogonalisation pair then has
+    2d = 4, 8, 16 columns: FP32 variants of both update kernels)."""
+    from tests.gpu_util import context
+
+    c = G.config("er20")
+    print(f"[solver] er20 mixed d={d}", flush=True)
+    ctx, dv, om = context(c, EPS_ER20, d=d, max_dim=128, prec=1)
+    st = ctx.lanczos_run()
+    assert st["nullity"] == 20
+    v = _basis(ctx)
+    assert exact.max_angle_sine(v, exact.indicator_basis(c.meta["labels"])) <= 1e-8
+    assert st["rel_resid_fro"] <= 1e-8
+
+
 @pytest.mark.parametrize("d", [1, 2, 4, 8])
 def test_planted_small_block_sizes(d):
     from tests.gpu_util import context
