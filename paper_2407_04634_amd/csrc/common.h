@@ -72,7 +72,7 @@ struct DBuf {
 constexpr int kMaxD = 8;            // largest supported block size
 constexpr int kRedBlocks = 512;     // grid cap of kernels that write per-block partials
 constexpr int kWideBlocks = 1024;   // grid cap of the many-column SpMM (its partials: x k)
-constexpr int kDeflMax = 256;       // deflation vectors of the refinement (at most)
+constexpr int kDeflMax = 384;       // deflation vectors of the refinement (at most)
 constexpr int kXcds = 8;            // accelerator complex dies; workgroups go round-robin over them
 constexpr int kStreamBlocks = 2048; // grid cap of the streaming SpMV
 constexpr int64_t kStreamMinNnz = 1 << 21;  // smaller matrices use the lanes-per-row kernels
