@@ -389,7 +389,7 @@ __global__ void k_w_reset(int col0, int ncols, double u_d, double* w, int ldw) {
 // Tall-skinny pair of the (partial) reorthogonalisation, classical
 // Gram-Schmidt (Sec. 4.2):
 //   H = Z^T C   (k x NC)  k_ts_tn writes per-row-chunk partials, k_reduce_cols sums them
-//   C = C - Z H           k_ts_nn
+//   C = C - Z H           k_ts_nn_v (NC <= 8), k_ts_nn (wider)
 // C is NC columns held as NA row-interleaved arrays of DA columns each
 // (NC = NA * DA): for the reorthogonalisation of [Q_ell, Q_ell+1] NA = 2.
 // When ``cond`` is non-null the kernels do nothing unless *cond != 0.
@@ -560,7 +560,8 @@ __global__ __launch_bounds__(256) void k_reduce_cols(const int* cond, int nparts
   }
 }
 
-// C -= Z H.  A block handles 64 rows; its 4 waves split the k columns and the
+// C -= Z H for C wider than 8 columns (d = 8 pair).  A block handles 64 rows;
+// its 4 waves split the k columns and the
 // partial sums are combined in LDS.  With GRAM the block also writes the
 // partial Gram matrix of the updated rows (for the final Cholesky QR).
 template <typename VT, int DA, int NA, bool GRAM>
