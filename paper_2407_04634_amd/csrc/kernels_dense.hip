@@ -561,9 +561,9 @@ __global__ __launch_bounds__(256) void k_reduce_cols(const int* cond, int nparts
 }
 
 // C -= Z H for C wider than 8 columns (d = 8 pair).  A block handles 64 rows;
-// its 4 waves split the k columns and the
-// partial sums are combined in LDS.  With GRAM the block also writes the
-// partial Gram matrix of the updated rows (for the final Cholesky QR).
+// its 4 waves split the k columns and the partial sums are combined in LDS.
+// With GRAM the block also writes the partial Gram matrix of the updated rows
+// (for the final Cholesky QR).
 template <typename VT, int DA, int NA, bool GRAM>
 __global__ __launch_bounds__(kThreads) void k_ts_nn(const int* cond, int64_t n,
                                                     const VT* __restrict__ z, int64_t ldz, int k,
