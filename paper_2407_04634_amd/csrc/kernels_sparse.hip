@@ -385,9 +385,35 @@ __global__ __launch_bounds__(kThreads) void k_csr_stream(
     const int e0 = rp[r0];
     const int cnt = rp[r1] - e0;
     const bool tiled = cnt <= TILE;  // uniform over the workgroup
-    if (tiled) {
+    if (tiled && !STEP) {
       // the matrix is read once per product: non-temporal loads keep it from
-      // evicting the gathered operand rows out of L2
+      // evicting the gathered operand rows out of L2.  A thread owns at most
+      // IPT entries of the tile: all their index and value loads are issued
+      // before the first gather, then all gathers, so each thread keeps IPT
+      // independent index-then-gather chains in flight instead of one.  (The
+      // fused second product keeps the plain loop: with its epilogue the
+      // extra registers cost more than the loads in flight gain.)
+      constexpr int IPT = (TILE + kThreads - 1) / kThreads;
+      int32_t cidx[IPT];
+      double aval[IPT];
+#pragma unroll
+      for (int u = 0; u < IPT; ++u) {
+        const int i = t + u * kThreads;
+        if (i < cnt) {
+          aval[u] = (double)__builtin_nontemporal_load(av + e0 + i);
+          cidx[u] = __builtin_nontemporal_load(ci + e0 + i);
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < IPT; ++u) {
+        const int i = t + u * kThreads;
+        if (i < cnt) {
+          const VT* xr = xin + (int64_t)cidx[u] * D;
+#pragma unroll
+          for (int j = 0; j < D; ++j) prod[i * D + j] = aval[u] * (double)xr[j];
+        }
+      }
+    } else if (tiled) {
       for (int i = t; i < cnt; i += kThreads) {
         const double a = __builtin_nontemporal_load(av + e0 + i);
         const VT* xr = xin + (int64_t)__builtin_nontemporal_load(ci + e0 + i) * D;
