@@ -28,11 +28,18 @@ listed with its justification in the design notes):
       w_{k+1,l}|G_k| + w_{k,l-1}|G_{l-1}| cancels exactly in the derivation
       (the Q_{l-1} coupling is subtracted explicitly) and is dropped.
   R5  "reorthogonalize" in the partial reorthogonalisation events = one
-      pass of classical Gram-Schmidt: the vectors are semi-orthogonal there
-      (bounds just above u_RO = sqrt(u)), so one projection leaves a component
-      of order u and a second pass would only matter under cancellation.  The
-      first step of a cycle and the restart (components of order ||B|| or 1)
-      use classical Gram-Schmidt twice (CGS2).
+      pass of classical Gram-Schmidt against Z_{ell-1}, accepted by the
+      Kahan-Parlett criterion ("twice is enough", Parlett, The Symmetric
+      Eigenvalue Problem, Sec. 6.9; the paper cites Parlett for the
+      round-off model of Sec. 4.2): a projected vector that keeps at least
+      1/sqrt(2) of its norm is orthogonal to the basis to working accuracy
+      after one pass, and a second pass is needed only when the projection
+      cancelled more.  At a flagged step the W bound sits just above
+      u_RO = sqrt(u), so a unit Lanczos vector loses a fraction of order
+      k u_RO^2 of its squared norm and the criterion holds with a wide
+      margin; it is checked anyway, and a violation (the W bound failed)
+      stops the run.  The first step of a cycle and the restart (components
+      of order ||B|| or 1) use classical Gram-Schmidt twice (CGS2).
   R6  QR = orthonormal factor with positive-diagonal triangular factor (the
       unique thin QR of a full-rank block); d = 1 is normalisation.
   R7  ||B|| in u_d: ||A||_1 ||A||_inf + eps in the first cycle, then the
@@ -80,6 +87,21 @@ def cgs1(z: np.ndarray, p: np.ndarray) -> np.ndarray:
     if z.shape[1] == 0:
         return p
     return p - z @ (z.T @ p)
+
+
+KAHAN_PARLETT = 1.0 / math.sqrt(2.0)
+
+
+def cgs1_accepted(z: np.ndarray, p: np.ndarray) -> np.ndarray:
+    """One classical Gram-Schmidt pass of the unit columns of P, checked by the
+    Kahan-Parlett criterion (reading R5): every projected column must keep at
+    least 1/sqrt(2) of its norm, else one pass is not enough."""
+    out = cgs1(z, p)
+    kept = np.linalg.norm(out, axis=0) / np.linalg.norm(p, axis=0)
+    if np.any(kept < KAHAN_PARLETT):
+        raise RuntimeError("partial reorthogonalisation: one Gram-Schmidt pass removed more than "
+                           "1 - 1/sqrt(2) of a vector's norm (the W bound failed)")
+    return out
 
 
 def cgs2(z: np.ndarray, p: np.ndarray) -> np.ndarray:
@@ -193,6 +215,18 @@ def _assemble_t(theta_kept, f, xis, gams, l0, nblocks, d):
     return t
 
 
+def coupling_block(r: np.ndarray, gamma_last: np.ndarray, vz: np.ndarray, dim_k: int, d: int,
+                   k_keep: int) -> np.ndarray:
+    """F = R Gamma_ell V_Z(last d rows, 1:k_keep) (Sec. 4.1, reading R11).
+
+    Multiplying B Z_ell = Z_ell T_ell + Q_{ell+1} [0, Gamma_ell] by the kept Ritz
+    vectors V_Z(:, 1:k_keep) leaves Q_{ell+1} Gamma_ell V_Z(last d rows, :) as
+    the residual; Q_{ell+1} = Q_{ell_0+1} R + Z_{ell_0} (...) turns it into
+    Q_{ell_0+1} F.
+    """
+    return r @ gamma_last @ vz[dim_k - d:dim_k, :k_keep]
+
+
 def restart_size(n_ell: int, dim_k: int, d: int) -> int:
     """Reading R1."""
     k_keep = d * ((n_ell + dim_k) // (2 * d))
@@ -293,7 +327,7 @@ def algorithm2(a, eps: float, dvec: np.ndarray, omega: np.ndarray, dim_k: int,
                 orth_trace.append((ell, wmax, true))
             if not full_reorth and wmax > u_ro:
                 # reorthogonalise Q_ell and Q_{ell+1} against Z_{ell-1} (Sec. 4.2)
-                blk = cgs1(zb[:, :c], zb[:, c:c + 2 * d])
+                blk = cgs1_accepted(zb[:, :c], zb[:, c:c + 2 * d])
                 qlr, _ = block_qr(blk[:, :d])
                 qnr, _ = block_qr(cgs1(qlr, blk[:, d:]))
                 zb[:, c:c + d] = qlr
@@ -310,9 +344,12 @@ def algorithm2(a, eps: float, dvec: np.ndarray, omega: np.ndarray, dim_k: int,
         out_of_budget = matvecs >= max_matvec or (max_cycles is not None and restarts + 1 >= max_cycles)
         if stop or out_of_budget:
             v = zb[:, :dim_k] @ vz[:, :n_ell]
+            # the last cycle's Lanczos decomposition B Z = Z T + Q_next [0, Gamma_last]
+            # (Eq. "laniter"), returned for the invariant checks of the tests
             return dict(V=v, N=n_ell, theta=theta, matvecs=matvecs, restarts=restarts,
                         reorths=reorths, history=history, converged=bool(stop),
-                        orth_trace=orth_trace, u_d=u_d)
+                        orth_trace=orth_trace, u_d=u_d, Z=zb[:, :dim_k].copy(), T=t,
+                        Q_next=zb[:, dim_k:dim_k + d].copy(), Gamma_last=gams[nb], l0=l0)
         # ---- thick restart (Sec. 4.1)
         k_keep = restart_size(n_ell, dim_k, d)
         if n_ell > k_keep:
@@ -320,7 +357,7 @@ def algorithm2(a, eps: float, dvec: np.ndarray, omega: np.ndarray, dim_k: int,
         z_new = zb[:, :dim_k] @ vz[:, :k_keep]
         q_last = zb[:, dim_k:dim_k + d]
         qn, r = block_qr(cgs2(z_new, q_last))
-        f = r @ gams[nb] @ vz[dim_k - d:dim_k, :k_keep]
+        f = coupling_block(r, gams[nb], vz, dim_k, d, k_keep)
         theta_kept = theta[:k_keep].copy()
         zb[:, :k_keep] = z_new
         zb[:, k_keep:k_keep + d] = qn
