@@ -209,7 +209,11 @@ nsp_status lanczos_run(nsp_ctx* ctx, nsp_stats* st);
 /* Nullity N found by the last lanczos_run (host out). */
 nsp_status nullspace_nullity(nsp_ctx* ctx, int32_t* nullity);
 
-/* Copy V (n x N, FP64, orthonormal columns) into V [ldv >= n], device.
+/* Copy V (n x N, FP64, orthonormal columns) into V [ldv >= n], device: the
+ * output of Alg. 2 ("Return V = Z_ell V_Z(:, 1:N_ell)", an orthonormal basis
+ * approximating null(A)), after the FP64 refinement when params.refine is set
+ * and mapped back by P_R^{-T} with outer preconditioning (Sec. 4.4), in the
+ * caller's order of the unknowns.
  * Errors: NSP_ERR_STATE before a successful (or NOCONV) lanczos_run. */
 nsp_status extract_basis(nsp_ctx* ctx, double* V, int64_t ldv);
 
@@ -217,6 +221,16 @@ nsp_status extract_basis(nsp_ctx* ctx, double* V, int64_t ldv);
  *  theta  host buffer of capacity cap; *count receives the number written
  *  (min(cap, dim K)).  Before refinement, i.e. eigenvalues of T_ell. */
 nsp_status nullspace_ritz_values(nsp_ctx* ctx, double* theta, int32_t cap, int32_t* count);
+
+/* Wall time of each restart cycle of the last lanczos_run, in order (host
+ * out): one cycle of Alg. 2's outer loop = the block Lanczos steps from
+ * ell_0 + 1 to dim K / d with their partial reorthogonalisation, the
+ * Rayleigh-Ritz step on T (Eq. "defT") and the thick restart (Sec. 4.1), or
+ * the extraction of V after the last one.  Each interval runs from one
+ * synchronisation of the library's stream to the next (host clock).
+ *  seconds  host buffer of capacity cap; *count receives min(cap, cycles).
+ * Errors: NSP_ERR_ARG for NULL pointers. */
+nsp_status nullspace_cycle_times(nsp_ctx* ctx, double* seconds, int32_t cap, int32_t* count);
 
 /* Eigen-decomposition of the restart matrix of Alg. 2 for block size 1
  * (Eq. "defT"), the Rayleigh-Ritz step the solver runs once per restart:
@@ -244,10 +258,15 @@ nsp_status nullspace_ritz_eig(nsp_ctx* ctx, int32_t K, int32_t kk, const double*
  * lanczos_run then return NSP_ERR_STATE until a call with valid values. */
 nsp_status nullspace_update_values(nsp_ctx* ctx, const double* vals);
 
-/* Backward pass for a loss L(P), P = V V^T, with V from extract_basis.
- *  GsV        [n x N], ld >= n, device: G_s V where G_s is the symmetric part
- *             of dL/dP.  (For dL/dV of a loss that depends on V only through P,
- *             G_s V = (dL/dV) / 2.)
+/* Backward pass for a loss L(P) of the null projector P = V V^T (the
+ * problem statement's null space, Sec. 1), with V from extract_basis.  The
+ * loss must depend on V only through P (V is unique up to a rotation of its
+ * columns); N is held fixed, so the derivative is that of the projector onto
+ * the N smallest right singular vectors of A.
+ *  dLdV       [n x N], ld >= n, device: dL/dV, the gradient of the loss with
+ *             respect to the returned basis.  For such a loss dL/dV = 2 G_s V
+ *             with G_s the symmetric part of dL/dP; the library uses
+ *             G_s V = dL/dV / 2.
  *  grad_vals  [nnz], device, out: dL/d vals in A's CSR order,
  *             grad_p = -2 <(A W)_i, V_j> for the stored entry p = (i, j), where
  *             W = (A^T A)^+ (I - V V^T) G_s V is computed by CG on A^T A
@@ -263,7 +282,7 @@ nsp_status nullspace_update_values(nsp_ctx* ctx, const double* vals);
  * normal equations: A W = (A P_R^{-T}) X with (A P_R^{-T})^T (A P_R^{-T}) X =
  * P_R^{-1} (I - V V^T) G_s V, which gives the same A W.  NSP_ERR_ARG for the
  * preconditioned symmetric form. */
-nsp_status backward(nsp_ctx* ctx, const double* GsV, int64_t ld, double* grad_vals, double tol,
+nsp_status backward(nsp_ctx* ctx, const double* dLdV, int64_t ld, double* grad_vals, double tol,
                     int64_t max_iter, int64_t* iters);
 
 /* Release everything the context owns.  NULL is accepted. */

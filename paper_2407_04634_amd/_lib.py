@@ -91,7 +91,7 @@ class Stats(ctypes.Structure):
 EXPORTS = ["nsp_default_params", "nullspace_init", "apply_op", "lanczos_run", "nullspace_nullity",
            "extract_basis", "nullspace_ritz_values", "nullspace_ritz_eig", "backward",
            "nullspace_destroy", "nullspace_last_error", "nullspace_locality_order",
-           "nullspace_update_values"]
+           "nullspace_update_values", "nullspace_cycle_times"]
 
 _lib = None
 
@@ -122,9 +122,10 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.nullspace_last_error.restype = ctypes.c_char_p
     lib.nullspace_locality_order.argtypes = [i64, i64, vp, vp, vp, vp]
     lib.nullspace_update_values.argtypes = [vp, vp]
+    lib.nullspace_cycle_times.argtypes = [vp, ctypes.POINTER(dbl), i32, ctypes.POINTER(i32)]
     for name in ("nullspace_init", "apply_op", "lanczos_run", "nullspace_nullity", "extract_basis",
                  "nullspace_ritz_values", "nullspace_ritz_eig", "backward",
-                 "nullspace_locality_order", "nullspace_update_values"):
+                 "nullspace_locality_order", "nullspace_update_values", "nullspace_cycle_times"):
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -236,6 +237,13 @@ class Context:
         _check(load().nullspace_ritz_values(self._h, buf, cap, ctypes.byref(cnt)))
         return [buf[i] for i in range(cnt.value)]
 
+    def cycle_times(self, cap: int = 1 << 16):
+        """Wall time (s) of each restart cycle of the last lanczos_run."""
+        buf = (ctypes.c_double * cap)()
+        cnt = ctypes.c_int32()
+        _check(load().nullspace_cycle_times(self._h, buf, cap, ctypes.byref(cnt)))
+        return [buf[i] for i in range(cnt.value)]
+
     def ritz_eig(self, theta, f, alpha, beta):
         """Eigenpairs of the restart matrix (d = 1) from device float64 vectors."""
         kk, m = int(theta.numel()), int(alpha.numel())
@@ -254,9 +262,9 @@ class Context:
             raise ValueError("vals must hold nnz values")
         _check(load().nullspace_update_values(self._h, _ptr(vals)))
 
-    def backward(self, gsv: torch.Tensor, tol: float = 1e-12, max_iter: int = 10 ** 6):
-        """grad w.r.t. A's stored values for G_s V (n x N), via the library's CG + SDDMM."""
-        g = gsv.t().contiguous()  # column-major n x N
+    def backward(self, dldv: torch.Tensor, tol: float = 1e-12, max_iter: int = 10 ** 6):
+        """grad w.r.t. A's stored values for dL/dV (n x N), via the library's CG + SDDMM."""
+        g = dldv.t().contiguous()  # column-major n x N
         grad = torch.empty(self.nnz, dtype=torch.float64, device="cuda")
         it = ctypes.c_int64()
         _check(load().backward(self._h, _ptr(g), self.n, _ptr(grad), float(tol), int(max_iter),

@@ -2,13 +2,13 @@
 
 The forward pass loads the values into a :class:`Context` built for A's
 pattern (``nullspace_update_values``), runs the solver and returns V (n x N).
-The backward pass hands G_s V to the library's ``backward`` entry point (range
+The backward pass hands dL/dV to the library's ``backward`` entry point (range
 CG on A^T A plus the SDDMM) and returns dL/dvals in A's CSR order.
 
 V is unique only up to a rotation of its columns, so the loss must depend on V
 through the projector P = V V^T alone (e.g. ||V^T X||_F^2 or tr(P M)); then
-dL/dV = 2 G_s V with G_s the symmetric part of dL/dP, which is what the
-backward pass needs.  N is held fixed: the derivative is that of the projector
+dL/dV = 2 G_s V with G_s the symmetric part of dL/dP, and the library takes
+G_s V = dL/dV / 2.  N is held fixed: the derivative is that of the projector
 onto the N smallest right singular vectors, defined while sigma_{N+1} > 0.
 
 One solve per Context at a time: a forward pass replaces the Context's basis,
@@ -38,8 +38,7 @@ class NullSpaceFunction(torch.autograd.Function):
         solver = ctx.solver
         if getattr(solver, "_generation", 0) != ctx.generation:
             raise RuntimeError("the Context ran another forward pass before this backward pass")
-        gsv = (0.5 * grad_v).contiguous()
-        grad, _ = solver.backward(gsv, tol=ctx.tol, max_iter=ctx.max_iter)
+        grad, _ = solver.backward(grad_v.contiguous(), tol=ctx.tol, max_iter=ctx.max_iter)
         return grad, None, None, None
 
 

@@ -200,6 +200,16 @@ nsp_status nullspace_ritz_values(nsp_ctx* ctx, double* theta, int32_t cap, int32
   });
 }
 
+nsp_status nullspace_cycle_times(nsp_ctx* ctx, double* seconds, int32_t cap, int32_t* count) {
+  return guarded([&] {
+    NSP_REQUIRE(ctx != nullptr && count != nullptr, "arguments must not be NULL");
+    NSP_REQUIRE(cap >= 0 && (cap == 0 || seconds != nullptr), "seconds must hold cap values");
+    const int32_t k = (int32_t)std::min<size_t>((size_t)cap, ctx->cycle_s.size());
+    for (int32_t i = 0; i < k; ++i) seconds[i] = ctx->cycle_s[i];
+    *count = k;
+  });
+}
+
 nsp_status nullspace_ritz_eig(nsp_ctx* ctx, int32_t K, int32_t kk, const double* theta,
                               const double* f, const double* alpha, const double* beta,
                               double* evals, double* evecs) {
@@ -272,18 +282,18 @@ nsp_status nullspace_update_values(nsp_ctx* ctx, const double* vals) {
   });
 }
 
-nsp_status backward(nsp_ctx* ctx, const double* GsV, int64_t ld, double* grad_vals, double tol,
+nsp_status backward(nsp_ctx* ctx, const double* dLdV, int64_t ld, double* grad_vals, double tol,
                     int64_t max_iter, int64_t* iters) {
   return guarded([&] {
     NSP_REQUIRE(ctx != nullptr, "ctx must not be NULL");
     if (ctx->state < 1) throw nsp::Error(NSP_ERR_STATE, "no basis yet: call lanczos_run first");
     NSP_REQUIRE(grad_vals != nullptr || ctx->nnz == 0, "grad_vals must not be NULL");
-    NSP_REQUIRE(ctx->nullity == 0 || (GsV != nullptr && ld >= ctx->n), "GsV must be n x N, ld >= n");
+    NSP_REQUIRE(ctx->nullity == 0 || (dLdV != nullptr && ld >= ctx->n), "dLdV must be n x N, ld >= n");
     NSP_REQUIRE(tol > 0.0 && max_iter > 0, "tol and max_iter must be positive");
     NSP_REQUIRE(!(ctx->precond && ctx->sym),
                 "backward does not support the preconditioned symmetric form");
     enter(ctx);
-    nsp::run_backward(ctx, GsV, ld, grad_vals, tol, max_iter, iters);
+    nsp::run_backward(ctx, dLdV, ld, grad_vals, tol, max_iter, iters);
     leave(ctx);
   });
 }

@@ -187,6 +187,7 @@ struct nsp_ctx {
   int state = 0;            // 0 = initialised, 1 = basis available
   bool values_ok = true;    // false after a rejected nullspace_update_values
   std::vector<double> ritz; // last Ritz values (host)
+  std::vector<double> cycle_s; // wall time of each restart cycle of the last solve (host)
   nsp_stats stats{};
 };
 
@@ -220,10 +221,14 @@ void refresh_values(nsp_ctx* c, const double* vals);
 
 // apply_op helper: Y = B X (FP64, column-major, ld)
 void apply_b_colmajor(nsp_ctx* c, const double* X, int64_t ldx, double* Y, int64_t ldy, int ncols);
+// the same with caller-provided scratch: chunks of at most wmax (<= kMaxD)
+// columns, xc / xr / zr of n * wmax doubles and yr of m * wmax doubles
+void apply_b_chunks(nsp_ctx* c, const double* X, int64_t ldx, double* Y, int64_t ldy, int ncols,
+                    int wmax, double* xc, double* xr, double* yr, double* zr);
 
 // Lanczos solve (solver.hip)
 void solve(nsp_ctx* c);
-void run_backward(nsp_ctx* c, const double* GsV, int64_t ld, double* grad, double tol,
+void run_backward(nsp_ctx* c, const double* dLdV, int64_t ld, double* grad, double tol,
                   int64_t max_iter, int64_t* iters);
 
 }  // namespace nsp

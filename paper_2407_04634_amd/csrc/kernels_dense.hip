@@ -748,6 +748,18 @@ __global__ __launch_bounds__(512) void k_ts_nn_v(const int* cond, int64_t n,
   }
 }
 
+// Partial reorthogonalisation is one classical Gram-Schmidt pass (Sec. 4.2),
+// accepted by the Kahan-Parlett criterion: each projected column of the unit
+// pair [Q_ell, Q_ell+1] must keep at least 1/sqrt(2) of its norm, i.e. the
+// diagonal of its Gram matrix g must stay >= 1/2.  A flagged step starts from
+// a loss of orthogonality just above sqrt(u), so this holds by a wide margin
+// unless the W bound failed.
+__device__ bool kahan_parlett_ok(int k, const double* g) {
+  for (int i = 0; i < k; ++i)
+    if (!(g[i + i * k] >= 0.5)) return false;
+  return true;
+}
+
 // Rows per block of the C -= Z H kernel (and so the number of Gram partials).
 template <typename VT, int NC> constexpr int ts_nn_rows() { return NC <= 8 ? kWave * RowVec<VT>::R : kWave; }
 
@@ -764,6 +776,7 @@ __global__ __launch_bounds__(256) void k_ts_gramfin(const int* cond, int nparts,
   if (threadIdx.x == 0) {
     double r[NV], ri[NV];
     if (!chol_upper_inv(NC, res, r, ri)) atomicOr(flags + 1, 1);
+    if (cond && !kahan_parlett_ok(NC, res)) atomicOr(flags + 1, 2);
     for (int i = 0; i < NV; ++i) { rinv[i] = ri[i]; rinv[NV + i] = r[i]; }
   }
 }
@@ -794,6 +807,7 @@ __global__ __launch_bounds__(kThreads) void k_ts_scale(const int* cond, int64_t 
       for (int i = 0; i < NV; ++i) ri[i] = rv[i];
       if (blockIdx.x == 0) {
         if (!ok) atomicOr(flags + 1, 1);
+        if (cond && !kahan_parlett_ok(NC, res)) atomicOr(flags + 1, 2);
         for (int i = 0; i < NV; ++i) { rinv[i] = rv[i]; rinv[NV + i] = r[i]; }
       }
     }

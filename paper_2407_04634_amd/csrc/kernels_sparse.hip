@@ -1081,32 +1081,39 @@ void precondition(nsp_ctx* c) {
 
 // Y = B X for column-major FP64 X, Y (apply_op).  Columns go through the
 // row-interleaved path in chunks of at most 8.
+void apply_b_chunks(nsp_ctx* c, const double* X, int64_t ldx, double* Y, int64_t ldy, int ncols,
+                    int wmax, double* xc, double* xr, double* yr, double* zr) {
+  const int64_t n = c->n;
+  const int32_t* cp = c->colperm.as<int32_t>();
+  for (int j0 = 0; j0 < ncols;) {
+    const int left = std::min(ncols - j0, wmax);
+    const int w = left >= 8 ? 8 : left >= 4 ? 4 : left >= 2 ? 2 : 1;
+    gather_rows(c, n, w, cp, X + (int64_t)j0 * ldx, ldx, xc, n);
+    colmajor_to_rows(c, n, w, xc, n, xr);
+    // B X: A^T (A X) + eps D X, or A X + eps D X for the symmetric form (the
+    // stored A^T is A itself then)
+    const double* yin = xr;
+    if (!c->sym) {
+      spmm_block<double>(c, c->A, w, xr, yr);
+      yin = yr;
+    }
+    spmmT_step<double>(c, w, yin, xr, nullptr, nullptr, zr, nullptr);
+    rows_to_colmajor(c, n, w, zr, xc, n);
+    scatter_rows(c, n, w, cp, xc, n, Y + (int64_t)j0 * ldy, ldy);
+    j0 += w;
+  }
+  NSP_HIP(hipStreamSynchronize(c->stream));
+}
+
 void apply_b_colmajor(nsp_ctx* c, const double* X, int64_t ldx, double* Y, int64_t ldy, int ncols) {
   const int64_t m = c->m, n = c->n;
-  const int32_t* cp = c->colperm.as<int32_t>();
   DBuf xc, xr, yr, zr;
   xc.alloc(sizeof(double) * n * kMaxD);
   xr.alloc(sizeof(double) * n * kMaxD);
   yr.alloc(sizeof(double) * m * kMaxD);
   zr.alloc(sizeof(double) * n * kMaxD);
-  for (int j0 = 0; j0 < ncols;) {
-    const int left = ncols - j0;
-    const int w = left >= 8 ? 8 : left >= 4 ? 4 : left >= 2 ? 2 : 1;
-    gather_rows(c, n, w, cp, X + (int64_t)j0 * ldx, ldx, xc.as<double>(), n);
-    colmajor_to_rows(c, n, w, xc.as<double>(), n, xr.as<double>());
-    // B X: A^T (A X) + eps D X, or A X + eps D X for the symmetric form (the
-    // stored A^T is A itself then)
-    const double* yin = xr.as<double>();
-    if (!c->sym) {
-      spmm_block<double>(c, c->A, w, xr.as<double>(), yr.as<double>());
-      yin = yr.as<double>();
-    }
-    spmmT_step<double>(c, w, yin, xr.as<double>(), nullptr, nullptr, zr.as<double>(), nullptr);
-    rows_to_colmajor(c, n, w, zr.as<double>(), xc.as<double>(), n);
-    scatter_rows(c, n, w, cp, xc.as<double>(), n, Y + (int64_t)j0 * ldy, ldy);
-    j0 += w;
-  }
-  NSP_HIP(hipStreamSynchronize(c->stream));
+  apply_b_chunks(c, X, ldx, Y, ldy, ncols, kMaxD, xc.as<double>(), xr.as<double>(), yr.as<double>(),
+                 zr.as<double>());
 }
 
 }  // namespace nsp

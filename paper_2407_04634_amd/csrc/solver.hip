@@ -6,8 +6,10 @@
 //      [d, K - 2d];
 //  R2  the recurrence subtracts Q_{ell-1} Gamma_{ell-1}^T;
 //  R3/R4 the W-recurrence cases (see k_wrec);
-//  R5  partial reorthogonalisation = one classical Gram-Schmidt pass (the vectors
-//      are semi-orthogonal); the cycle's first step and the restart use two;
+//  R5  partial reorthogonalisation = one classical Gram-Schmidt pass, accepted
+//      by the Kahan-Parlett criterion (each unit column keeps >= 1/sqrt(2) of
+//      its norm; checked on the device, a violation stops the run); the
+//      cycle's first step and the restart use two passes;
 //  R6  QR = Cholesky QR (twice for d > 1), positive diagonal;
 //  R7  ||B|| = ||A||_1 ||A||_inf + eps max(D) in the first cycle, then the
 //      largest Ritz value;
@@ -323,6 +325,7 @@ struct Lanczos {
     const char* ns = std::getenv("NSP_NO_SPEED_STOP");
     const bool no_speed_stop = ns && ns[0] == '1';
     double last_print = now_s();
+    c->cycle_s.clear();
     for (;;) {
       const double tc0 = now_s();
       const int kk = l0 * d;
@@ -387,6 +390,10 @@ struct Lanczos {
       if (flags_h[4] != 0)
         throw Error(NSP_ERR_HIP, "tridiagonal eigensolver did not converge (info " +
                                      std::to_string(flags_h[4]) + ")");
+      if (flags_h[1] & 2)
+        throw Error(NSP_ERR_BREAKDOWN,
+                    "partial reorthogonalisation: one Gram-Schmidt pass removed more than "
+                    "1 - 1/sqrt(2) of a vector's norm (the W bound failed)");
       if (flags_h[1]) throw Error(NSP_ERR_BREAKDOWN, "a Lanczos block lost rank (Krylov breakdown)");
       for (double v : hev)
         if (!std::isfinite(v)) throw Error(NSP_ERR_NONFINITE, "non-finite Ritz value");
@@ -404,7 +411,9 @@ struct Lanczos {
       c->ritz = hev;
       if (stop || budget) {
         extract(n_ell);
+        NSP_HIP(hipStreamSynchronize(c->stream));
         t_rr += now_s() - tc1;
+        c->cycle_s.push_back(now_s() - tc0);
         break;
       }
       // ---- thick restart (Sec. 4.1)
@@ -415,7 +424,9 @@ struct Lanczos {
       u_d = d * u_step * norm_b;
       l0 = kn / d;
       st.restarts++;
+      NSP_HIP(hipStreamSynchronize(c->stream));
       t_rr += now_s() - tc1;
+      c->cycle_s.push_back(now_s() - tc0);
     }
     NSP_HIP(hipMemcpyAsync(c->pin_i, flags, sizeof(int) * 8, hipMemcpyDeviceToHost, c->stream));
     NSP_HIP(hipStreamSynchronize(c->stream));
@@ -864,7 +875,7 @@ void solve(nsp_ctx* c) {
 // ---------------------------------------------------------------------------
 // backward: W = (A^T A)^+ (I - V V^T) G_s V by CG on range(A^T); grad = SDDMM
 // ---------------------------------------------------------------------------
-void run_backward(nsp_ctx* c, const double* GsV, int64_t ld, double* grad, double tol,
+void run_backward(nsp_ctx* c, const double* dLdV, int64_t ld, double* grad, double tol,
                   int64_t max_iter, int64_t* iters) {
   const int64_t n = c->n, m = c->m;
   const int k = c->nullity;
@@ -881,10 +892,10 @@ void run_backward(nsp_ctx* c, const double* GsV, int64_t ld, double* grad, doubl
   double* r = alloc_as<double>(b_r, (size_t)n * k);
   colmajor_to_rows(c, n, k, c->V.as<double>(), n, vr);
   {
-    // G_s V arrives in the caller's order of the unknowns
+    // dL/dV arrives in the caller's order of the unknowns
     DBuf b_gc;
     double* gc = alloc_as<double>(b_gc, (size_t)n * k);
-    gather_rows(c, n, k, c->colperm.as<int32_t>(), GsV, ld, gc, n);
+    gather_rows(c, n, k, c->colperm.as<int32_t>(), dLdV, ld, gc, n);
     colmajor_to_rows(c, n, k, gc, n, r);
     NSP_HIP(hipStreamSynchronize(c->stream));
   }
@@ -1041,9 +1052,11 @@ void run_backward(nsp_ctx* c, const double* GsV, int64_t ld, double* grad, doubl
     }
   }
   // W = W_U C (row-major n x k): Wcm (k x n) = C^T W_Ucm; the buffer u is free now
-  // (preconditioned: X = X_U C, and A W = (A P^{-T}) X below)
+  // (preconditioned: X = X_U C, and A W = (A P^{-T}) X below).  The right-hand
+  // side so far was dL/dV; the projector's symmetric gradient enters as
+  // G_s V = (dL/dV) / 2, hence the factor 1/2 here (W is linear in it).
   double* wf = alloc_as<double>(b_u, (size_t)n * k);
-  dgemm(c, rocblas_operation_transpose, rocblas_operation_none, k, n, kc, 1.0, crd, kc, w, kc, 0.0, wf, k);
+  dgemm(c, rocblas_operation_transpose, rocblas_operation_none, k, n, kc, 0.5, crd, kc, w, kc, 0.0, wf, k);
   // Y = A W, grad_p = -2 <Y_i, V_j>
   spmm_wide(c, c->A, k, wf, y);
   {

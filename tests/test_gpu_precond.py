@@ -133,8 +133,8 @@ def test_backward_precond_matches_dense_gradient():
     assert ctx.lanczos_run()["nullity"] == 8
     v = ctx.extract_basis().cpu().numpy()
     x = G.gaussian_matrix(c.n, 8, seed=5)
-    gsv = bw.gsv_pxf(v, x)
-    grad, it = ctx.backward(torch.from_numpy(gsv).cuda(), tol=1e-13)
+    dldv = 2.0 * bw.gsv_pxf(v, x)  # L = ||P X||_F^2: dL/dV = 2 G_s V
+    grad, it = ctx.backward(torch.from_numpy(dldv).cuda(), tol=1e-13)
     grad = grad.cpu().numpy()
     rows = np.repeat(np.arange(c.m), np.diff(c.rowptr))
     ref = bw.dense_grad(ad, 8, bw.gs_pxf(x), rows, c.colind)

@@ -127,8 +127,8 @@ def test_fd_instance_backward_other_right_hand_sides(kind):
     else:
         h = G.gaussian_matrix(c.n, c.n, seed=7)
         gs = h + h.T
-    gsv = gs @ v
-    grad, it = ctx.backward(torch.from_numpy(np.ascontiguousarray(gsv)).cuda(), tol=1e-13)
+    dldv = 2.0 * (gs @ v)  # dL/dV = 2 G_s V for a loss on P
+    grad, it = ctx.backward(torch.from_numpy(np.ascontiguousarray(dldv)).cuda(), tol=1e-13)
     grad = grad.cpu().numpy()
     rows = np.repeat(np.arange(c.m), np.diff(c.rowptr))
     ref = bw.dense_grad(ad, 8, gs, rows, c.colind)
@@ -152,8 +152,8 @@ def test_fd_instance_backward_matches_dense_gradient():
     assert st["nullity"] == 8
     v = _basis(ctx)
     x = G.gaussian_matrix(c.n, 8, seed=5)
-    gsv = bw.gsv_pxf(v, x)
-    grad, it = ctx.backward(torch.from_numpy(gsv).cuda(), tol=1e-13)
+    dldv = 2.0 * bw.gsv_pxf(v, x)  # L = ||P X||_F^2: dL/dV = 2 G_s V
+    grad, it = ctx.backward(torch.from_numpy(dldv).cuda(), tol=1e-13)
     grad = grad.cpu().numpy()
     rows = np.repeat(np.arange(c.m), np.diff(c.rowptr))
     ref = bw.dense_grad(ad, 8, bw.gs_pxf(x), rows, c.colind)
