@@ -222,6 +222,17 @@ nsp_status extract_basis(nsp_ctx* ctx, double* V, int64_t ldv);
  *  (min(cap, dim K)).  Before refinement, i.e. eigenvalues of T_ell. */
 nsp_status nullspace_ritz_values(nsp_ctx* ctx, double* theta, int32_t cap, int32_t* count);
 
+/* Residual norms of the Ritz pairs of the last Rayleigh-Ritz extraction, in
+ * the order of nullspace_ritz_values (host out).  The Lanczos decomposition
+ * B Z = Z T + Q_{ell+1} [0, Gamma_ell] (Eq. "laniter", with the arrowhead T
+ * of Eq. "defT" after a restart) gives the Ritz pair (theta_i, Z V_Z(:, i))
+ * the residual Q_{ell+1} Gamma_ell V_Z(last d rows, i); the value returned is
+ * its norm ||Gamma_ell V_Z(last d rows, i)||, the usual convergence measure
+ * (Sec. 4.1: the coupling block F of the kept pairs is made of these rows).
+ *  res  host buffer of capacity cap; *count receives min(cap, dim K).
+ * Errors: NSP_ERR_ARG for NULL pointers. */
+nsp_status nullspace_ritz_residuals(nsp_ctx* ctx, double* res, int32_t cap, int32_t* count);
+
 /* Wall time of each restart cycle of the last lanczos_run, in order (host
  * out): one cycle of Alg. 2's outer loop = the block Lanczos steps from
  * ell_0 + 1 to dim K / d with their partial reorthogonalisation, the

@@ -346,10 +346,13 @@ def algorithm2(a, eps: float, dvec: np.ndarray, omega: np.ndarray, dim_k: int,
             v = zb[:, :dim_k] @ vz[:, :n_ell]
             # the last cycle's Lanczos decomposition B Z = Z T + Q_next [0, Gamma_last]
             # (Eq. "laniter"), returned for the invariant checks of the tests
+            # residual norm of each Ritz pair: ||Gamma_last V_Z(last d rows, i)||
+            ritz_res = np.linalg.norm(gams[nb] @ vz[dim_k - d:dim_k, :], axis=0)
             return dict(V=v, N=n_ell, theta=theta, matvecs=matvecs, restarts=restarts,
                         reorths=reorths, history=history, converged=bool(stop),
                         orth_trace=orth_trace, u_d=u_d, Z=zb[:, :dim_k].copy(), T=t,
-                        Q_next=zb[:, dim_k:dim_k + d].copy(), Gamma_last=gams[nb], l0=l0)
+                        Q_next=zb[:, dim_k:dim_k + d].copy(), Gamma_last=gams[nb], l0=l0,
+                        ritz_res=ritz_res)
         # ---- thick restart (Sec. 4.1)
         k_keep = restart_size(n_ell, dim_k, d)
         if n_ell > k_keep:

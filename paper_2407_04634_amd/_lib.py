@@ -91,7 +91,7 @@ class Stats(ctypes.Structure):
 EXPORTS = ["nsp_default_params", "nullspace_init", "apply_op", "lanczos_run", "nullspace_nullity",
            "extract_basis", "nullspace_ritz_values", "nullspace_ritz_eig", "backward",
            "nullspace_destroy", "nullspace_last_error", "nullspace_locality_order",
-           "nullspace_update_values", "nullspace_cycle_times"]
+           "nullspace_update_values", "nullspace_cycle_times", "nullspace_ritz_residuals"]
 
 _lib = None
 
@@ -123,9 +123,11 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.nullspace_locality_order.argtypes = [i64, i64, vp, vp, vp, vp]
     lib.nullspace_update_values.argtypes = [vp, vp]
     lib.nullspace_cycle_times.argtypes = [vp, ctypes.POINTER(dbl), i32, ctypes.POINTER(i32)]
+    lib.nullspace_ritz_residuals.argtypes = [vp, ctypes.POINTER(dbl), i32, ctypes.POINTER(i32)]
     for name in ("nullspace_init", "apply_op", "lanczos_run", "nullspace_nullity", "extract_basis",
                  "nullspace_ritz_values", "nullspace_ritz_eig", "backward",
-                 "nullspace_locality_order", "nullspace_update_values", "nullspace_cycle_times"):
+                 "nullspace_locality_order", "nullspace_update_values", "nullspace_cycle_times",
+                 "nullspace_ritz_residuals"):
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -235,6 +237,13 @@ class Context:
         buf = (ctypes.c_double * cap)()
         cnt = ctypes.c_int32()
         _check(load().nullspace_ritz_values(self._h, buf, cap, ctypes.byref(cnt)))
+        return [buf[i] for i in range(cnt.value)]
+
+    def ritz_residuals(self, cap: int = 1 << 14):
+        """Residual norms ||Gamma_ell V_Z(last d rows, i)|| of the last Ritz pairs."""
+        buf = (ctypes.c_double * cap)()
+        cnt = ctypes.c_int32()
+        _check(load().nullspace_ritz_residuals(self._h, buf, cap, ctypes.byref(cnt)))
         return [buf[i] for i in range(cnt.value)]
 
     def cycle_times(self, cap: int = 1 << 16):

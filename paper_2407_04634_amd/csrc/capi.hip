@@ -200,6 +200,16 @@ nsp_status nullspace_ritz_values(nsp_ctx* ctx, double* theta, int32_t cap, int32
   });
 }
 
+nsp_status nullspace_ritz_residuals(nsp_ctx* ctx, double* res, int32_t cap, int32_t* count) {
+  return guarded([&] {
+    NSP_REQUIRE(ctx != nullptr && count != nullptr, "arguments must not be NULL");
+    NSP_REQUIRE(cap >= 0 && (cap == 0 || res != nullptr), "res must hold cap values");
+    const int32_t k = (int32_t)std::min<size_t>((size_t)cap, ctx->ritz_res.size());
+    for (int32_t i = 0; i < k; ++i) res[i] = ctx->ritz_res[i];
+    *count = k;
+  });
+}
+
 nsp_status nullspace_cycle_times(nsp_ctx* ctx, double* seconds, int32_t cap, int32_t* count) {
   return guarded([&] {
     NSP_REQUIRE(ctx != nullptr && count != nullptr, "arguments must not be NULL");

@@ -187,6 +187,7 @@ struct nsp_ctx {
   int state = 0;            // 0 = initialised, 1 = basis available
   bool values_ok = true;    // false after a rejected nullspace_update_values
   std::vector<double> ritz; // last Ritz values (host)
+  std::vector<double> ritz_res; // their Lanczos residual norms (host)
   std::vector<double> cycle_s; // wall time of each restart cycle of the last solve (host)
   nsp_stats stats{};
 };

@@ -407,12 +407,13 @@ struct CPair {
 };
 
 // Basis columns per wave (JW) and per block (JB) of the projection kernel.
-// FP32 rows come four per 16-byte load, so half as many columns keep the
-// register footprint (and the occupancy) of the FP64 kernel.
+// Each column is one 16-byte load per lane and row group, kept in its storage
+// precision until its FMAs, so FP32 keeps as many loads in flight as FP64.
+constexpr int ts_jw(int nc) { return nc >= 16 ? 1 : (nc >= 4 ? 4 : 8); }
+constexpr int kTsWaves = 4;  // waves per block (8 measured slower: fewer, heavier blocks)
 template <int NC, int ESIZE = 8> struct TsShape {
-  static constexpr int JW8 = NC >= 16 ? 1 : (NC >= 4 ? 4 : 8);
-  static constexpr int JW = ESIZE == 4 && JW8 > 1 ? JW8 / 2 : JW8;
-  static constexpr int NWT = 4;  // waves per block (8 measured slower: fewer, heavier blocks)
+  static constexpr int JW = ts_jw(NC);
+  static constexpr int NWT = kTsWaves;
   static constexpr int JB = NWT * JW;
 };
 
@@ -445,6 +446,26 @@ __device__ __forceinline__ void load_crow(const VT* __restrict__ p, double (&o)[
 #pragma unroll
     for (int c = 0; c < DA; ++c) o[c] = (double)p[c];
   }
+}
+
+// RV consecutive rows of a column as one 16-byte vector (zeros past n)
+template <typename VT>
+__device__ __forceinline__ typename RowVec<VT>::T load_vec(const VT* __restrict__ p, int64_t r,
+                                                           int64_t n) {
+  using V = typename RowVec<VT>::T;
+  constexpr int R = RowVec<VT>::R;
+  if (r + R <= n) return *reinterpret_cast<const V*>(p + r);
+  VT t[R];
+#pragma unroll
+  for (int i = 0; i < R; ++i) t[i] = r + i < n ? p[r + i] : VT(0);
+  if constexpr (R == 2) return V{t[0], t[1]};
+  else return V{t[0], t[1], t[2], t[3]};
+}
+
+template <typename V>
+__device__ __forceinline__ double vec_elem(const V& v, int i) {
+  if constexpr (sizeof(v.x) == 8) return i == 0 ? v.x : v.y;
+  else return (double)(i == 0 ? v.x : i == 1 ? v.y : i == 2 ? v.z : v.w);
 }
 
 template <typename VT>
@@ -515,20 +536,22 @@ __global__ __launch_bounds__(kThreads) void k_ts_tn(const int* cond, int64_t n, 
           }
         }
       }
-      double zv[JW][RV];
+      // the JW column loads are issued together and stay in the storage
+      // precision (half the registers for FP32) until the FMAs
+      typename RowVec<VT>::T zv[JW];
 #pragma unroll
       for (int q = 0; q < JW; ++q) {
-        if (q < jn) load_rows<VT>(z + (int64_t)(j0 + q) * ldz, r, r1, zv[q]);
-        else
-#pragma unroll
-          for (int i = 0; i < RV; ++i) zv[q][i] = 0.0;
+        if (q < jn) zv[q] = load_vec<VT>(z + (int64_t)(j0 + q) * ldz, r, r1);
+        else zv[q] = typename RowVec<VT>::T{};
       }
 #pragma unroll
       for (int q = 0; q < JW; ++q)
 #pragma unroll
-        for (int i = 0; i < RV; ++i)
+        for (int i = 0; i < RV; ++i) {
+          const double zq = vec_elem(zv[q], i);
 #pragma unroll
-          for (int c = 0; c < NC; ++c) acc[q][c] = fma(zv[q][i], cv[i][c], acc[q][c]);
+          for (int c = 0; c < NC; ++c) acc[q][c] = fma(zq, cv[i][c], acc[q][c]);
+        }
     }
   }
 #pragma unroll
@@ -1110,8 +1133,8 @@ void w_reset(nsp_ctx* c, int col0, int ncols, double u_d, double* w, int ldw) {
 // Row chunk of the H = Z^T C kernel: about 2048 blocks over (chunks x column
 // groups), at least 1024 rows, a multiple of 256 rows (aligned vector loads).
 int64_t ts_chunk_rows(int64_t n, int k, int nc, int esize) {
-  int jb = nc >= 16 ? 4 : (nc >= 4 ? 16 : 32);
-  if (esize == 4 && nc < 16) jb /= 2;  // TsShape<NC, 4>::JB
+  const int jb = kTsWaves * ts_jw(nc);  // TsShape<NC, esize>::JB
+  (void)esize;
   const int64_t col_groups = std::max<int64_t>(1, (k + jb - 1) / jb);
   const int64_t chunks = std::max<int64_t>(1, 2048 / col_groups);
   int64_t rows = (n + chunks - 1) / chunks;

@@ -226,6 +226,8 @@ struct Lanczos {
       maxchunks = std::max(maxchunks, (n + chunk - 1) / chunk);
     }
     hpart = alloc_as<double>(b_hpart, (size_t)maxchunks * (K + d) * 2 * d);
+    // read-backs per cycle: K Ritz values, the last d rows of V_Z, Gamma_L
+    c->pin_d = c->pind.ensure((size_t)K * (d + 1) + (size_t)d * d + 16);
     flags = alloc_as<int>(c->flags, 8);
     NSP_HIP(hipMemsetAsync(flags, 0, sizeof(int) * 8, c->stream));
     NSP_HIP(hipMemsetAsync(W, 0, sizeof(double) * ldw * ldw, c->stream));
@@ -382,11 +384,19 @@ struct Lanczos {
         assemble_t(c, K, d, kk, theta_kept, fmat, xi, gam, T);
         syevd(c, K, T, evals, c->ework, b_info);
       }
+      // Ritz values, the last d rows of V_Z and Gamma_L (for the residual norms)
+      double* pin_s = c->pin_d + K;
+      double* pin_g = pin_s + (size_t)K * d;
       NSP_HIP(hipMemcpyAsync(c->pin_d, evals, sizeof(double) * K, hipMemcpyDeviceToHost, c->stream));
+      NSP_HIP(hipMemcpy2DAsync(pin_s, sizeof(double) * d, T + (K - d), sizeof(double) * K,
+                               sizeof(double) * d, K, hipMemcpyDeviceToHost, c->stream));
+      NSP_HIP(hipMemcpyAsync(pin_g, gam + (size_t)L * d * d, sizeof(double) * d * d,
+                             hipMemcpyDeviceToHost, c->stream));
       NSP_HIP(hipMemcpyAsync(c->pin_i, flags, sizeof(int) * 8, hipMemcpyDeviceToHost, c->stream));
       NSP_HIP(hipStreamSynchronize(c->stream));
       std::copy(c->pin_d, c->pin_d + K, hev.begin());
       std::copy(c->pin_i, c->pin_i + 8, flags_h);
+      ritz_residuals(pin_s, pin_g);
       if (flags_h[4] != 0)
         throw Error(NSP_ERR_HIP, "tridiagonal eigensolver did not converge (info " +
                                      std::to_string(flags_h[4]) + ")");
@@ -455,6 +465,24 @@ struct Lanczos {
     c->nullity = n_ell;
     c->state = 1;
     (void)t0;
+  }
+
+  // Lanczos residual norms of the Ritz pairs (Eq. "laniter"): with
+  // B Z = Z T + Q_{L+1} [0, Gamma_L], the pair (theta_i, Z V_Z(:, i)) has
+  // residual Q_{L+1} Gamma_L V_Z(last d rows, i), of norm ||Gamma_L s_i||.
+  // s: the last d rows of V_Z (d x K, column i at s + i d); g: Gamma_L
+  // (upper triangular, column-major d x d).
+  void ritz_residuals(const double* s, const double* g) {
+    c->ritz_res.assign(K, 0.0);
+    for (int i = 0; i < K; ++i) {
+      double r2 = 0.0;
+      for (int a = 0; a < d; ++a) {
+        double t = 0.0;
+        for (int b = a; b < d; ++b) t += g[a + b * d] * s[(size_t)i * d + b];
+        r2 += t * t;
+      }
+      c->ritz_res[i] = std::sqrt(r2);
+    }
   }
 
   // Z_new = Z V_Z(:, 1:kn); Q_{l0+1} = orth((I - Z_new Z_new^T) Q_{L+1}); F

@@ -128,3 +128,23 @@ def test_kahan_parlett_criterion_rejects_cancellation():
     q /= np.linalg.norm(q)
     with pytest.raises(RuntimeError, match="W bound failed"):
         lanczos.cgs1_accepted(z, q[:, None])
+
+
+@pytest.mark.parametrize("d", [1, 4])
+def test_ritz_residuals_bound_distance_to_the_spectrum(d):
+    """Kahan's bound for a symmetric B: a Ritz pair with residual norm r has an
+    eigenvalue of B within r of its Ritz value.  The residual norms the oracle
+    returns are ||Gamma_ell V_Z(last d rows, i)||, exact for the pairs of the
+    Lanczos decomposition; checked against the dense spectrum of B."""
+    c, a, eps, dim_k = _planted600()
+    dv = G.perturbation_diagonal(c.n, 2)
+    r = lanczos.algorithm2(a, eps, dv, G.gaussian_start_block(c.n, d, 2), dim_k, max_cycles=3)
+    lam = np.linalg.eigvalsh(op.apply_b(a, eps, dv, np.eye(c.n)))
+    nb = float(lam[-1])
+    slack = dim_k * math.sqrt(c.n) * lanczos.U * nb
+    dist = np.abs(r["theta"][:, None] - lam[None, :]).min(axis=1)
+    assert np.all(dist <= r["ritz_res"] + slack)
+    # and they are the true residual norms of the Ritz vectors
+    y = r["Z"] @ np.linalg.eigh(r["T"])[1]
+    true = np.linalg.norm(op.apply_b(a, eps, dv, y) - y * r["theta"][None, :], axis=0)
+    assert np.all(np.abs(true - r["ritz_res"]) <= slack)
