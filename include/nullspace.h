@@ -199,6 +199,20 @@ nsp_status nullspace_init(nsp_ctx** out, int64_t m, int64_t n, int64_t nnz,
 nsp_status apply_op(nsp_ctx* ctx, const double* X, int64_t ldx, double* Y, int64_t ldy,
                     int32_t ncols);
 
+/* apply_op without any device allocation, for callers that cannot allocate
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc).  Same arguments, result and errors as apply_op, computed by the
+ * same kernels; its scratch (X in the library's order, A X and B X: 3 n + m
+ * doubles per column) lives in a 64 MiB device array of the library, one per
+ * device, held until the process ends and shared by every call on that
+ * device.  Columns go in chunks of 8, 4, 2 or 1 as they fit; a matrix whose
+ * single column needs more than 64 MiB (3 n + m > 8 Mi) is rejected with
+ * NSP_ERR_ARG.  Calls that overlap in time on one device (other contexts or
+ * streams) race on the array and must be serialised by the caller.  The
+ * stream synchronisation at the end is the same as apply_op's. */
+nsp_status apply_op_noalloc(nsp_ctx* ctx, const double* X, int64_t ldx, double* Y, int64_t ldy,
+                            int32_t ncols);
+
 /* Run Algorithm 2 (Sec. 4.3) and, if p->refine, the FP64 refinement.
  *  st  host, may be NULL.
  * Returns NSP_OK, or NSP_ERR_NOCONV when the budget ran out (the basis of the

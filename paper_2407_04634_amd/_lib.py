@@ -91,7 +91,8 @@ class Stats(ctypes.Structure):
 EXPORTS = ["nsp_default_params", "nullspace_init", "apply_op", "lanczos_run", "nullspace_nullity",
            "extract_basis", "nullspace_ritz_values", "nullspace_ritz_eig", "backward",
            "nullspace_destroy", "nullspace_last_error", "nullspace_locality_order",
-           "nullspace_update_values", "nullspace_cycle_times", "nullspace_ritz_residuals"]
+           "nullspace_update_values", "nullspace_cycle_times", "nullspace_ritz_residuals",
+           "apply_op_noalloc"]
 
 _lib = None
 
@@ -110,6 +111,7 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.nullspace_init.argtypes = [ctypes.POINTER(vp), i64, i64, i64, vp, vp, vp, vp, vp,
                                    ctypes.POINTER(Params), vp]
     lib.apply_op.argtypes = [vp, vp, i64, vp, i64, i32]
+    lib.apply_op_noalloc.argtypes = [vp, vp, i64, vp, i64, i32]
     lib.lanczos_run.argtypes = [vp, ctypes.POINTER(Stats)]
     lib.nullspace_nullity.argtypes = [vp, ctypes.POINTER(i32)]
     lib.extract_basis.argtypes = [vp, vp, i64]
@@ -124,7 +126,7 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.nullspace_update_values.argtypes = [vp, vp]
     lib.nullspace_cycle_times.argtypes = [vp, ctypes.POINTER(dbl), i32, ctypes.POINTER(i32)]
     lib.nullspace_ritz_residuals.argtypes = [vp, ctypes.POINTER(dbl), i32, ctypes.POINTER(i32)]
-    for name in ("nullspace_init", "apply_op", "lanczos_run", "nullspace_nullity", "extract_basis",
+    for name in ("nullspace_init", "apply_op", "apply_op_noalloc", "lanczos_run", "nullspace_nullity", "extract_basis",
                  "nullspace_ritz_values", "nullspace_ritz_eig", "backward",
                  "nullspace_locality_order", "nullspace_update_values", "nullspace_cycle_times",
                  "nullspace_ritz_residuals"):
@@ -213,6 +215,23 @@ class Context:
         _check(load().apply_op(self._h, _ptr(xc), self.n, _ptr(y), self.n, k))
         y = y.t()
         return y.reshape(-1) if squeeze else y
+
+    def apply_op_noalloc(self, x: torch.Tensor, out: torch.Tensor) -> torch.Tensor:
+        """Y = B X into ``out`` through the allocation-free entry point.
+
+        ``x`` and ``out`` are n x k float64 CUDA tensors in column-major layout
+        (e.g. ``t.t()`` of a contiguous k x n tensor); the library allocates
+        nothing.
+        """
+        for t, name in ((x, "x"), (out, "out")):
+            if not (t.is_cuda and t.dtype == torch.float64 and t.dim() == 2 and t.shape[0] == self.n
+                    and t.stride(0) == 1 and t.stride(1) >= self.n):
+                raise TypeError(f"{name} must be an n x k column-major float64 CUDA tensor")
+        if out.shape[1] != x.shape[1]:
+            raise ValueError("x and out must have the same number of columns")
+        _check(load().apply_op_noalloc(self._h, _ptr(x), x.stride(1), _ptr(out), out.stride(1),
+                                       int(x.shape[1])))
+        return out
 
     def lanczos_run(self, allow_noconv: bool = False) -> dict:
         st = Stats()

@@ -111,6 +111,8 @@ nsp_status nullspace_init(nsp_ctx** out, int64_t m, int64_t n, int64_t nnz, cons
     c->nnz = nnz;
     c->prm = *p;
     c->user_stream = static_cast<hipStream_t>(stream);
+    NSP_HIP(hipGetDevice(&c->device));
+    nsp::noalloc_setup();  // scratch of apply_op_noalloc on this device
     NSP_HIP(hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking));
     NSP_HIP(hipEventCreateWithFlags(&c->ev_in, hipEventDisableTiming));
     NSP_HIP(hipEventCreateWithFlags(&c->ev_out, hipEventDisableTiming));
@@ -149,6 +151,20 @@ nsp_status apply_op(nsp_ctx* ctx, const double* X, int64_t ldx, double* Y, int64
     if (!ctx->values_ok) throw nsp::Error(NSP_ERR_STATE, "the last nullspace_update_values failed");
     enter(ctx);
     nsp::apply_b_colmajor(ctx, X, ldx, Y, ldy, ncols);
+    leave(ctx);
+  });
+}
+
+nsp_status apply_op_noalloc(nsp_ctx* ctx, const double* X, int64_t ldx, double* Y, int64_t ldy,
+                            int32_t ncols) {
+  return guarded([&] {
+    NSP_REQUIRE(ctx != nullptr, "ctx must not be NULL");
+    NSP_REQUIRE(ncols >= 1, "ncols must be >= 1");
+    NSP_REQUIRE(X != nullptr && Y != nullptr, "X and Y must not be NULL");
+    NSP_REQUIRE(ldx >= ctx->n && ldy >= ctx->n, "leading dimensions must be >= n");
+    if (!ctx->values_ok) throw nsp::Error(NSP_ERR_STATE, "the last nullspace_update_values failed");
+    enter(ctx);
+    nsp::apply_b_noalloc(ctx, X, ldx, Y, ldy, ncols);
     leave(ctx);
   });
 }

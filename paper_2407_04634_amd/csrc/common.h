@@ -125,6 +125,7 @@ struct PinBuf {
 
 struct nsp_ctx {
   int64_t m = 0, n = 0, nnz = 0;
+  int device = 0;                     // the device that was current at nullspace_init
   nsp_params prm{};
   hipStream_t stream = nullptr;       // the library's own non-blocking stream (all work)
   hipStream_t user_stream = nullptr;  // the caller's stream; ordered by events at each call
@@ -226,6 +227,10 @@ void apply_b_colmajor(nsp_ctx* c, const double* X, int64_t ldx, double* Y, int64
 // columns, xc / xr / zr of n * wmax doubles and yr of m * wmax doubles
 void apply_b_chunks(nsp_ctx* c, const double* X, int64_t ldx, double* Y, int64_t ldy, int ncols,
                     int wmax, double* xc, double* xr, double* yr, double* zr);
+// allocation-free apply_op (noalloc.hip): the scratch lives in a file-scope
+// device array; noalloc_setup resolves its address on the current device
+void noalloc_setup();
+void apply_b_noalloc(nsp_ctx* c, const double* X, int64_t ldx, double* Y, int64_t ldy, int ncols);
 
 // Lanczos solve (solver.hip)
 void solve(nsp_ctx* c);
