@@ -87,10 +87,9 @@ def range_cg(a: sp.csr_matrix, v: np.ndarray, rhs: np.ndarray, tol: float = 1e-1
 
     Every CG iterate lies in the Krylov space of A^T A and R; R is projected
     onto range(A^T) = null(A)^perp first, so the iteration stays on the range
-    where A^T A is positive definite.  Every 16 iterations the residual is
-    projected onto range(A^T) again (a no-op in exact arithmetic; it removes the
-    rounding-level null-space component A^T A cannot reduce when V is a null
-    basis only to rounding accuracy).  Columns stop individually once
+    where A^T A is positive definite.  V must span null(A) to working accuracy
+    (a closed-form basis): a null-space component of R left by a less
+    accurate V is one CG cannot reduce.  Columns stop individually once
     ||r_j|| <= tol * ||R_j||.
     """
     r = rhs - v @ (v.T @ rhs)
@@ -112,9 +111,6 @@ def range_cg(a: sp.csr_matrix, v: np.ndarray, rhs: np.ndarray, tol: float = 1e-1
         p = np.where(active[None, :], r + p * beta[None, :], p)
         rr = np.where(active, rnew, rr)
         it += 1
-        if it % 16 == 0:
-            r = r - v @ (v.T @ r)
-            rr = np.einsum("ij,ij->j", r, r)
         active = np.sqrt(rr) > tol * r0
     return w, it
 

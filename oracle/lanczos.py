@@ -57,11 +57,14 @@ listed with its justification in the design notes):
       stretch before the first increase is not a sample: the first Ritz
       value only has to separate the perturbed-zero cluster from the rest of
       the spectrum, the later ones must also resolve the cluster, so it
-      under-estimates s.  Without a sample the run goes to the matvec budget.
+      under-estimates s.  Without a sample the run goes to the matvec budget,
+      unless R12 applies.
   R11 the restart's coupling block is F = R Gamma_ell V_Z(last d rows, 1:k_keep),
       where R (~ I) is the triangular factor of re-orthonormalising Q_{ell+1}
       against the new Z_{ell_0}; the printed "[O, Gamma_{ell_0}] V_Z" drops
       Gamma_ell (Sec. 4.1 derives F = E_{ell+1} V_Z with E_{ell+1} = [0, Gamma_ell]).
+  R12 with N_ell = 0, stop once the smallest Ritz value has converged above
+      3 eps (see nothing_below).
 """
 from __future__ import annotations
 
@@ -254,6 +257,20 @@ def speed_rule(history, d: int):
     return (history[-1][0] - events[-1][0]) > s, s
 
 
+def nothing_below(theta, ritz_res, eps: float) -> bool:
+    """Reading R12: no Ritz value below 3 eps and the smallest one converged above it.
+
+    With N_ell = 0 the speed rule never gets a sample.  Sec. 4.3 names the
+    simpler idea of stopping once an unwanted Ritz value above 3 eps has
+    converged; here only for that case: theta_1 has residual r_1 <= eps and
+    theta_1 - r_1 >= 3 eps, so an eigenvalue of B lies in
+    [theta_1 - r_1, theta_1 + r_1], above the nullity threshold.
+    """
+    if len(theta) == 0 or theta[0] < 3.0 * eps:
+        return False
+    return bool(ritz_res[0] <= eps and theta[0] - ritz_res[0] >= 3.0 * eps)
+
+
 def algorithm2(a, eps: float, dvec: np.ndarray, omega: np.ndarray, dim_k: int,
                max_matvec: int = 10 ** 7, ro_tol: float | None = None, full_reorth: bool = False,
                track_orth: bool = False, max_cycles: int | None = None, op: str = "normal"):
@@ -340,14 +357,15 @@ def algorithm2(a, eps: float, dvec: np.ndarray, omega: np.ndarray, dim_k: int,
         theta, vz = np.linalg.eigh(t)
         n_ell = int(np.sum(theta < 3.0 * eps))
         history.append((matvecs, n_ell))
+        # residual norm of each Ritz pair: ||Gamma_last V_Z(last d rows, i)||
+        ritz_res = np.linalg.norm(gams[nb] @ vz[dim_k - d:dim_k, :], axis=0)
         stop, _ = speed_rule(history, d)
+        stop = stop or nothing_below(theta, ritz_res, eps)
         out_of_budget = matvecs >= max_matvec or (max_cycles is not None and restarts + 1 >= max_cycles)
         if stop or out_of_budget:
             v = zb[:, :dim_k] @ vz[:, :n_ell]
             # the last cycle's Lanczos decomposition B Z = Z T + Q_next [0, Gamma_last]
             # (Eq. "laniter"), returned for the invariant checks of the tests
-            # residual norm of each Ritz pair: ||Gamma_last V_Z(last d rows, i)||
-            ritz_res = np.linalg.norm(gams[nb] @ vz[dim_k - d:dim_k, :], axis=0)
             return dict(V=v, N=n_ell, theta=theta, matvecs=matvecs, restarts=restarts,
                         reorths=reorths, history=history, converged=bool(stop),
                         orth_trace=orth_trace, u_d=u_d, Z=zb[:, :dim_k].copy(), T=t,

@@ -11,7 +11,8 @@ Laplacians) the operator is B_R = P_R^{-1} A P_R^{-T} + eps D, with the same
 post-processing.
 
 P_R is either a diagonal (a vector p, P_R = diag(p)) or a dense invertible
-lower-triangular matrix; the library implements the diagonal case.
+lower-triangular matrix, e.g. the incomplete Cholesky factor of ``ichol``
+(the preconditioner of the paper's Laplacian experiments, Sec. 5.1).
 
 Readings (where the paper is silent):
   P1  the post-processed basis P_R^{-T} V_R is orthonormalised (thin QR with a
@@ -20,6 +21,11 @@ Readings (where the paper is silent):
       M = A^T A (normal form; p_j = ||A e_j||_2) or M = A (symmetric form;
       p_j = sqrt(A_jj)), i.e. the Cholesky factor of M with every off-diagonal
       entry dropped; p_j = 1 where that diagonal entry is not positive.
+  P5  incomplete Cholesky (Sec. 5.1 uses a threshold factor with drop
+      tolerance 1e-3 and diagonal compensation 0.1): L L^T ~ Mc = M + alpha
+      diag(M), computed column by column; the drop rule compares |l_ij| with
+      droptol times the 1-norm of Mc(j:n, j); droptol = 0 keeps exactly the
+      pattern of M (IC(0)).
 """
 from __future__ import annotations
 
@@ -41,6 +47,37 @@ def jacobi_diagonal(a: sp.csr_matrix, op: str = "normal") -> np.ndarray:
     pos = d > 0
     p[pos] = np.sqrt(d[pos])
     return p
+
+
+def ichol(m, droptol: float = 0.0, diagcomp: float = 0.0) -> np.ndarray:
+    """Incomplete Cholesky factor L (dense lower triangular) of M + diagcomp diag(M) (P5).
+
+    Column by column (j = 0, 1, ...): w = Mc(j:n, j) - L(j:n, :j) L(j, :j)^T,
+    l_jj = sqrt(w_j), l_ij = w_i / l_jj, then
+      droptol == 0: IC(0) -- l_ij kept only where M has a nonzero (i, j);
+      droptol > 0:  threshold -- l_ij dropped when |l_ij| < droptol ||Mc(j:n, j)||_1.
+    Raises ValueError on a non-positive pivot.  Dense: small matrices only.
+    """
+    md = m.toarray() if sp.issparse(m) else np.array(m, dtype=np.float64)
+    n = md.shape[0]
+    mc = md + diagcomp * np.diag(np.diag(md))
+    pattern = md != 0.0
+    lo = np.zeros((n, n))
+    for j in range(n):
+        w = mc[j:, j] - lo[j:, :j] @ lo[j, :j]
+        if not np.any(mc[j:, j]) and not np.any(w):
+            w[0] = 1.0  # an unknown M does not couple at all keeps l_jj = 1
+        if not (w[0] > 0.0):
+            raise ValueError(f"incomplete Cholesky: non-positive pivot at column {j}")
+        d = np.sqrt(w[0])
+        col = w[1:] / d
+        if droptol > 0.0:
+            keep = np.abs(col) >= droptol * np.sum(np.abs(mc[j:, j]))
+        else:
+            keep = pattern[j + 1:, j]
+        lo[j, j] = d
+        lo[j + 1:, j] = np.where(keep, col, 0.0)
+    return lo
 
 
 def _is_diag(pr) -> bool:

@@ -164,3 +164,22 @@ def test_diag_example_recovered_with_d1():
     r = lanczos.algorithm2(a, eps, G.perturbation_diagonal(n, 6), G.gaussian_start_block(n, 1, 6), 128)
     assert r["N"] == g["nullity"]
     assert exact.max_angle_sine(r["V"], np.eye(n)[:, :z]) < 0.1
+
+
+def test_full_column_rank_stops_with_nullity_zero():
+    """Reading R12: a matrix of full column rank has no Ritz value below 3 eps;
+    the run stops once the smallest one has converged above it, well before the
+    matvec budget, and that Ritz value is the smallest eigenvalue of B."""
+    rng = np.random.default_rng(4)
+    b = G._random_sparse_columns(rng, 400, 300, 8)
+    a = sp.csr_matrix(b)
+    smin2 = np.linalg.svd(a.toarray(), compute_uv=False)[-1] ** 2
+    eps = 0.1 * smin2
+    dv = G.perturbation_diagonal(300, 1)
+    r = lanczos.algorithm2(a, eps, dv, G.gaussian_start_block(300, 1, 1), 64, max_matvec=100_000)
+    assert r["N"] == 0 and r["converged"] and r["matvecs"] < 20_000
+    lam = np.linalg.eigvalsh(op.apply_b(a, eps, dv, np.eye(300)))
+    assert abs(r["theta"][0] - lam[0]) <= r["ritz_res"][0] + 1e-12 * lam[-1]
+    assert lanczos.nothing_below(np.array([5 * eps, 1.0]), np.array([0.1 * eps, 1.0]), eps)
+    assert not lanczos.nothing_below(np.array([2 * eps, 1.0]), np.array([0.0, 1.0]), eps)
+    assert not lanczos.nothing_below(np.array([3.5 * eps, 1.0]), np.array([0.9 * eps, 1.0]), eps)

@@ -142,3 +142,48 @@ def test_algorithm2_on_a_column_scaled_planted_matrix():
     v0 = exact.column_scaled_basis(exact.planted_basis(c.meta["R"]), c.meta["col_scale"])
     assert exact.max_angle_sine(v, v0) <= 1e-8
     assert np.linalg.norm(a @ v) <= 1e-10 * np.sqrt(np.sum(a.data ** 2))
+
+
+# ------------------------------------------------------------ incomplete Cholesky
+def test_ichol_without_fill_is_the_cholesky_factor():
+    """A tridiagonal matrix has no fill, so IC(0) is its exact Cholesky factor."""
+    n = 60
+    t = sp.diags([np.full(n - 1, -1.0), np.full(n, 2.5), np.full(n - 1, -1.0)], [-1, 0, 1])
+    lo = pc.ichol(t, 0.0, 0.0)
+    assert np.abs(lo - np.linalg.cholesky(t.toarray())).max() <= 1e-14
+
+
+def test_ichol_tiny_drop_tolerance_is_the_compensated_cholesky_factor():
+    c = G.er_component_laplacian(5, 40, 6.0, seed=3)
+    a = c.to_scipy()
+    lo = pc.ichol(a, 1e-16, 0.1)
+    ref = np.linalg.cholesky(a.toarray() + 0.1 * np.diag(a.diagonal()))
+    assert np.abs(lo - ref).max() <= 1e-13
+
+
+def test_ic0_matches_the_matrix_on_its_pattern():
+    """IC(0): L has the pattern of tril(M) and L L^T = Mc on that pattern."""
+    c = G.er_component_laplacian(5, 40, 6.0, seed=3)
+    a = c.to_scipy()
+    ad = a.toarray()
+    lo = pc.ichol(a, 0.0, 0.1)
+    assert np.all((lo != 0) <= (np.tril(ad) != 0))
+    r = ad + 0.1 * np.diag(np.diag(ad)) - lo @ lo.T
+    assert np.abs(r[ad != 0]).max() <= 1e-13
+
+
+def test_ichol_threshold_preconditions_the_laplacian():
+    """The Sec. 5.1 settings (drop tolerance 1e-3, compensation 0.1) shrink the
+    effective condition number of the symmetric form and keep its null space:
+    null(L^{-1} A L^{-T}) = L^T null(A)."""
+    c = G.config("er20")
+    a = c.to_scipy()
+    lo = pc.ichol(a, 1e-3, 0.1)
+    ar = pc.preconditioned_matrix(a, lo, op="sym").toarray()
+    lam0 = np.sort(np.linalg.eigvalsh(a.toarray()))
+    lam = np.sort(np.linalg.eigvalsh(0.5 * (ar + ar.T)))
+    assert lam0[19] < 1e-12 and lam[19] < 1e-12  # nullity 20 kept
+    kappa0, kappa = lam0[-1] / lam0[20], lam[-1] / lam[20]
+    assert kappa < kappa0 / 5, (kappa0, kappa)
+    v0 = exact.indicator_basis(c.meta["labels"])
+    assert np.linalg.norm(ar @ exact.orthonormalize(lo.T @ v0)) <= 1e-12
