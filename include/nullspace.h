@@ -71,7 +71,7 @@ typedef enum {
 
 typedef enum {
   NSP_PRECOND_NONE = 0,   /* Lanczos on B as given by op                              */
-  NSP_PRECOND_JACOBI = 1  /* outer preconditioning (Sec. 4.4, "Outer preconditioning")
+  NSP_PRECOND_JACOBI = 1, /* outer preconditioning (Sec. 4.4, "Outer preconditioning")
                              with the diagonal P_R = diag(p): Lanczos on
                              B_R = P_R^{-1} A^T A P_R^{-T} + eps D (NSP_OP_NORMAL,
                              p_j = ||A e_j||_2) or P_R^{-1} A P_R^{-T} + eps D
@@ -80,6 +80,17 @@ typedef enum {
                              P_R^T null(A); V = P_R^{-T} V_R, orthonormalised, is
                              what extract_basis returns.  Undoes column scaling
                              exactly (A S has the same B_R as A for diagonal S > 0). */
+  NSP_PRECOND_IC = 2      /* outer preconditioning with an incomplete Cholesky factor,
+                             the preconditioner of the paper's Laplacian experiments
+                             (Sec. 5.1): P_R = L, L L^T ~ M + ic_diagcomp diag(M)
+                             with M = A (NSP_OP_SYM) or M = A^T A (NSP_OP_NORMAL,
+                             formed on the host at init), factored on the host at
+                             init in the library's order of the unknowns.  Every
+                             application of B_R = L^{-1} A^T A L^{-T} + eps D (or
+                             L^{-1} A L^{-T} + eps D) solves with L^T and L on the
+                             device, level by level; V = L^{-T} V_R, orthonormalised.
+                             NSP_ERR_ARG at init on a non-positive pivot (raise
+                             ic_diagcomp) or a factor above 64 nnz(M) entries. */
 } nsp_precond;
 
 /* Solver parameters (host struct).  nsp_default_params() fills defaults. */
@@ -121,6 +132,12 @@ typedef struct {
                             ||A V||_F / ||A||_F of the returned basis.               */
   uint64_t seed;         /* seed of the built-in Philox4x32-10 draws of D and Omega,
                             used only when the caller passes D or Omega as NULL       */
+  double ic_droptol;     /* NSP_PRECOND_IC: > 0 drops the factor entries l_ij (i > j)
+                            with |l_ij| < ic_droptol ||Mc(j:n, j)||_1, Mc = M +
+                            ic_diagcomp diag(M) (threshold incomplete Cholesky);
+                            0 keeps exactly the pattern of M (IC(0)).  Default 1e-3. */
+  double ic_diagcomp;    /* NSP_PRECOND_IC: diagonal compensation alpha >= 0 (M +
+                            alpha diag(M) is factored).  Default 0.1.               */
 } nsp_params;
 
 /* Statistics of the last lanczos_run (host struct). */
@@ -162,7 +179,8 @@ typedef struct {
    max_matvec = 10^7, ro_tol = 0, prec = FP64, refine = 1, tol_rel_resid = 1e-10,
    tol_abs_resid = 0, tol_angle = 1e-9, max_refine_iter = 10^6, max_cycles = 0,
    profile = 0, reorder = 1, op = NSP_OP_NORMAL, precond = NSP_PRECOND_NONE,
-   seed = 20240704. */
+   seed = 20240704, ic_droptol = 1e-3, ic_diagcomp = 0.1 (the drop tolerance and
+   compensation of the incomplete Cholesky in Sec. 5.1). */
 void nsp_default_params(nsp_params* p);
 
 /* Create a solver context for A (m x n, nnz stored entries, CSR).
@@ -302,6 +320,10 @@ nsp_status nullspace_update_values(nsp_ctx* ctx, const double* vals);
  *             deflation the attainable level is about 1e-12: smaller values
  *             are raised to 1e-12.
  *  max_iter   CG iteration cap; the call returns NSP_ERR_NOCONV if reached.
+ *             A run whose largest relative residual has not dropped by 1%
+ *             within 4096 iterations has reached its attainable level (the
+ *             null-space component of the residual is removed only to the
+ *             accuracy of V) and ends there with NSP_OK.
  *  iters      host out (nullable): CG iterations used.
  * With NSP_PRECOND_JACOBI (normal form) the CG runs on the preconditioned
  * normal equations: A W = (A P_R^{-T}) X with (A P_R^{-T})^T (A P_R^{-T}) X =

@@ -17,5 +17,6 @@ from ._lib import (  # noqa: F401
     OP_SYM,
     PRECOND_NONE,
     PRECOND_JACOBI,
+    PRECOND_IC,
 )
 from .autograd import NullSpaceFunction, null_space  # noqa: F401

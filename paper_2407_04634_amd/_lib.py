@@ -21,7 +21,7 @@ STATUS_NAMES = ["NSP_OK", "NSP_ERR_ARG", "NSP_ERR_HIP", "NSP_ERR_NOMEM", "NSP_ER
                 "NSP_ERR_NOCONV", "NSP_ERR_BREAKDOWN", "NSP_ERR_NONFINITE"]
 PREC_FP64, PREC_MIXED = 0, 1
 OP_NORMAL, OP_SYM = 0, 1
-PRECOND_NONE, PRECOND_JACOBI = 0, 1
+PRECOND_NONE, PRECOND_JACOBI, PRECOND_IC = 0, 1, 2
 
 
 class NspError(RuntimeError):
@@ -50,6 +50,8 @@ class Params(ctypes.Structure):
         ("op", ctypes.c_int32),
         ("precond", ctypes.c_int32),
         ("seed", ctypes.c_uint64),
+        ("ic_droptol", ctypes.c_double),
+        ("ic_diagcomp", ctypes.c_double),
     ]
 
 

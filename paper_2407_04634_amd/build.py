@@ -15,7 +15,8 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libnullspace.so")
-SOURCES = ["capi.hip", "kernels_sparse.hip", "kernels_dense.hip", "eig.hip", "solver.hip", "noalloc.hip"]
+SOURCES = ["capi.hip", "kernels_sparse.hip", "kernels_dense.hip", "eig.hip", "solver.hip", "noalloc.hip",
+           "precond_ic.hip"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950",

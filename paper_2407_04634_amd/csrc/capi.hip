@@ -61,8 +61,12 @@ void validate_params(const nsp_params* p, int64_t n) {
   NSP_REQUIRE(p->max_cycles >= 0, "max_cycles must be >= 0");
   NSP_REQUIRE(p->reorder == 0 || p->reorder == 1, "reorder must be 0 or 1");
   NSP_REQUIRE(p->op == NSP_OP_NORMAL || p->op == NSP_OP_SYM, "op must be NSP_OP_NORMAL or NSP_OP_SYM");
-  NSP_REQUIRE(p->precond == NSP_PRECOND_NONE || p->precond == NSP_PRECOND_JACOBI,
-              "precond must be NSP_PRECOND_NONE or NSP_PRECOND_JACOBI");
+  NSP_REQUIRE(p->precond == NSP_PRECOND_NONE || p->precond == NSP_PRECOND_JACOBI ||
+                  p->precond == NSP_PRECOND_IC,
+              "precond must be NSP_PRECOND_NONE, NSP_PRECOND_JACOBI or NSP_PRECOND_IC");
+  NSP_REQUIRE(std::isfinite(p->ic_droptol) && p->ic_droptol >= 0.0 && std::isfinite(p->ic_diagcomp) &&
+                  p->ic_diagcomp >= 0.0,
+              "ic_droptol and ic_diagcomp must be finite and >= 0");
 }
 
 }  // namespace
@@ -89,6 +93,8 @@ void nsp_default_params(nsp_params* p) {
   p->op = NSP_OP_NORMAL;
   p->precond = NSP_PRECOND_NONE;
   p->seed = 20240704ull;
+  p->ic_droptol = 1e-3;
+  p->ic_diagcomp = 0.1;
 }
 
 nsp_status nullspace_init(nsp_ctx** out, int64_t m, int64_t n, int64_t nnz, const int64_t* rowptr,

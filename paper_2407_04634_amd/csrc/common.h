@@ -98,6 +98,20 @@ struct Csr {
 // nonzeros per row block of the streaming SpMV for a block of d columns
 constexpr int stream_tile(int d) { return 2048 / d; }
 
+// one triangular factor stored for a level-scheduled solve: CSR (int32), the
+// rows grouped by level (perm), level boundaries on the host
+struct TriSolve {
+  DBuf rowptr, colind, val, perm;
+  std::vector<int32_t> levptr;
+  int64_t nnz = 0;
+};
+// incomplete Cholesky P_R = L: L by rows (forward solves) and L^T by rows (backward)
+struct IcFactor {
+  TriSolve fwd, bwd;
+  int64_t m_nnz = 0;       // entries of the factored matrix M
+  double norm_bound = 0.0; // estimate of ||B_R - eps D|| (power iteration, with a margin)
+};
+
 // pinned host buffer for the small read-backs (hipHostMalloc, grown on demand)
 template <typename T>
 struct PinBuf {
@@ -154,6 +168,12 @@ struct nsp_ctx {
   // norm of that matrix and normA_fro_orig the caller's ||A||_F
   bool precond = false;
   nsp::DBuf pdiag;          // p in the library's order of the unknowns
+  // NSP_PRECOND_IC: the stored values stay those of A; every application of
+  // B_R solves with L^T and L (precond_ic.hip)
+  bool precond_ic = false;
+  nsp::IcFactor ic;
+  nsp::DBuf ic_tmp;         // n x d working-precision block of the Lanczos step
+  nsp::DBuf ic_wide, ic_dots;  // n x k FP64 block and dot partials of the wide products
   double normA_fro_orig = 0.0;
   double maxD = 1.0;        // max of the perturbation diagonal
 
@@ -216,6 +236,18 @@ double matrix_norms(nsp_ctx* c);
 // NSP_PRECOND_JACOBI: p from the stored matrix, stored values -> those of the
 // preconditioned matrix (FP32 copies included); call after matrix_norms
 void precondition(nsp_ctx* c);
+// NSP_PRECOND_IC (precond_ic.hip): factor M = A or A^T A, store L for the solves
+void ic_setup(nsp_ctx* c);
+// in-place solves L y = b / L^T y = b on a row-major n x k block
+template <typename VT> void ic_solve_l(nsp_ctx* c, int k, VT* y);
+template <typename VT> void ic_solve_lt(nsp_ctx* c, int k, VT* y);
+// y += eps D x on row-major n x k FP64 blocks
+void add_eps_dx(nsp_ctx* c, int k, const double* x, double* y);
+// P += eps D X - Xp Gamma_prev^T with Xi = X^T P partials (the Lanczos step's
+// epilogue when B is not applied by the fused products); returns the count
+template <typename VT>
+int step_epilogue(nsp_ctx* c, int d, const VT* x, const VT* xp, const double* gprev, VT* p,
+                  double* part_xi);
 void check_symmetric_values(nsp_ctx* c);
 void copy_f32(nsp_ctx* c);
 // nullspace_update_values: new values, same pattern (caller's order)

@@ -35,7 +35,9 @@ def _init(**kw):
     (dict(prec=7), "precision"),
     (dict(op=5), "op must be"),
     (dict(reorder=3), "reorder"),
-    (dict(precond=2), "precond must be"),
+    (dict(precond=3), "precond must be"),
+    (dict(precond=2, ic_droptol=-1.0), "ic_droptol"),
+    (dict(precond=2, ic_diagcomp=float("nan")), "ic_diagcomp"),
     (dict(op=1, m=120, n=100), "square"),
 ])
 def test_invalid_arguments_are_rejected(kw, msg):

@@ -158,3 +158,41 @@ def test_fd_instance_backward_matches_dense_gradient():
     rows = np.repeat(np.arange(c.m), np.diff(c.rowptr))
     ref = bw.dense_grad(ad, 8, bw.gs_pxf(x), rows, c.colind)
     assert np.linalg.norm(grad - ref) <= 1e-6 * np.linalg.norm(ref)
+
+
+def test_backward_matches_oracle_cg_sddmm_planted5000():
+    """The backward pass at the largest planted size the oracle's range CG
+    finishes within a test (5000 x 5000, nullity 20, 15k CG iterations):
+    L = ||P X||_F^2 with X seeded n x 8, against oracle.backward.cg_sddmm_grad
+    on the closed-form null basis (the GPU's own basis agrees with it to sin
+    angle <= 1e-8, and the gradient depends on V only through P)."""
+    import time
+
+    import torch
+    from oracle import backward as bw
+    from tests.gpu_util import context
+
+    c = G.config("planted50k", "small")
+    a = c.to_scipy()
+    v0 = exact.planted_basis(c.meta["R"])
+    print("[solver] planted5000 backward vs oracle CG + SDDMM", flush=True)
+    t0 = time.time()
+    ctx, dv, om = context(c, 2e-6, d=1, max_dim=200, tol_angle=1e-10)  # eps ~ 0.1 sigma^2
+    st = ctx.lanczos_run()
+    print(f"[solver] solve {time.time() - t0:.1f} s: nullity {st['nullity']}, {st['matvecs']} matvecs, "
+          f"{st['refine_iters']} refinement iterations", flush=True)
+    assert st["nullity"] == 20
+    v = _basis(ctx)
+    assert exact.max_angle_sine(v, v0) <= 1e-8
+    x = G.gaussian_matrix(c.n, 8, seed=5)
+    dldv = 2.0 * bw.gsv_pxf(v, x)  # L = ||P X||_F^2: dL/dV = 2 G_s V
+    t0 = time.time()
+    grad, it = ctx.backward(torch.from_numpy(np.ascontiguousarray(dldv)).cuda(), tol=1e-12)
+    grad = grad.cpu().numpy()
+    print(f"[solver] GPU backward {time.time() - t0:.1f} s, {it} CG iterations", flush=True)
+    t0 = time.time()
+    ref, it_o = bw.cg_sddmm_grad(a, v0, bw.gsv_pxf(v0, x), tol=1e-12)
+    print(f"[solver] oracle backward {time.time() - t0:.1f} s", flush=True)
+    err = np.linalg.norm(grad - ref) / np.linalg.norm(ref)
+    print(f"[solver] backward rel. error {err:.2e} (GPU {it} CG iterations, oracle {it_o})", flush=True)
+    assert err <= 1e-6
