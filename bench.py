@@ -47,7 +47,11 @@ HBM_PEAK_GBS = 8000.0
 # the algorithmic bytes.  Keyed by (workload, d, precision, kernel); an entry is
 # dropped whenever that kernel changes.  The summaries with their commands are
 # in profiles/.
-TRAFFIC = {}
+TRAFFIC = {
+    # profiles/k_ts_pair_zipf4m_traffic.md: 1511 reorthogonalising launches
+    ("zipf4m", 1, "mixed", "k_ts_tn"): {"ratio": 0.94},
+    ("zipf4m", 1, "mixed", "k_ts_nn_v"): {"ratio": 0.88},
+}
 
 # eps = c * sigma^2 with c = 0.1 (the Remark after Thm. "thmmain" asks for
 # c < 1/3), sigma^2 the smallest nonzero eigenvalue of A^T A (normal form) or
@@ -339,6 +343,54 @@ def leg_spmv(name, prec, d=1, max_dim=64):
             "frac_hbm": gbs / HBM_PEAK_GBS}
 
 
+def leg_gather(name="zipf4m", reps=20):
+    """Reference rates for the streaming SpMV's two access streams on the
+    pattern its kernel sees (the library's locality order): a pure gather
+    x[colind] (torch index_select, FP32 and FP64 x, int32 indices) and a plain
+    copy of the CSR stream's bytes (torch copy_).  The SpMV needs both; the
+    faster of the two references is a floor for its time."""
+    import torch
+    from paper_2407_04634_amd import locality_order
+    from workloads import generators as G
+
+    c = G.config(name)
+    ro, co = locality_order(c.rowptr, c.colind, c.m, c.n)
+    inv = np.empty(c.n, dtype=np.int32)
+    inv[co] = np.arange(c.n, dtype=np.int32)
+    lens = np.diff(c.rowptr)[ro]
+    starts = c.rowptr[:-1][ro]
+    take = np.repeat(starts - np.concatenate([[0], np.cumsum(lens)[:-1]]), lens) + np.arange(c.nnz)
+    ci = torch.from_numpy(inv[c.colind[take]]).cuda()
+    del take
+
+    def timed(fn):
+        fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) * 1e3 / reps
+
+    out = {"workload": name, "nnz": c.nnz, "n": c.n, "order": "library locality order"}
+    for tag, dt in (("fp32", torch.float32), ("fp64", torch.float64)):
+        x = torch.randn(c.n, dtype=dt, device="cuda")
+        y = torch.empty(c.nnz, dtype=dt, device="cuda")
+        us = timed(lambda: torch.index_select(x, 0, ci, out=y))
+        out[f"gather_{tag}_us"] = us
+        out[f"gather_{tag}_gnnz_per_s"] = c.nnz / (us * 1e-6) / 1e9
+        nbytes = c.nnz * (4 + x.element_size())
+        src = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        us_c = timed(lambda: dst.copy_(src))
+        out[f"stream_copy_{tag}_us"] = us_c
+        out[f"stream_copy_{tag}_bytes"] = nbytes
+        del x, y, src, dst
+    return out
+
+
 def leg_backward(ctx_args):
     """Backward pass at the planted50k size: L = ||P X||_F^2, X seeded n x 8."""
     import torch
@@ -383,7 +435,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--legs", default="",
                     help="comma-separated extra measurements: spmv (streaming SpMV pair on the 4M-vertex "
-                         "Laplacian and the 1M-point coboundary, normal form), backward (planted50k)")
+                         "Laplacian and the 1M-point coboundary, normal form), gather (pure gather and streaming-copy "
+                         "references on the workload's pattern), backward (planted50k)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run the plain copy that scales the rocprofv3 byte counters")
     args = ap.parse_args()
@@ -468,6 +521,9 @@ def main():
                                     for p in ("fp64", "mixed")]
         for r in line["spmv_normal_form"]:
             log(f"spmv {json.dumps(r)}")
+    if "gather" in legs:
+        line["gather_reference"] = leg_gather(args.workload)
+        log(f"gather {json.dumps(line['gather_reference'])}")
     if "backward" in legs:
         line["backward"] = leg_backward({})
         log(f"backward {json.dumps(line['backward'])}")
