@@ -289,6 +289,25 @@ nsp_status nullspace_ritz_eig(nsp_ctx* ctx, int32_t K, int32_t kk, const double*
                               const double* f, const double* alpha, const double* beta,
                               double* evals, double* evecs);
 
+/* The same for block size d (Eq. "defT"):
+ *     T = [diag(theta)  F^T     0        ...]
+ *         [F            Xi_1    Gamma_1^T   ]
+ *         [0            Gamma_1 Xi_2     ...]   (block tridiagonal below)
+ * with K/d - kk/d diagonal blocks Xi_j (symmetric d x d) and the couplings
+ * Gamma_j = T(block j+1, block j) (d x d) between consecutive ones.
+ *  d      1..8, dividing K and kk; kk = 0 or kk <= K - 2d; K <= 4096.
+ *  theta  [kk] ascending; F [d x kk] column-major (ld d);
+ *  xi     [(K-kk)/d blocks of d x d], each column-major, first block first;
+ *  gam    [(K-kk)/d - 1 blocks of d x d] (may be NULL when there is one block);
+ *  evals  [K] out, ascending; evecs [K x K] out, column-major; all device FP64.
+ * The solver tears each coupling by its SVD into d rank-one updates (block
+ * divide and conquer) and treats the kept part as d chained arrowheads.
+ * Runs on the context's stream and synchronises.  Errors: NSP_ERR_ARG,
+ * NSP_ERR_HIP. */
+nsp_status nullspace_ritz_eig_blocks(nsp_ctx* ctx, int32_t K, int32_t d, int32_t kk, const double* theta,
+                                     const double* f, const double* xi, const double* gam, double* evals,
+                                     double* evecs);
+
 /* New values of A for the same sparsity pattern (optimisation loops that
  * change A between solves).  vals [nnz] float64, device, in the caller's CSR
  * order of nullspace_init; copied during the call.  Reuses the locality order,

@@ -91,7 +91,8 @@ class Stats(ctypes.Structure):
 
 
 EXPORTS = ["nsp_default_params", "nullspace_init", "apply_op", "lanczos_run", "nullspace_nullity",
-           "extract_basis", "nullspace_ritz_values", "nullspace_ritz_eig", "backward",
+           "extract_basis", "nullspace_ritz_values", "nullspace_ritz_eig", "nullspace_ritz_eig_blocks",
+           "backward",
            "nullspace_destroy", "nullspace_last_error", "nullspace_locality_order",
            "nullspace_update_values", "nullspace_cycle_times", "nullspace_ritz_residuals",
            "apply_op_noalloc"]
@@ -119,6 +120,7 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.extract_basis.argtypes = [vp, vp, i64]
     lib.nullspace_ritz_values.argtypes = [vp, ctypes.POINTER(dbl), i32, ctypes.POINTER(i32)]
     lib.nullspace_ritz_eig.argtypes = [vp, i32, i32, vp, vp, vp, vp, vp, vp]
+    lib.nullspace_ritz_eig_blocks.argtypes = [vp, i32, i32, i32, vp, vp, vp, vp, vp, vp]
     lib.backward.argtypes = [vp, vp, i64, vp, dbl, i64, ctypes.POINTER(i64)]
     lib.nullspace_destroy.argtypes = [vp]
     lib.nullspace_destroy.restype = None
@@ -129,7 +131,7 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.nullspace_cycle_times.argtypes = [vp, ctypes.POINTER(dbl), i32, ctypes.POINTER(i32)]
     lib.nullspace_ritz_residuals.argtypes = [vp, ctypes.POINTER(dbl), i32, ctypes.POINTER(i32)]
     for name in ("nullspace_init", "apply_op", "apply_op_noalloc", "lanczos_run", "nullspace_nullity", "extract_basis",
-                 "nullspace_ritz_values", "nullspace_ritz_eig", "backward",
+                 "nullspace_ritz_values", "nullspace_ritz_eig", "nullspace_ritz_eig_blocks", "backward",
                  "nullspace_locality_order", "nullspace_update_values", "nullspace_cycle_times",
                  "nullspace_ritz_residuals"):
         getattr(lib, name).restype = ctypes.c_int
@@ -283,6 +285,19 @@ class Context:
         _check(load().nullspace_ritz_eig(self._h, k, kk, _ptr(theta) if kk else None,
                                          _ptr(f) if kk else None, _ptr(alpha), _ptr(beta), _ptr(ev),
                                          _ptr(vec)))
+        return ev, vec.t()
+
+    def ritz_eig_blocks(self, d, theta, f, xi, gam):
+        """Eigenpairs of the restart matrix for block size d.  theta [kk], f (kk x d
+        as the column-major d x kk matrix's transpose), xi and gam as (nblocks, d, d)
+        tensors holding each block transposed (column-major), all device float64."""
+        kk, nbk = int(theta.numel()), int(xi.shape[0])
+        k = kk + nbk * d
+        ev = torch.empty(k, dtype=torch.float64, device="cuda")
+        vec = torch.empty((k, k), dtype=torch.float64, device="cuda")
+        _check(load().nullspace_ritz_eig_blocks(self._h, k, d, kk, _ptr(theta) if kk else None,
+                                                _ptr(f) if kk else None, _ptr(xi),
+                                                _ptr(gam) if nbk > 1 else None, _ptr(ev), _ptr(vec)))
         return ev, vec.t()
 
     def update_values(self, vals: torch.Tensor):

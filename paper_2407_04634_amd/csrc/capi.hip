@@ -69,6 +69,60 @@ void validate_params(const nsp_params* p, int64_t n) {
               "ic_droptol and ic_diagcomp must be finite and >= 0");
 }
 
+
+// Rayleigh-Ritz step on T for testing (d x d blocks, see nullspace.h): a
+// bound on ||T|| from host copies (largest absolute row sum), block-indexed
+// device copies of Xi and Gamma, then the solver's eigensolver.
+void ritz_eig_blocks(nsp_ctx* ctx, int32_t K, int32_t d, int32_t kk, const double* theta, const double* f,
+                     const double* xib, const double* gamb, double* evals, double* evecs) {
+  const int L = K / d, l0 = kk / d, nbk = L - l0;
+  const size_t dd = (size_t)d * d;
+  std::vector<double> ht(kk), hf((size_t)d * kk), hx(nbk * dd), hg(std::max(nbk - 1, 0) * dd);
+  if (kk) {
+    NSP_HIP(hipMemcpy(ht.data(), theta, sizeof(double) * kk, hipMemcpyDeviceToHost));
+    NSP_HIP(hipMemcpy(hf.data(), f, sizeof(double) * d * kk, hipMemcpyDeviceToHost));
+  }
+  NSP_HIP(hipMemcpy(hx.data(), xib, sizeof(double) * hx.size(), hipMemcpyDeviceToHost));
+  if (!hg.empty()) NSP_HIP(hipMemcpy(hg.data(), gamb, sizeof(double) * hg.size(), hipMemcpyDeviceToHost));
+  double bound = 0.0;
+  for (int i = 0; i < kk; ++i) {
+    double r = std::fabs(ht[i]);
+    for (int q = 0; q < d; ++q) r += std::fabs(hf[q + (size_t)i * d]);
+    bound = std::max(bound, r);
+  }
+  for (int j = 0; j < nbk; ++j)
+    for (int r = 0; r < d; ++r) {
+      double sum = 0.0;
+      for (int c2 = 0; c2 < d; ++c2) {
+        sum += std::fabs(hx[j * dd + r + (size_t)c2 * d]);
+        if (j > 0) sum += std::fabs(hg[(j - 1) * dd + r + (size_t)c2 * d]);      // T(blk j, blk j-1)
+        if (j + 1 < nbk) sum += std::fabs(hg[j * dd + c2 + (size_t)r * d]);      // T(blk j, blk j+1)
+      }
+      if (j == 0)
+        for (int i = 0; i < kk; ++i) sum += std::fabs(hf[r + (size_t)i * d]);
+      bound = std::max(bound, sum);
+    }
+  nsp::DBuf xi, gam;
+  xi.alloc(sizeof(double) * (size_t)(L + 2) * dd);
+  gam.alloc(sizeof(double) * (size_t)(L + 2) * dd);
+  NSP_HIP(hipMemsetAsync(xi.p, 0, sizeof(double) * (L + 2) * dd, ctx->stream));
+  NSP_HIP(hipMemsetAsync(gam.p, 0, sizeof(double) * (L + 2) * dd, ctx->stream));
+  NSP_HIP(hipMemcpyAsync(xi.as<double>() + (size_t)(l0 + 1) * dd, xib, sizeof(double) * nbk * dd,
+                         hipMemcpyDeviceToDevice, ctx->stream));
+  if (nbk > 1)
+    NSP_HIP(hipMemcpyAsync(gam.as<double>() + (size_t)(l0 + 1) * dd, gamb, sizeof(double) * (nbk - 1) * dd,
+                           hipMemcpyDeviceToDevice, ctx->stream));
+  nsp::EigWork* w = nsp::eig_work_new();
+  try {
+    nsp::eig_restart(ctx, *w, K, d, kk, bound, theta, f, xi.as<double>(), gam.as<double>(), evals, evecs);
+    NSP_HIP(hipStreamSynchronize(ctx->stream));
+  } catch (...) {
+    nsp::eig_work_delete(w);
+    throw;
+  }
+  nsp::eig_work_delete(w);
+}
+
 }  // namespace
 
 extern "C" {
@@ -242,6 +296,7 @@ nsp_status nullspace_cycle_times(nsp_ctx* ctx, double* seconds, int32_t cap, int
   });
 }
 
+
 nsp_status nullspace_ritz_eig(nsp_ctx* ctx, int32_t K, int32_t kk, const double* theta,
                               const double* f, const double* alpha, const double* beta,
                               double* evals, double* evecs) {
@@ -250,48 +305,24 @@ nsp_status nullspace_ritz_eig(nsp_ctx* ctx, int32_t K, int32_t kk, const double*
     NSP_REQUIRE(K >= 2 && kk >= 0 && kk <= K - 2, "need K >= 2 and 0 <= kk <= K-2");
     NSP_REQUIRE(alpha && beta && evals && evecs && (kk == 0 || (theta && f)), "NULL argument");
     enter(ctx);
-    const int m = K - kk;
-    // host copies give a bound on ||T|| (largest absolute row sum)
-    std::vector<double> ht(kk), hf(kk), ha(m), hb(m - 1);
-    if (kk) {
-      NSP_HIP(hipMemcpy(ht.data(), theta, sizeof(double) * kk, hipMemcpyDeviceToHost));
-      NSP_HIP(hipMemcpy(hf.data(), f, sizeof(double) * kk, hipMemcpyDeviceToHost));
-    }
-    NSP_HIP(hipMemcpy(ha.data(), alpha, sizeof(double) * m, hipMemcpyDeviceToHost));
-    if (m > 1) NSP_HIP(hipMemcpy(hb.data(), beta, sizeof(double) * (m - 1), hipMemcpyDeviceToHost));
-    double bound = 0.0, tip = std::fabs(ha[0]) + (m > 1 ? std::fabs(hb[0]) : 0.0);
-    for (int i = 0; i < kk; ++i) {
-      bound = std::max(bound, std::fabs(ht[i]) + std::fabs(hf[i]));
-      tip += std::fabs(hf[i]);
-    }
-    bound = std::max(bound, tip);
-    for (int i = 1; i < m; ++i)
-      bound = std::max(bound, std::fabs(ha[i]) + std::fabs(hb[i - 1]) + (i + 1 < m ? std::fabs(hb[i]) : 0.0));
-    // block-indexed copies: xi[kk+1+i] = alpha[i], gam[kk+1+i] = beta[i]
-    nsp::DBuf xi, gam, info;
-    xi.alloc(sizeof(double) * (K + 2));
-    gam.alloc(sizeof(double) * (K + 2));
-    info.alloc(sizeof(int) * 4);
-    NSP_HIP(hipMemsetAsync(xi.p, 0, sizeof(double) * (K + 2), ctx->stream));
-    NSP_HIP(hipMemsetAsync(gam.p, 0, sizeof(double) * (K + 2), ctx->stream));
-    NSP_HIP(hipMemsetAsync(info.p, 0, sizeof(int) * 4, ctx->stream));
-    NSP_HIP(hipMemcpyAsync(xi.as<double>() + kk + 1, alpha, sizeof(double) * m, hipMemcpyDeviceToDevice,
-                           ctx->stream));
-    if (m > 1)
-      NSP_HIP(hipMemcpyAsync(gam.as<double>() + kk + 1, beta, sizeof(double) * (m - 1),
-                             hipMemcpyDeviceToDevice, ctx->stream));
-    nsp::EigWork* w = nsp::eig_work_new();
-    try {
-      nsp::eig_restart_d1(ctx, *w, K, kk, bound, theta, f, xi.as<double>(), gam.as<double>(), evals,
-                          evecs, info.as<int>());
-      NSP_HIP(hipMemcpyAsync(ctx->pin_i, info.p, sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
-      NSP_HIP(hipStreamSynchronize(ctx->stream));
-    } catch (...) {
-      nsp::eig_work_delete(w);
-      throw;
-    }
-    nsp::eig_work_delete(w);
-    if (ctx->pin_i[0] != 0) throw nsp::Error(NSP_ERR_HIP, "tridiagonal eigensolver failed");
+    ritz_eig_blocks(ctx, K, 1, kk, theta, f, alpha, beta, evals, evecs);
+    leave(ctx);
+  });
+}
+
+nsp_status nullspace_ritz_eig_blocks(nsp_ctx* ctx, int32_t K, int32_t d, int32_t kk, const double* theta,
+                                     const double* f, const double* xi, const double* gam, double* evals,
+                                     double* evecs) {
+  return guarded([&] {
+    NSP_REQUIRE(ctx != nullptr, "ctx must not be NULL");
+    NSP_REQUIRE(d >= 1 && d <= nsp::kMaxD, "d must be in [1, 8]");
+    NSP_REQUIRE(K >= d && K % d == 0 && kk % d == 0 && kk >= 0 && (kk == 0 || kk <= K - 2 * d),
+                "need K a multiple of d, kk a multiple of d, and kk = 0 or kk <= K - 2d");
+    NSP_REQUIRE(K <= 4096, "K must not exceed 4096");
+    NSP_REQUIRE(xi && evals && evecs && (K / d - kk / d < 2 || gam) && (kk == 0 || (theta && f)),
+                "NULL argument");
+    enter(ctx);
+    ritz_eig_blocks(ctx, K, d, kk, theta, f, xi, gam, evals, evecs);
     leave(ctx);
   });
 }

@@ -1,23 +1,33 @@
-// Eigen-decomposition of the restart matrix T (Eq. "defT") for block size 1.
+// Eigen-decomposition of the restart matrix T (Eq. "defT") for block size d.
 //
-// After a thick restart T = [diag(theta) f 0; f^T a1 b1 ...; 0 tridiagonal tail]:
-// kk kept Ritz values theta (ascending) bordered by the coupling row f, the
-// arrow tip a1 = Xi_{l0+1}, and a tridiagonal tail.  Cuppen's tear at the
-// coupling b1 = Gamma_{l0+1} between the tip and the tail writes
-//     T = diag(M1 - b1 e_tip e_tip^T, T2 - b1 e_0 e_0^T) + b1 v v^T,
-// v = e_tip + e_{kk+1}.  M1 is an arrowhead ("bordered diagonal") matrix whose
-// eigenvalues are the roots of the secular equation
-//     a - l - sum_i f_i^2 / (theta_i - l) = 0,
-// the tail is tridiagonal (rocSOLVER's divide and conquer), and the rank-one
-// merge solves 1 + b1 sum_i z_i^2 / (d_i - l) = 0.  Both secular problems use
-// deflation of negligible couplings and of (nearly) equal poles by Givens
-// rotations, roots found by bisection on a shifted variable (l = pole + tau,
-// so differences l - pole keep full relative accuracy), and Loewner-formula
-// weights (Gu & Eisenstat) so that the computed eigenvectors are orthogonal to
-// working precision.  The first cycle (no kept vectors) has a plain
-// tridiagonal T and goes to the tridiagonal solver directly.
+// After a thick restart
+//     T = [diag(theta)  F^T   0            ]   kk kept Ritz values theta
+//         [F            Xi_1  Gamma_1^T    ]   (ascending), their coupling F
+//         [0            Gamma_1  Xi_2  ... ]   (d x kk) to the first new block,
+//                                              then the block tridiagonal tail
+// (Xi_j symmetric d x d on the diagonal, Gamma_j upper triangular below it);
+// the first cycle (kk = 0) has the block tridiagonal part only.  Divide and
+// conquer in the manner of Cuppen, for d x d blocks:
+//  * a coupling Gamma = P S Q^T (SVD) between consecutive blocks is torn:
+//        [0 Gamma^T; Gamma 0] = sum_i s_i v_i v_i^T - diag(Q S Q^T, P S P^T),
+//    v_i = [q_i; p_i], so the upper block loses Q S Q^T, the lower one
+//    P S P^T, and the two halves are joined again by d rank-one updates;
+//  * the tail is torn down to its d x d blocks (Jacobi), padded to a power of
+//    two with decoupled blocks above every eigenvalue of T, and merged level
+//    by level, all merges of a level in one batch;
+//  * the kept part with its d-row border is a block arrowhead, solved as d
+//    successive arrowheads [diag(lambda) z; z^T x] (one secular equation
+//    each, z the next border row in the current eigenbasis);
+//  * arrowhead and tail are joined by the d rank-one updates of the tear at
+//    the coupling between them.
+// Every secular problem uses deflation of negligible couplings and of
+// (nearly) equal poles by Givens rotations, roots found by bisection in a
+// shifted variable (lambda = pole + tau, so differences lambda - pole keep
+// full relative accuracy), and Loewner-formula weights (Gu & Eisenstat) so
+// that the computed eigenvectors are orthogonal to working precision.
 #include <algorithm>
 #include <cmath>
+#include <vector>
 
 #include "common.h"
 #include "kernels.h"
@@ -27,10 +37,13 @@ namespace nsp {
 namespace {
 
 constexpr double kU = 1.1102230246251565e-16;  // 2^-53, rounding unit for the deflation tolerance
+constexpr int kLdsBytes = 64 * 1024;            // dynamic LDS the secular kernels may stage into
 
 inline unsigned nb(int64_t work, int per) { return (unsigned)((work + per - 1) / per); }
 
-// Secular problem descriptor (device arrays, counts on the device).
+// Secular problem descriptor (device arrays, counts on the device).  A batch of
+// problems shares one descriptor: problem b uses every array at offset b * S
+// (the counts at offset 4 b).
 struct Sec {
   int* cnt;       // [0] n' non-deflated poles, [1] number of rotations, [2] number deflated
   double* p;      // poles (ascending, distinct), n'
@@ -40,39 +53,74 @@ struct Sec {
   int* rot_j;
   double* rot_c;
   double* rot_s;
-  double* dval;   // deflated eigenvalues (ascending by recording order of indices)
+  double* dval;   // deflated eigenvalues
   int* didx;      // their row index
   int* ro;        // root origin pole index
   double* rt;     // root shift tau
   double* what;   // Loewner weights (signed square roots)
 };
 
+__device__ __forceinline__ Sec sec_at(const Sec& s, int b, int S) {
+  const int64_t o = (int64_t)b * S;
+  Sec r;
+  r.cnt = s.cnt + 4 * b;
+  r.p = s.p + o;
+  r.w = s.w + o;
+  r.idx = s.idx + o;
+  r.rot_i = s.rot_i + o;
+  r.rot_j = s.rot_j + o;
+  r.rot_c = s.rot_c + o;
+  r.rot_s = s.rot_s + o;
+  r.dval = s.dval + o;
+  r.didx = s.didx + o;
+  r.ro = s.ro + o;
+  r.rt = s.rt + o;
+  r.what = s.what + o;
+  return r;
+}
+
 // -------------------------------------------------------------------------
-// deflation (one thread; sequential over the sorted poles)
-//   ARROW: rows 0..m-2 are the poles (value val[i], coupling cpl[i]),
-//          row m-1 is the arrow tip; weight = cpl^2.
+// deflation (one block per problem: the poles and couplings are staged in LDS,
+// then one thread scans them in order)
+//   ARROW: rows 0..m-1 are the poles (value val[i], coupling cpl[i]); the
+//          arrow tip is row m; weight = cpl^2.
 //   RANK1: rows 0..m-1 are the poles (val[i] sorted ascending), coupling
 //          cpl[i]; weight = cpl^2 (rho applied in the root finder).
+// val of problem b at val + b vstride; coupling i at cpl[b cstride + i cinc].
 // -------------------------------------------------------------------------
-__global__ void k_deflate(int npoles, const double* __restrict__ val, const double* __restrict__ cpl,
-                          const double* cscale_ptr, double scale, Sec s) {
-  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+template <bool LDS>
+__global__ __launch_bounds__(256) void k_deflate(int npoles, const double* __restrict__ val, int64_t vstride,
+                                                 const double* __restrict__ cpl, int cinc, int64_t cstride,
+                                                 const double* __restrict__ rho, double scale, Sec s0, int S) {
+  extern __shared__ double sh[];
+  const int b = blockIdx.x;
+  const Sec s = sec_at(s0, b, S);
+  const double* v = val + (int64_t)b * vstride;
+  const double* cp = cpl + (int64_t)b * cstride;
+  if (LDS) {
+    for (int i = threadIdx.x; i < npoles; i += blockDim.x) {
+      sh[i] = v[i];
+      sh[npoles + i] = cp[(int64_t)i * cinc];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x != 0) return;
   const double tol = 8.0 * kU * scale;
-  // a coupling is negligible when its contribution (times rho for the merge) is below tol
-  const double cscale = cscale_ptr ? fabs(*cscale_ptr) : 1.0;
+  // a coupling is negligible when its contribution (times rho for a merge) is below tol
+  const double cscale = rho ? fabs(rho[b]) : 1.0;
   int np = 0, nr = 0, nd = 0;
   int last = -1;         // row index of the last kept pole
   double last_f = 0.0;   // its (rotated) coupling
   double last_v = 0.0;
   for (int i = 0; i < npoles; ++i) {
-    const double v = val[i];
-    double fi = cpl[i];
+    const double vi = LDS ? sh[i] : v[i];
+    double fi = LDS ? sh[npoles + i] : cp[(int64_t)i * cinc];
     if (fabs(fi) * cscale <= tol) {
-      s.dval[nd] = v;
+      s.dval[nd] = vi;
       s.didx[nd++] = i;
       continue;
     }
-    if (last >= 0 && v - last_v <= tol) {
+    if (last >= 0 && vi - last_v <= tol) {
       // rotate (last, i) so that the coupling of ``last`` vanishes; ``last`` deflates
       const double r = hypot(last_f, fi);
       const double c = fi / r, sn = last_f / r;
@@ -85,7 +133,7 @@ __global__ void k_deflate(int npoles, const double* __restrict__ val, const doub
       --np;  // drop ``last`` from the kept poles
       fi = r;
     }
-    s.p[np] = v;
+    s.p[np] = vi;
     s.w[np] = fi * fi;
     s.idx[np] = i;
     // the coupling sign is needed for the eigenvector signs: keep it in what
@@ -93,7 +141,7 @@ __global__ void k_deflate(int npoles, const double* __restrict__ val, const doub
     ++np;
     last = i;
     last_f = fi;
-    last_v = v;
+    last_v = vi;
   }
   s.cnt[0] = np;
   s.cnt[1] = nr;
@@ -109,34 +157,49 @@ __device__ __forceinline__ double wave_sum64(double v) {
 }
 
 template <bool ARROW>
-__device__ double sec_eval(int np, const double* p, const double* w, int o, double tau, double a_or_rho) {
+__device__ double sec_eval(int np, const double* p, const double* w, int o, double tau, double a_or_rho,
+                           int lane) {
   const double po = p[o];
   double s = 0.0;
-  for (int i = threadIdx.x; i < np; i += 64) s += w[i] / ((p[i] - po) - tau);
+  for (int i = lane; i < np; i += 64) s += w[i] / ((p[i] - po) - tau);
   s = wave_sum64(s);
   if (ARROW) return (a_or_rho - po) - tau - s;  // decreasing in tau
   return 1.0 + a_or_rho * s;                    // increasing in tau (rho > 0)
 }
 
 // roots: ARROW has n'+1 roots (one below p0, one per gap, one above), RANK1 has
-// n'; one 64-lane block per root
-template <bool ARROW>
-__global__ __launch_bounds__(64) void k_roots(Sec s, const double* a_or_rho_ptr, double lo_bound,
-                                              double hi_bound) {
+// n'; one wavefront per root, four per block (grid.y = problem), the poles and
+// weights staged in LDS when they fit.  a_or_rho: tip or rho per problem.
+template <bool ARROW, bool LDS>
+__global__ __launch_bounds__(256) void k_roots(Sec s0, int S, const double* __restrict__ a_or_rho,
+                                               double lo_bound, double hi_bound) {
+  extern __shared__ double sh[];
+  const int b = blockIdx.y;
+  const Sec s = sec_at(s0, b, S);
   const int np = s.cnt[0];
+  const double* p = s.p;
+  const double* w = s.w;
+  if (LDS) {
+    for (int i = threadIdx.x; i < np; i += blockDim.x) {
+      sh[i] = s.p[i];
+      sh[np + i] = s.w[i];
+    }
+    __syncthreads();
+    p = sh;
+    w = sh + np;
+  }
   const int nroots = ARROW ? np + 1 : np;
-  const int j = blockIdx.x;
+  const int lane = threadIdx.x & 63;
+  const int j = blockIdx.x * 4 + (threadIdx.x >> 6);
   if (j >= nroots) return;
-  const double ar = *a_or_rho_ptr;
+  const double ar = a_or_rho[b];
   if (ARROW && np == 0) {  // every coupling deflated: the tip is an eigenvalue
-    if (threadIdx.x == 0) {
+    if (lane == 0) {
       s.ro[0] = -1;
       s.rt[0] = ar;
     }
     return;
   }
-  const double* p = s.p;
-  const double* w = s.w;
   int o;
   double lo, hi;
   if (ARROW) {
@@ -146,19 +209,19 @@ __global__ __launch_bounds__(64) void k_roots(Sec s, const double* a_or_rho_ptr,
       o = np - 1; lo = 0.0; hi = hi_bound - p[np - 1];
     } else {
       const double h = p[j] - p[j - 1];
-      const double gm = sec_eval<true>(np, p, w, j - 1, 0.5 * h, ar);
+      const double gm = sec_eval<true>(np, p, w, j - 1, 0.5 * h, ar, lane);
       if (gm > 0.0) { o = j; lo = -0.5 * h; hi = 0.0; }       // root in the right half
       else { o = j - 1; lo = 0.0; hi = 0.5 * h; }
     }
   } else {
     if (j == np - 1) {
       double sw = 0.0;
-      for (int i = threadIdx.x; i < np; i += 64) sw += w[i];
+      for (int i = lane; i < np; i += 64) sw += w[i];
       sw = wave_sum64(sw);
       o = np - 1; lo = 0.0; hi = ar * sw;
     } else {
       const double h = p[j + 1] - p[j];
-      const double fm = sec_eval<false>(np, p, w, j, 0.5 * h, ar);
+      const double fm = sec_eval<false>(np, p, w, j, 0.5 * h, ar, lane);
       if (fm > 0.0) { o = j; lo = 0.0; hi = 0.5 * h; }         // root in the left half
       else { o = j + 1; lo = -0.5 * h; hi = 0.0; }
     }
@@ -167,11 +230,11 @@ __global__ __launch_bounds__(64) void k_roots(Sec s, const double* a_or_rho_ptr,
   for (int it = 0; it < 200; ++it) {
     const double mid = 0.5 * (lo + hi);
     if (mid <= lo || mid >= hi) break;
-    const double g = sec_eval<ARROW>(np, p, w, o, mid, ar);
+    const double g = sec_eval<ARROW>(np, p, w, o, mid, ar, lane);
     const bool right = ARROW ? (g > 0.0) : (g < 0.0);
     if (right) lo = mid; else hi = mid;
   }
-  if (threadIdx.x == 0) {
+  if (lane == 0) {
     s.ro[j] = o;
     s.rt[j] = 0.5 * (lo + hi);
   }
@@ -188,37 +251,109 @@ __device__ __forceinline__ double root_val(const Sec& s, int k) {
 
 // Loewner weights: signed square roots of the weights for which the computed
 // roots are exact eigenvalues (pairing the factors keeps every ratio bounded).
+// One wavefront per pole: the lanes share the product over k.
 template <bool ARROW>
-__global__ void k_lowner(Sec s, const double* a_or_rho_ptr) {
+__global__ __launch_bounds__(256) void k_lowner(Sec s0, int S, const double* __restrict__ a_or_rho) {
+  const int b = blockIdx.y;
+  const Sec s = sec_at(s0, b, S);
   const int np = s.cnt[0];
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int lane = threadIdx.x & 63;
+  const int i = blockIdx.x * 4 + (threadIdx.x >> 6);
   if (i >= np) return;
   const double* p = s.p;
-  double prod;
-  if (ARROW) {
-    // f_i^2 = -(p_i - l_i)(p_i - l_{i+1}) prod_{k<i} (p_i - l_k)/(p_i - p_k)
-    //                                      prod_{k>i} (p_i - l_{k+1})/(p_i - p_k)
-    prod = lam_minus(s, i, i) * lam_minus(s, i + 1, i);  // (l_i - p_i)(l_{i+1} - p_i) < 0
-    prod = -prod;
-    for (int k = 0; k < i; ++k) prod *= (-lam_minus(s, k, i)) / (p[i] - p[k]);
-    for (int k = i + 1; k < np; ++k) prod *= (-lam_minus(s, k + 1, i)) / (p[i] - p[k]);
-  } else {
-    // z_i^2 = -(1/rho)(d_i - l_{n-1}) prod_{k<i} (d_i - l_k)/(d_i - d_k)
-    //                                 prod_{k>i} (d_i - l_{k-1})/(d_i - d_k)
-    const double rho = *a_or_rho_ptr;
-    prod = lam_minus(s, np - 1, i) / rho;  // (l_{n-1} - d_i)/rho > 0
-    for (int k = 0; k < i; ++k) prod *= (-lam_minus(s, k, i)) / (p[i] - p[k]);
-    for (int k = i + 1; k < np; ++k) prod *= (-lam_minus(s, k - 1, i)) / (p[i] - p[k]);
+  const double pi = p[i];
+  // ARROW: f_i^2 = -(p_i - l_i)(p_i - l_{i+1}) prod_{k<i} (p_i - l_k)/(p_i - p_k)
+  //                                            prod_{k>i} (p_i - l_{k+1})/(p_i - p_k)
+  // RANK1: z_i^2 = -(1/rho)(d_i - l_{n-1}) prod_{k<i} (d_i - l_k)/(d_i - d_k)
+  //                                       prod_{k>i} (d_i - l_{k-1})/(d_i - d_k)
+  double prod = 1.0;
+  for (int k = lane; k < np; k += 64) {
+    if (k < i) prod *= (-lam_minus(s, k, i)) / (pi - p[k]);
+    else if (k > i) prod *= (-lam_minus(s, ARROW ? k + 1 : k - 1, i)) / (pi - p[k]);
   }
-  const double sign = s.what[i] < 0.0 ? -1.0 : 1.0;
-  s.what[i] = sign * sqrt(fmax(prod, 0.0));
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) prod *= __shfl_xor(prod, off, 64);
+  if (lane == 0) {
+    const double lead = ARROW ? -(lam_minus(s, i, i) * lam_minus(s, i + 1, i))  // (l_i - p_i)(l_{i+1} - p_i) < 0
+                              : lam_minus(s, np - 1, i) / a_or_rho[b];          // (l_{n-1} - d_i)/rho > 0
+    const double sign = s.what[i] < 0.0 ? -1.0 : 1.0;
+    s.what[i] = sign * sqrt(fmax(lead * prod, 0.0));
+  }
 }
 
-// Eigenvector of root j (one block per root), written as column j of X
-// (ldx rows, row index space of the problem).  ARROW: entries at the pole
-// rows and 1 at the tip row; RANK1: entries at the pole rows.
+// Ascending order of the eigenvalues: the secular roots (ascending by
+// construction) and the deflated values.  The deflated list is sorted first
+// (insertion sort in LDS by one thread: it is nearly sorted), then every
+// value finds its position by binary search in the other list (roots first on
+// ties).  Writes lam[position] and pos[source] = position, source = root r or
+// nroots + q for the q-th deflated value.
 template <bool ARROW>
-__global__ void k_vectors(Sec s, double* x, int ldx, int tip_row) {
+__global__ __launch_bounds__(256) void k_order(Sec s0, int S, double* __restrict__ lam, int64_t lstride,
+                                               int* __restrict__ pos, int64_t pstride) {
+  extern __shared__ double sh[];
+  const int b = blockIdx.x;
+  const Sec s = sec_at(s0, b, S);
+  const int np = s.cnt[0], nd = s.cnt[2];
+  const int nroots = ARROW ? np + 1 : np;
+  double* dv = sh;
+  int* di = reinterpret_cast<int*>(sh + nd);
+  for (int q = threadIdx.x; q < nd; q += blockDim.x) {
+    dv[q] = s.dval[q];
+    di[q] = s.didx[q];
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int a = 1; a < nd; ++a) {
+      const double v = dv[a];
+      const int id = di[a];
+      int c = a - 1;
+      while (c >= 0 && dv[c] > v) {
+        dv[c + 1] = dv[c];
+        di[c + 1] = di[c];
+        --c;
+      }
+      dv[c + 1] = v;
+      di[c + 1] = id;
+    }
+  }
+  __syncthreads();
+  double* lb = lam + (int64_t)b * lstride;
+  int* pb = pos + (int64_t)b * pstride;
+  for (int q = threadIdx.x; q < nd; q += blockDim.x) {
+    s.dval[q] = dv[q];
+    s.didx[q] = di[q];
+  }
+  for (int r = threadIdx.x; r < nroots; r += blockDim.x) {
+    const double v = root_val(s, r);
+    int lo = 0, hi = nd;  // number of deflated values < v
+    while (lo < hi) {
+      const int mid = (lo + hi) >> 1;
+      if (dv[mid] < v) lo = mid + 1; else hi = mid;
+    }
+    lb[r + lo] = v;
+    pb[r] = r + lo;
+  }
+  for (int q = threadIdx.x; q < nd; q += blockDim.x) {
+    const double v = dv[q];
+    int lo = 0, hi = nroots;  // number of roots <= v
+    while (lo < hi) {
+      const int mid = (lo + hi) >> 1;
+      if (root_val(s, mid) <= v) lo = mid + 1; else hi = mid;
+    }
+    lb[q + lo] = v;
+    pb[nroots + q] = q + lo;
+  }
+}
+
+// Eigenvector of root j (one block per root, grid.y = problem), written as
+// column pos[j] of X (ldx rows, row index space of the problem).  ARROW:
+// entries at the pole rows and 1 at the tip row; RANK1: entries at the pole
+// rows.  X must be zero beforehand.
+template <bool ARROW>
+__global__ __launch_bounds__(256) void k_vectors(Sec s0, int S, const int* __restrict__ pos, int64_t pstride,
+                                                 double* __restrict__ x, int64_t xstride, int ldx, int tip_row) {
+  const int b = blockIdx.y;
+  const Sec s = sec_at(s0, b, S);
   const int np = s.cnt[0];
   const int nroots = ARROW ? np + 1 : np;
   const int j = blockIdx.x;
@@ -237,7 +372,7 @@ __global__ void k_vectors(Sec s, double* x, int ldx, int tip_row) {
     __syncthreads();
   }
   const double nrm = sqrt(red[0] + (ARROW ? 1.0 : 0.0));
-  double* col = x + (int64_t)j * ldx;
+  double* col = x + (int64_t)b * xstride + (int64_t)pos[(int64_t)b * pstride + j] * ldx;
   for (int i = threadIdx.x; i < np; i += blockDim.x) {
     const double den = ARROW ? lam_minus(s, j, i) : -lam_minus(s, j, i);
     col[s.idx[i]] = s.what[i] / den / nrm;
@@ -245,123 +380,334 @@ __global__ void k_vectors(Sec s, double* x, int ldx, int tip_row) {
   if (ARROW && threadIdx.x == 0) col[tip_row] = 1.0 / nrm;
 }
 
-// deflated columns: unit vectors at their rows, in the last nd of the m
-// columns (the secular roots fill the first m - nd)
-__global__ void k_deflated_cols(Sec s, double* x, int ldx, int m) {
+// deflated columns: unit vectors at their rows, in their ordered columns
+template <bool ARROW>
+__global__ void k_deflated_cols(Sec s0, int S, const int* __restrict__ pos, int64_t pstride,
+                                double* __restrict__ x, int64_t xstride, int ldx) {
+  const int b = blockIdx.y;
+  const Sec s = sec_at(s0, b, S);
   const int nd = s.cnt[2];
+  const int nroots = ARROW ? s.cnt[0] + 1 : s.cnt[0];
   const int q = blockIdx.x * blockDim.x + threadIdx.x;
   if (q >= nd) return;
-  x[(int64_t)(m - nd + q) * ldx + s.didx[q]] = 1.0;
+  x[(int64_t)b * xstride + (int64_t)pos[(int64_t)b * pstride + nroots + q] * ldx + s.didx[q]] = 1.0;
 }
 
 // undo the deflation rotations on the rows of X (latest first), all columns
-__global__ void k_unrotate(Sec s, double* x, int ldx, int ncols) {
+__global__ void k_unrotate(Sec s0, int S, double* __restrict__ x, int64_t xstride, int ldx, int ncols) {
+  const int b = blockIdx.x;
+  const Sec s = sec_at(s0, b, S);
   const int nr = s.cnt[1];
+  double* xb = x + (int64_t)b * xstride;
   for (int r = nr - 1; r >= 0; --r) {
     const int pi = s.rot_i[r], pj = s.rot_j[r];
     const double c = s.rot_c[r], sn = s.rot_s[r];
     for (int col = threadIdx.x; col < ncols; col += blockDim.x) {
-      double* xc = x + (int64_t)col * ldx;
-      const double a = xc[pi], b = xc[pj];
-      xc[pi] = c * a + sn * b;
-      xc[pj] = -sn * a + c * b;
+      double* xc = xb + (int64_t)col * ldx;
+      const double a = xc[pi], bb = xc[pj];
+      xc[pi] = c * a + sn * bb;
+      xc[pj] = -sn * a + c * bb;
     }
     __syncthreads();
   }
 }
 
-// ascending (value, column) list from the secular roots (columns 0..nroots-1)
-// and the deflated values (columns nroots..), merging two sorted sequences;
-// the deflated values are first sorted by insertion (few, nearly sorted)
-template <bool ARROW>
-__global__ void k_order(Sec s, double* lam, int* col) {
-  if (threadIdx.x != 0 || blockIdx.x != 0) return;
-  const int np = s.cnt[0], nd = s.cnt[2];
-  const int nroots = ARROW ? np + 1 : np;
-  // insertion sort of the deflated list (stable, by value) carrying the index
-  for (int a = 1; a < nd; ++a) {
-    const double v = s.dval[a];
-    const int id = s.didx[a];
-    int b = a - 1;
-    while (b >= 0 && s.dval[b] > v) {
-      s.dval[b + 1] = s.dval[b];
-      s.didx[b + 1] = s.didx[b];
-      --b;
-    }
-    s.dval[b + 1] = v;
-    s.didx[b + 1] = id;
+// -------------------------------------------------------------------------
+// tears, leaves, merges
+// -------------------------------------------------------------------------
+
+// SVD of a d x d matrix g (column-major) by one-sided Jacobi: g = P S Q^T.
+// Columns of P with s = 0 are returned as zero (their rank-one update has
+// rho = 0 and deflates whatever its coupling).
+__device__ void svd_small(int d, const double* g, double* pm, double* sv, double* qm) {
+  double a[kMaxD * kMaxD], v[kMaxD * kMaxD];
+  for (int i = 0; i < d * d; ++i) a[i] = g[i];
+  for (int c = 0; c < d; ++c)
+    for (int r = 0; r < d; ++r) v[r + c * d] = r == c ? 1.0 : 0.0;
+  for (int sweep = 0; sweep < 40; ++sweep) {
+    bool rotated = false;
+    for (int k = 0; k < d - 1; ++k)
+      for (int l = k + 1; l < d; ++l) {
+        double al = 0.0, be = 0.0, ga = 0.0;
+        for (int r = 0; r < d; ++r) {
+          al += a[r + k * d] * a[r + k * d];
+          be += a[r + l * d] * a[r + l * d];
+          ga += a[r + k * d] * a[r + l * d];
+        }
+        if (fabs(ga) <= 1e-17 * sqrt(al * be) || ga == 0.0) continue;
+        rotated = true;
+        const double ze = (be - al) / (2.0 * ga);
+        const double t = (ze >= 0.0 ? 1.0 : -1.0) / (fabs(ze) + sqrt(1.0 + ze * ze));
+        const double c = 1.0 / sqrt(1.0 + t * t), sn = c * t;
+        for (int r = 0; r < d; ++r) {
+          const double x = a[r + k * d], y = a[r + l * d];
+          a[r + k * d] = c * x - sn * y;
+          a[r + l * d] = sn * x + c * y;
+          const double vx = v[r + k * d], vy = v[r + l * d];
+          v[r + k * d] = c * vx - sn * vy;
+          v[r + l * d] = sn * vx + c * vy;
+        }
+      }
+    if (!rotated) break;
   }
-  int r = 0, q = 0, k = 0;
-  while (r < nroots || q < nd) {
-    const double lr = r < nroots ? root_val(s, r) : INFINITY;
-    const double lq = q < nd ? s.dval[q] : INFINITY;
-    if (lr <= lq) { lam[k] = lr; col[k++] = r++; }
-    else { lam[k] = lq; col[k++] = nroots + q++; }
-  }
-}
-
-// tail tridiagonal (d = 1): diag a_{l0+2..L} (first reduced by b), offdiag b_{l0+2..L-1}
-__global__ void k_tail(int m2, const double* __restrict__ xi, const double* __restrict__ gam,
-                       int first_blk, double* __restrict__ dd, double* __restrict__ ee) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= m2) return;
-  const double b = gam[first_blk - 1];  // Gamma_{l0+1}: coupling to the arrow tip
-  dd[i] = xi[first_blk + i] - (i == 0 ? b : 0.0);
-  if (i + 1 < m2) ee[i] = gam[first_blk + i];
-}
-
-// full tridiagonal (first cycle): diag a_1..a_L, offdiag b_1..b_{L-1}
-__global__ void k_tridiag(int L, const double* __restrict__ xi, const double* __restrict__ gam,
-                          double* __restrict__ dd, double* __restrict__ ee) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= L) return;
-  dd[i] = xi[1 + i];
-  if (i + 1 < L) ee[i] = gam[1 + i];
-}
-
-// arrow data: poles theta (kk), couplings f (kk), tip a1 - b1, scale
-__global__ void k_arrow_tip(const double* __restrict__ xi, const double* __restrict__ gam, int blk,
-                            double* tip) {
-  if (threadIdx.x == 0 && blockIdx.x == 0) tip[0] = xi[blk] - gam[blk];  // a1 - b1
-}
-
-// the merge problem: union of the arrow eigenvalues (lam1/col1 over U1) and the
-// tail eigenvalues (ascending, columns of U2); couplings z = U1[tip, col] and
-// U2[0, col]; src[k] = column in U1 (>= 0) or -(1 + column in U2)
-__global__ void k_merge_union(int m1, int m2, const double* __restrict__ lam1,
-                              const int* __restrict__ col1, const double* __restrict__ u1,
-                              const double* __restrict__ lam2, const double* __restrict__ u2,
-                              double* __restrict__ d, double* __restrict__ z, int* __restrict__ src) {
-  if (threadIdx.x != 0 || blockIdx.x != 0) return;
-  int a = 0, b = 0, k = 0;
-  while (a < m1 || b < m2) {
-    const double va = a < m1 ? lam1[a] : INFINITY;
-    const double vb = b < m2 ? lam2[b] : INFINITY;
-    if (va <= vb) {
-      d[k] = va;
-      z[k] = u1[(int64_t)col1[a] * m1 + (m1 - 1)];
-      src[k++] = col1[a++];
-    } else {
-      d[k] = vb;
-      z[k] = u2[(int64_t)b * m2];
-      src[k++] = -(1 + b++);
+  for (int k = 0; k < d; ++k) {
+    double nr = 0.0;
+    for (int r = 0; r < d; ++r) nr += a[r + k * d] * a[r + k * d];
+    nr = sqrt(nr);
+    sv[k] = nr;
+    for (int r = 0; r < d; ++r) {
+      pm[r + k * d] = nr > 0.0 ? a[r + k * d] / nr : 0.0;
+      qm[r + k * d] = v[r + k * d];
     }
   }
 }
 
-// scatter the merge eigenvectors (rows = union index, natural column order) to
-// Wa (m1 x K, rows = U1 columns) and Wt (m2 x K, rows = U2 columns), columns in
-// final ascending order
-__global__ void k_scatter(int K, int m1, int m2, const double* __restrict__ wn,
-                          const int* __restrict__ src, const int* __restrict__ colf,
-                          double* __restrict__ wa, double* __restrict__ wt) {
+// Eigen-decomposition of a symmetric d x d matrix (cyclic Jacobi), eigenvalues
+// ascending with their vectors.
+__device__ void eig_small(int d, double* a, double* lam, double* u) {
+  double v[kMaxD * kMaxD];
+  for (int c = 0; c < d; ++c)
+    for (int r = 0; r < d; ++r) v[r + c * d] = r == c ? 1.0 : 0.0;
+  for (int sweep = 0; sweep < 50; ++sweep) {
+    double off = 0.0, tot = 0.0;
+    for (int c = 0; c < d; ++c)
+      for (int r = 0; r < d; ++r) {
+        tot += a[r + c * d] * a[r + c * d];
+        if (r != c) off += a[r + c * d] * a[r + c * d];
+      }
+    if (off <= 1e-34 * tot || off == 0.0) break;
+    for (int k = 0; k < d - 1; ++k)
+      for (int l = k + 1; l < d; ++l) {
+        const double akl = a[k + l * d];
+        if (akl == 0.0) continue;
+        const double th = (a[l + l * d] - a[k + k * d]) / (2.0 * akl);
+        const double t = (th >= 0.0 ? 1.0 : -1.0) / (fabs(th) + sqrt(1.0 + th * th));
+        const double c = 1.0 / sqrt(1.0 + t * t), sn = c * t;
+        // A <- J^T A J with J the rotation in the plane (k, l)
+        for (int r = 0; r < d; ++r) {
+          const double x = a[r + k * d], y = a[r + l * d];
+          a[r + k * d] = c * x - sn * y;
+          a[r + l * d] = sn * x + c * y;
+        }
+        for (int r = 0; r < d; ++r) {
+          const double x = a[k + r * d], y = a[l + r * d];
+          a[k + r * d] = c * x - sn * y;
+          a[l + r * d] = sn * x + c * y;
+        }
+        for (int r = 0; r < d; ++r) {
+          const double x = v[r + k * d], y = v[r + l * d];
+          v[r + k * d] = c * x - sn * y;
+          v[r + l * d] = sn * x + c * y;
+        }
+      }
+  }
+  int ord[kMaxD];
+  for (int i = 0; i < d; ++i) ord[i] = i;
+  for (int i = 1; i < d; ++i) {
+    const int o = ord[i];
+    int j = i - 1;
+    while (j >= 0 && a[ord[j] + ord[j] * d] > a[o + o * d]) {
+      ord[j + 1] = ord[j];
+      --j;
+    }
+    ord[j + 1] = o;
+  }
+  for (int i = 0; i < d; ++i) {
+    lam[i] = a[ord[i] + ord[i] * d];
+    for (int r = 0; r < d; ++r) u[r + i * d] = v[r + ord[i] * d];
+  }
+}
+
+// Tears of the couplings.  Slot t holds P (d x d), S (d), Q (d x d) of the
+// coupling between chain blocks t and t+1; chain block 0 is the first block
+// listed in gam (gam + t d^2 is the coupling of chain blocks t, t+1).
+// Slots t >= nreal are decoupled padding: S = 0, P = 0, Q = I.
+__global__ void k_tear(int d, int nslots, int nreal, const double* __restrict__ gam, double* __restrict__ pm,
+                       double* __restrict__ sv, double* __restrict__ qm) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= nslots) return;
+  double* p = pm + (int64_t)t * d * d;
+  double* q = qm + (int64_t)t * d * d;
+  double* s = sv + (int64_t)t * d;
+  if (t < nreal) {
+    svd_small(d, gam + (int64_t)t * d * d, p, s, q);
+  } else {
+    for (int c = 0; c < d; ++c) {
+      s[c] = 0.0;
+      for (int r = 0; r < d; ++r) {
+        p[r + c * d] = 0.0;
+        q[r + c * d] = r == c ? 1.0 : 0.0;
+      }
+    }
+  }
+}
+
+// Leaves of the tail: block t (0-based within the tail, first tail block at
+// xi0) minus Q S Q^T of the tear below it (slot toff + t) and P S P^T of the
+// tear above it (slot toff + t - 1, which for t = 0 exists only when toff =
+// 1: the tear between the arrowhead and the tail).  Blocks t >= nb are
+// decoupled padding with eigenvalues big + t d + i.
+__global__ void k_leaf(int d, int nb, int nb2, int toff, double big, const double* __restrict__ xi0,
+                       const double* __restrict__ pm, const double* __restrict__ sv,
+                       const double* __restrict__ qm, double* __restrict__ lam, double* __restrict__ u) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= nb2) return;
+  double* lt = lam + (int64_t)t * d;
+  double* ut = u + (int64_t)t * d * d;
+  if (t >= nb) {
+    for (int c = 0; c < d; ++c) {
+      lt[c] = big + (double)(t * d + c);
+      for (int r = 0; r < d; ++r) ut[r + c * d] = r == c ? 1.0 : 0.0;
+    }
+    return;
+  }
+  double a[kMaxD * kMaxD];
+  for (int i = 0; i < d * d; ++i) a[i] = xi0[(int64_t)t * d * d + i];
+  const int below = toff + t, above = toff + t - 1;
+  if (t < nb - 1) {
+    const double* q = qm + (int64_t)below * d * d;
+    const double* s = sv + (int64_t)below * d;
+    for (int c = 0; c < d; ++c)
+      for (int r = 0; r < d; ++r) {
+        double acc = 0.0;
+        for (int k = 0; k < d; ++k) acc += q[r + k * d] * s[k] * q[c + k * d];
+        a[r + c * d] -= acc;
+      }
+  }
+  if (above >= 0) {
+    const double* p = pm + (int64_t)above * d * d;
+    const double* s = sv + (int64_t)above * d;
+    for (int c = 0; c < d; ++c)
+      for (int r = 0; r < d; ++r) {
+        double acc = 0.0;
+        for (int k = 0; k < d; ++k) acc += p[r + k * d] * s[k] * p[c + k * d];
+        a[r + c * d] -= acc;
+      }
+  }
+  eig_small(d, a, lt, ut);
+}
+
+// arrow tip block X = Xi_{l0+1} - Q S Q^T of the tear with the tail (slot 0)
+__global__ void k_tip(int d, const double* __restrict__ xi1, const double* __restrict__ qm,
+                      const double* __restrict__ sv, int has_tail, double* __restrict__ x) {
+  const int e = threadIdx.x;
+  if (e >= d * d) return;
+  const int r = e % d, c = e / d;
+  double acc = 0.0;
+  if (has_tail)
+    for (int k = 0; k < d; ++k) acc += qm[r + k * d] * sv[k] * qm[c + k * d];
+  x[e] = xi1[e] - acc;
+}
+
+// Union of two ascending lists (left first on ties), one block per problem:
+// poles[position] = value, src[position] = a (left) or mL + r (right).
+__global__ void k_union(int mL, int mR, const double* __restrict__ lamL, int64_t sL,
+                        const double* __restrict__ lamR, int64_t sR, double* __restrict__ poles,
+                        int* __restrict__ src, int64_t so) {
+  const int b = blockIdx.x;
+  const double* l = lamL + (int64_t)b * sL;
+  const double* r = lamR + (int64_t)b * sR;
+  double* po = poles + (int64_t)b * so;
+  int* sr = src + (int64_t)b * so;
+  for (int a = threadIdx.x; a < mL; a += blockDim.x) {
+    const double v = l[a];
+    int lo = 0, hi = mR;  // right values < v
+    while (lo < hi) {
+      const int mid = (lo + hi) >> 1;
+      if (r[mid] < v) lo = mid + 1; else hi = mid;
+    }
+    po[a + lo] = v;
+    sr[a + lo] = a;
+  }
+  for (int c = threadIdx.x; c < mR; c += blockDim.x) {
+    const double v = r[c];
+    int lo = 0, hi = mL;  // left values <= v
+    while (lo < hi) {
+      const int mid = (lo + hi) >> 1;
+      if (l[mid] <= v) lo = mid + 1; else hi = mid;
+    }
+    po[c + lo] = v;
+    sr[c + lo] = mL + c;
+  }
+}
+
+// Coupling vector of the first update of a merge, in the union order: z[k] =
+// U_L(last d rows, col) q (left columns) or U_R(first d rows, col) p (right
+// columns), with q = Q(:, i), p = P(:, i) of the problem's tear slot
+// (slot0 + b sstep); also rho[b] = S(i).
+__global__ void k_zfirst(int mL, int mR, int d, int i, const double* __restrict__ uL, int64_t suL, int ldL,
+                         const double* __restrict__ uR, int64_t suR, int ldR, const int* __restrict__ src,
+                         int64_t so, const double* __restrict__ pm, const double* __restrict__ sv,
+                         const double* __restrict__ qm, int slot0, int sstep, double* __restrict__ z,
+                         double* __restrict__ rho) {
+  const int b = blockIdx.y;
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  const int slot = slot0 + b * sstep;
+  if (k == 0) rho[b] = sv[(int64_t)slot * d + i];
+  if (k >= mL + mR) return;
+  const int sc = src[(int64_t)b * so + k];
+  double acc = 0.0;
+  if (sc < mL) {
+    const double* col = uL + (int64_t)b * suL + (int64_t)sc * ldL + (mL - d);
+    const double* q = qm + (int64_t)slot * d * d + (int64_t)i * d;
+    for (int r = 0; r < d; ++r) acc += col[r] * q[r];
+  } else {
+    const double* col = uR + (int64_t)b * suR + (int64_t)(sc - mL) * ldR;
+    const double* p = pm + (int64_t)slot * d * d + (int64_t)i * d;
+    for (int r = 0; r < d; ++r) acc += col[r] * p[r];
+  }
+  z[(int64_t)b * (mL + mR) + k] = acc;
+}
+
+// Coupling vector of a later update of a merge: z = E^T v, v = q_i at rows
+// mL-d..mL-1 and p_i at rows mL..mL+d-1 of E (m x m, ld ldE); rho[b] = S(i).
+__global__ void k_zvec(int m, int mL, int d, int i, const double* __restrict__ e, int64_t se, int ldE,
+                       const double* __restrict__ pm, const double* __restrict__ sv,
+                       const double* __restrict__ qm, int slot0, int sstep, double* __restrict__ z,
+                       double* __restrict__ rho) {
+  const int b = blockIdx.y;
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  const int slot = slot0 + b * sstep;
+  if (k == 0) rho[b] = sv[(int64_t)slot * d + i];
+  if (k >= m) return;
+  const double* col = e + (int64_t)b * se + (int64_t)k * ldE;
+  const double* q = qm + (int64_t)slot * d * d + (int64_t)i * d;
+  const double* p = pm + (int64_t)slot * d * d + (int64_t)i * d;
+  double acc = 0.0;
+  for (int r = 0; r < d; ++r) acc += col[mL - d + r] * q[r] + col[mL + r] * p[r];
+  z[(int64_t)b * m + k] = acc;
+}
+
+// split the rows of the merge eigenvectors W (m x m, rows in union order) by
+// the block they came from: Wl (mL x m, row = left column) and Wr (mR x m)
+__global__ void k_split(int m, int mL, const double* __restrict__ w, int64_t sw, const int* __restrict__ src,
+                        int64_t so, double* __restrict__ wl, int64_t sl, double* __restrict__ wr,
+                        int64_t sr) {
+  const int b = blockIdx.y;
   const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= (int64_t)K * K) return;
-  const int k = (int)(e % K), j = (int)(e / K);  // union row k, final column j
-  const double v = wn[(int64_t)colf[j] * K + k];
-  const int sc = src[k];
-  if (sc >= 0) wa[(int64_t)j * m1 + sc] = v;
-  else wt[(int64_t)j * m2 + (-sc - 1)] = v;
+  if (e >= (int64_t)m * m) return;
+  const int k = (int)(e % m), j = (int)(e / m);
+  const double v = w[(int64_t)b * sw + e];
+  const int sc = src[(int64_t)b * so + k];
+  const int mR = m - mL;
+  if (sc < mL) wl[(int64_t)b * sl + (int64_t)j * mL + sc] = v;
+  else wr[(int64_t)b * sr + (int64_t)j * mR + (sc - mL)] = v;
+}
+
+// border row i of the block arrowhead in the current row space (kk + i rows):
+// c = [F(i, :), X(i, 0:i)]
+__global__ void k_arrow_c(int kk, int d, int i, const double* __restrict__ f, const double* __restrict__ x,
+                          double* __restrict__ c) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= kk + i) return;
+  c[k] = k < kk ? f[i + (int64_t)k * d] : x[i + (int64_t)(k - kk) * d];
+}
+
+// row m of E (ld m + 1) = row m of W (ld m + 1): the new tip row
+__global__ void k_copy_row(int m, const double* __restrict__ w, double* __restrict__ e) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j > m) return;
+  e[m + (int64_t)j * (m + 1)] = w[m + (int64_t)j * (m + 1)];
 }
 
 }  // namespace
@@ -370,117 +716,296 @@ __global__ void k_scatter(int K, int m1, int m2, const double* __restrict__ wn,
 // host side
 // ---------------------------------------------------------------------------
 struct EigWork {
-  DBuf b_int, b_dbl, b_u1, b_u2, b_wn, b_wa, b_wt, b_dd, b_ee, b_info;
+  DBuf b_int, b_dbl, b_tear, b_small, b_lam, b_g0, b_g1, b_g2, b_w, b_wl, b_wr, b_ea, b_eb, b_c;
 };
 
-static Sec make_sec(double*& dp, int*& ip, int m) {
+namespace {
+
+Sec make_sec(double*& dp, int*& ip, int nbat, int S) {
   Sec s;
-  s.cnt = ip; ip += 4;
-  s.p = dp; dp += m;
-  s.w = dp; dp += m;
-  s.idx = ip; ip += m;
-  s.rot_i = ip; ip += m;
-  s.rot_j = ip; ip += m;
-  s.rot_c = dp; dp += m;
-  s.rot_s = dp; dp += m;
-  s.dval = dp; dp += m;
-  s.didx = ip; ip += m;
-  s.ro = ip; ip += m + 1;
-  s.rt = dp; dp += m + 1;
-  s.what = dp; dp += m;
+  const int64_t n = (int64_t)nbat * S;
+  s.cnt = ip; ip += 4 * nbat;
+  s.p = dp; dp += n;
+  s.w = dp; dp += n;
+  s.idx = ip; ip += n;
+  s.rot_i = ip; ip += n;
+  s.rot_j = ip; ip += n;
+  s.rot_c = dp; dp += n;
+  s.rot_s = dp; dp += n;
+  s.dval = dp; dp += n;
+  s.didx = ip; ip += n;
+  s.ro = ip; ip += n;
+  s.rt = dp; dp += n;
+  s.what = dp; dp += n;
   return s;
 }
+constexpr int kSecDbl = 7, kSecInt = 6;  // per-entry doubles / ints of a Sec (plus 4 ints per problem)
 
-static void stedc(nsp_ctx* c, int n, double* dd, double* ee, double* cvec, rocblas_int* info) {
-  NSP_BLAS(rocsolver_dstedc(c->blas, rocblas_evect_tridiagonal, n, dd, ee, cvec, n, info));
+void gemm_batched(nsp_ctx* c, int m, int n, int k, const double* a, int lda, int64_t sa, const double* b,
+                  int ldb, int64_t sb, double* cc, int ldc, int64_t sc, int batch) {
+  const double one = 1.0, zero = 0.0;
+  if (batch == 1) {
+    NSP_BLAS(rocblas_dgemm(c->blas, rocblas_operation_none, rocblas_operation_none, m, n, k, &one, a, lda,
+                           b, ldb, &zero, cc, ldc));
+  } else {
+    NSP_BLAS(rocblas_dgemm_strided_batched(c->blas, rocblas_operation_none, rocblas_operation_none, m, n, k,
+                                           &one, a, lda, sa, b, ldb, sb, &zero, cc, ldc, sc, batch));
+  }
 }
 
-// Eigen-decomposition of T for d = 1 (see the file comment).  xi and gam are
-// indexed by Lanczos block number (xi[j] = Xi_j, gam[j] = Gamma_j); theta and
-// f hold the kk kept Ritz values and couplings.  norm_t bounds ||T||.  On
-// return evecs (K x K, column-major) holds the eigenvectors and evals the
-// eigenvalues, ascending; *info_dev receives the tridiagonal solver's info.
-void eig_restart_d1(nsp_ctx* c, EigWork& w, int K, int kk, double norm_t, const double* theta,
-                    const double* f, const double* xi, const double* gam, double* evals,
-                    double* evecs, int* info_dev) {
-  rocblas_int* info = reinterpret_cast<rocblas_int*>(info_dev);
-  if (kk == 0) {
-    w.b_ee.alloc(sizeof(double) * (size_t)K);
-    k_tridiag<<<nb(K, 256), 256, 0, c->stream>>>(K, xi, gam, evals, w.b_ee.as<double>());
+// One secular solve per problem of a batch, eigenvectors into X (zeroed here,
+// columns ascending), eigenvalues into lam.  RANK1 problems: m poles (vals
+// ascending), couplings cpl, rho per problem; ARROW: m poles, tip per problem,
+// X has m + 1 rows and columns.
+template <bool ARROW>
+void secular(nsp_ctx* c, Sec sec, int S, int nbat, int m, const double* vals, int64_t vstride,
+             const double* cpl, int cinc, int64_t cstride, const double* a_or_rho, double scale,
+             double bound, double* lam, int64_t lstride, int* pos, int64_t pstride, double* x,
+             int64_t xstride, int ldx) {
+  const int nroots = ARROW ? m + 1 : m;
+  const size_t lds2 = sizeof(double) * 2 * (size_t)m;
+  const bool lds = lds2 <= (size_t)kLdsBytes;
+  if (lds)
+    k_deflate<true><<<nbat, 256, lds2, c->stream>>>(m, vals, vstride, cpl, cinc, cstride,
+                                                    ARROW ? nullptr : a_or_rho, scale, sec, S);
+  else
+    k_deflate<false><<<nbat, 256, 0, c->stream>>>(m, vals, vstride, cpl, cinc, cstride,
+                                                  ARROW ? nullptr : a_or_rho, scale, sec, S);
+  const dim3 gr(nb(nroots, 4), nbat);
+  if (lds)
+    k_roots<ARROW, true><<<gr, 256, lds2, c->stream>>>(sec, S, a_or_rho, -bound, bound);
+  else
+    k_roots<ARROW, false><<<gr, 256, 0, c->stream>>>(sec, S, a_or_rho, -bound, bound);
+  k_lowner<ARROW><<<dim3(nb(m, 4), nbat), 256, 0, c->stream>>>(sec, S, a_or_rho);
+  const size_t lds_o = (sizeof(double) + sizeof(int)) * (size_t)(m + 1);
+  if (lds_o > (size_t)kLdsBytes) throw Error(NSP_ERR_ARG, "restart matrix too large for the eigensolver");
+  k_order<ARROW><<<nbat, 256, lds_o, c->stream>>>(sec, S, lam, lstride, pos, pstride);
+  const int xc = ARROW ? m + 1 : m;
+  if (nbat == 1 || xstride == (int64_t)ldx * xc) {
+    NSP_HIP(hipMemsetAsync(x, 0, sizeof(double) * (size_t)ldx * xc * nbat, c->stream));
+  } else {
+    NSP_HIP(hipMemset2DAsync(x, sizeof(double) * (size_t)xstride, 0, sizeof(double) * (size_t)ldx * xc, nbat,
+                             c->stream));
+  }
+  k_vectors<ARROW><<<dim3(nroots, nbat), 256, 0, c->stream>>>(sec, S, pos, pstride, x, xstride, ldx, m);
+  k_deflated_cols<ARROW><<<dim3(nb(m + 1, 256), nbat), 256, 0, c->stream>>>(sec, S, pos, pstride, x,
+                                                                             xstride, ldx);
+  k_unrotate<<<nbat, 1024, 0, c->stream>>>(sec, S, x, xstride, ldx, xc);
+  NSP_HIP(hipGetLastError());
+}
+
+inline int next_pow2(int v) {
+  int p = 1;
+  while (p < v) p <<= 1;
+  return p;
+}
+
+}  // namespace
+
+// Eigen-decomposition of T (see the file comment).  xi and gam are indexed by
+// Lanczos block number (block j at xi + j d^2, column-major d x d; gam + j d^2
+// is the coupling of blocks j and j+1, i.e. T(block j+1, block j)); theta and
+// f (d x kk, column-major) hold the kk kept Ritz values and their coupling.
+// norm_t bounds ||T||.  On return evecs (K x K, column-major) holds the
+// eigenvectors and evals the eigenvalues, ascending.
+void eig_restart(nsp_ctx* c, EigWork& w, int K, int d, int kk, double norm_t, const double* theta,
+                 const double* f, const double* xi, const double* gam, double* evals, double* evecs) {
+  const int L = K / d, l0 = kk / d;
+  if (K % d || kk % d || kk > K - d || L < 1) throw Error(NSP_ERR_ARG, "eig_restart: inconsistent sizes");
+  const bool arrow = kk > 0;
+  const int jb0 = arrow ? l0 + 2 : 1;      // first tail block (Lanczos block number)
+  const int nbt = L - jb0 + 1;             // tail blocks (0 when the arrowhead is all of T)
+  const int m1 = arrow ? kk + d : 0, m2 = nbt * d;
+  const int nb2 = nbt > 0 ? next_pow2(nbt) : 0, m2p = nb2 * d;
+  const int toff = arrow ? 1 : 0;          // tear slot 0: arrowhead-tail (when both exist)
+  const int nslots = toff + std::max(nb2 - 1, 0);
+  const double big = 4.0 * norm_t + 4.0;   // above every eigenvalue of every sub-problem
+  const double bound = 4.0 * norm_t + 1.0; // every arrowhead eigenvalue lies inside
+  const int mmax = std::max(K, m2p) + 2;
+
+  // workspaces (sized by K so that they are allocated once per run)
+  const int64_t big2 = (int64_t)mmax * mmax;
+  w.b_dbl.alloc(sizeof(double) * (size_t)(kSecDbl * (2 * mmax + 64) + 6 * mmax + 64));
+  w.b_int.alloc(sizeof(int) * (size_t)(kSecInt * (2 * mmax + 64) + 4 * (mmax + 64) + 3 * mmax + 64));
+  w.b_tear.alloc(sizeof(double) * (size_t)(std::max(nslots, 1) * (2 * d * d + d)));
+  w.b_small.alloc(sizeof(double) * (size_t)(kMaxD * kMaxD + 2 * mmax + 64));
+  w.b_lam.alloc(sizeof(double) * (size_t)(3 * mmax));
+  w.b_g0.alloc(sizeof(double) * (size_t)big2);
+  w.b_g1.alloc(sizeof(double) * (size_t)big2);
+  w.b_g2.alloc(sizeof(double) * (size_t)big2);
+  w.b_w.alloc(sizeof(double) * (size_t)big2);
+  w.b_wl.alloc(sizeof(double) * (size_t)big2);
+  w.b_wr.alloc(sizeof(double) * (size_t)big2);
+  double* pm = w.b_tear.as<double>();
+  double* qm = pm + (int64_t)std::max(nslots, 1) * d * d;
+  double* sv = qm + (int64_t)std::max(nslots, 1) * d * d;
+  double* xtip = w.b_small.as<double>();
+  double* rho = xtip + kMaxD * kMaxD;
+  double* zc = rho + mmax + 32;  // coupling vectors (z), up to mmax
+  double* lamb[3] = {w.b_lam.as<double>(), w.b_lam.as<double>() + mmax, w.b_lam.as<double>() + 2 * mmax};
+  double* dp0 = w.b_dbl.as<double>();
+  int* ip0 = w.b_int.as<int>();
+  double* poles = dp0 + kSecDbl * (2 * mmax + 64);
+  double* zb = poles + mmax;        // batched coupling vectors
+  int* src = ip0 + kSecInt * (2 * mmax + 64);
+  int* pos = src + mmax;
+
+  // ---- tears and leaves
+  if (nslots > 0) {
+    // slot 0 (arrow case): Gamma_{l0+1}; tail slots: Gamma_{jb0 + t}
+    const int nreal = arrow ? nbt : std::max(nbt - 1, 0);  // couplings present in gam
+    const double* g0 = gam + (int64_t)(arrow ? l0 + 1 : 1) * d * d;
+    k_tear<<<nb(nslots, 64), 64, 0, c->stream>>>(d, nslots, nreal, g0, pm, sv, qm);
     NSP_HIP(hipGetLastError());
-    stedc(c, K, evals, w.b_ee.as<double>(), evecs, info);
+  }
+
+  // ---- tail: leaves, then merges level by level (E groups in b_g0/b_g1)
+  double* tl_lam = nullptr;  // tail eigenvalues (m2p, ascending, the first m2 real)
+  double* tl_vec = nullptr;  // tail eigenvectors (m2p x m2p, ld m2p)
+  if (nbt > 0) {
+    double* gcur = w.b_g0.as<double>();
+    double* gnext = w.b_g1.as<double>();
+    double* gtmp = w.b_g2.as<double>();
+    double* lcur = lamb[0];
+    double* lnext = lamb[1];
+    double* ltmp = lamb[2];
+    k_leaf<<<nb(nb2, 64), 64, 0, c->stream>>>(d, nbt, nb2, toff, big, xi + (int64_t)jb0 * d * d, pm, sv, qm,
+                                              lcur, gcur);
+    NSP_HIP(hipGetLastError());
+    for (int gs = d, lev = 0; gs < m2p; gs *= 2, ++lev) {
+      const int m = 2 * gs, npair = m2p / m;
+      const int S = m + 2;
+      double* dp = dp0;
+      int* ip = ip0;
+      Sec sec = make_sec(dp, ip, npair, S);
+      // tear slot of pair b: the coupling between tail blocks (2b+1) 2^lev - 1 and (2b+1) 2^lev
+      const int slot0 = toff + (1 << lev) - 1, sstep = 1 << (lev + 1);
+      const int64_t sg = (int64_t)gs * gs, sm = (int64_t)m * m;
+      // first update: union of the children's spectra, block-structured GEMMs
+      k_union<<<npair, 256, 0, c->stream>>>(gs, gs, lcur, m, lcur + gs, m, poles, src, m);
+      k_zfirst<<<dim3(nb(m, 256), npair), 256, 0, c->stream>>>(gs, gs, d, 0, gcur, 2 * sg, gs, gcur + sg,
+                                                              2 * sg, gs, src, m, pm, sv, qm, slot0, sstep,
+                                                              zb, rho);
+      NSP_HIP(hipGetLastError());
+      double* wbuf = w.b_w.as<double>();
+      secular<false>(c, sec, S, npair, m, poles, m, zb, 1, m, rho, norm_t, bound, lnext, m, pos, m, wbuf, sm, m);
+      double* wl = w.b_wl.as<double>();
+      double* wr = w.b_wr.as<double>();
+      k_split<<<dim3(nb(sm, 256), npair), 256, 0, c->stream>>>(m, gs, wbuf, sm, src, m, wl, (int64_t)gs * m,
+                                                              wr, (int64_t)gs * m);
+      NSP_HIP(hipGetLastError());
+      gemm_batched(c, gs, m, gs, gcur, gs, 2 * sg, wl, gs, (int64_t)gs * m, gnext, m, sm, npair);
+      gemm_batched(c, gs, m, gs, gcur + sg, gs, 2 * sg, wr, gs, (int64_t)gs * m, gnext + gs, m, sm, npair);
+      // later updates: dense
+      for (int i = 1; i < d; ++i) {
+        k_zvec<<<dim3(nb(m, 256), npair), 256, 0, c->stream>>>(m, gs, d, i, gnext, sm, m, pm, sv, qm, slot0,
+                                                              sstep, zb, rho);
+        NSP_HIP(hipGetLastError());
+        secular<false>(c, sec, S, npair, m, lnext, m, zb, 1, m, rho, norm_t, bound, ltmp, m, pos, m, wbuf, sm,
+                       m);
+        gemm_batched(c, m, m, m, gnext, m, sm, wbuf, m, sm, gtmp, m, sm, npair);
+        std::swap(gnext, gtmp);
+        std::swap(lnext, ltmp);
+      }
+      std::swap(gcur, gnext);
+      std::swap(lcur, lnext);
+    }
+    tl_lam = lcur;
+    tl_vec = gcur;
+    // keep the tail's buffers out of the way of what follows
+    if (tl_vec != w.b_g0.as<double>()) {
+      NSP_HIP(hipMemcpyAsync(w.b_g0.as<double>(), tl_vec, sizeof(double) * (size_t)m2p * m2p,
+                             hipMemcpyDeviceToDevice, c->stream));
+      tl_vec = w.b_g0.as<double>();
+    }
+    if (tl_lam != lamb[0]) {
+      NSP_HIP(hipMemcpyAsync(lamb[0], tl_lam, sizeof(double) * (size_t)m2p, hipMemcpyDeviceToDevice,
+                             c->stream));
+      tl_lam = lamb[0];
+    }
+  }
+
+  if (!arrow) {
+    // first cycle: T is the tail (m2 = K); copy the real block out
+    NSP_HIP(hipMemcpy2DAsync(evecs, sizeof(double) * K, tl_vec, sizeof(double) * m2p, sizeof(double) * K, K,
+                             hipMemcpyDeviceToDevice, c->stream));
+    NSP_HIP(hipMemcpyAsync(evals, tl_lam, sizeof(double) * K, hipMemcpyDeviceToDevice, c->stream));
     return;
   }
-  const int l0 = kk;  // d = 1: kept blocks = kept vectors
-  const int m1 = kk + 1, m2 = K - kk - 1;
-  w.b_int.alloc(sizeof(int) * (size_t)(24 * (K + 8)));
-  w.b_dbl.alloc(sizeof(double) * (size_t)(24 * (K + 8)));
-  w.b_u1.alloc(sizeof(double) * (size_t)m1 * m1);
-  w.b_u2.alloc(sizeof(double) * (size_t)m2 * m2);
-  w.b_wn.alloc(sizeof(double) * (size_t)K * K);
-  w.b_wa.alloc(sizeof(double) * (size_t)m1 * K);
-  w.b_wt.alloc(sizeof(double) * (size_t)m2 * K);
-  w.b_dd.alloc(sizeof(double) * (size_t)(m2 + 8));
-  w.b_ee.alloc(sizeof(double) * (size_t)(m2 + 8));
-  double* dp = w.b_dbl.as<double>();
-  int* ip = w.b_int.as<int>();
-  Sec sa = make_sec(dp, ip, m1);
-  Sec sm = make_sec(dp, ip, K);
-  double* tip = dp; dp += 2;
-  double* lam1 = dp; dp += m1;
-  double* lam = dp; dp += K;
-  double* dvals = dp; dp += K;
-  double* zc = dp; dp += K;
-  int* col1 = ip; ip += m1;
-  int* colf = ip; ip += K;
-  int* src = ip; ip += K;
-  double* u1 = w.b_u1.as<double>();
-  double* u2 = w.b_u2.as<double>();
-  double* wn = w.b_wn.as<double>();
-  double* dd = w.b_dd.as<double>();
-  double* ee = w.b_ee.as<double>();
-  const double bound = 4.0 * norm_t + 1.0;  // every eigenvalue of the arrowhead lies inside
 
-  // ---- arrowhead M1 = [diag(theta) f; f^T Xi_{l0+1} - Gamma_{l0+1}]
-  k_arrow_tip<<<1, 1, 0, c->stream>>>(xi, gam, l0 + 1, tip);
-  k_deflate<<<1, 1, 0, c->stream>>>(kk, theta, f, nullptr, norm_t, sa);
-  k_roots<true><<<m1, 64, 0, c->stream>>>(sa, tip, -bound, bound);
-  k_lowner<true><<<nb(m1, 128), 128, 0, c->stream>>>(sa, tip);
-  NSP_HIP(hipMemsetAsync(u1, 0, sizeof(double) * (size_t)m1 * m1, c->stream));
-  k_vectors<true><<<m1, 256, 0, c->stream>>>(sa, u1, m1, m1 - 1);
-  k_order<true><<<1, 1, 0, c->stream>>>(sa, lam1, col1);
-  k_deflated_cols<<<nb(m1, 256), 256, 0, c->stream>>>(sa, u1, m1, m1);
-  k_unrotate<<<1, 1024, 0, c->stream>>>(sa, u1, m1, m1);
+  // ---- block arrowhead M1 = [diag(theta) F^T; F X], X = Xi_{l0+1} - Q S Q^T
+  k_tip<<<1, 64, 0, c->stream>>>(d, xi + (int64_t)(l0 + 1) * d * d, qm, sv, nbt > 0 ? 1 : 0, xtip);
   NSP_HIP(hipGetLastError());
+  double* ea = w.b_g1.as<double>();   // current arrowhead eigenvectors ((kk+i) x (kk+i), compact)
+  double* eb = w.b_g2.as<double>();
+  double* la = lamb[1];
+  double* lb2 = lamb[2];
+  {
+    const int m = kk, S = m + 3;
+    double* dp = dp0;
+    int* ip = ip0;
+    Sec sec = make_sec(dp, ip, 1, S);
+    // first tip: poles theta, couplings F(0, :), tip X(0, 0); eigenvectors = W
+    secular<true>(c, sec, S, 1, m, theta, 0, f, d, 0, xtip, norm_t, bound, la, 0, pos, 0, ea, 0, m + 1);
+    for (int i = 1; i < d; ++i) {
+      const int mi = kk + i, Si = mi + 3;
+      dp = dp0;
+      ip = ip0;
+      Sec si = make_sec(dp, ip, 1, Si);
+      k_arrow_c<<<nb(mi, 256), 256, 0, c->stream>>>(kk, d, i, f, xtip, zc);
+      NSP_HIP(hipGetLastError());
+      const double one = 1.0, zero = 0.0;
+      // z = E^T c
+      NSP_BLAS(rocblas_dgemv(c->blas, rocblas_operation_transpose, mi, mi, &one, ea, mi, zc, 1, &zero, zb, 1));
+      double* wbuf = w.b_w.as<double>();
+      secular<true>(c, si, Si, 1, mi, la, 0, zb, 1, 0, xtip + i + (int64_t)i * d, norm_t, bound, lb2, 0, pos,
+                    0, wbuf, 0, mi + 1);
+      // E_new = [E 0; 0 1] W: rows 0..mi-1 by GEMM, row mi copied
+      NSP_BLAS(rocblas_dgemm(c->blas, rocblas_operation_none, rocblas_operation_none, mi, mi + 1, mi, &one, ea,
+                             mi, wbuf, mi + 1, &zero, eb, mi + 1));
+      k_copy_row<<<nb(mi + 1, 256), 256, 0, c->stream>>>(mi, wbuf, eb);
+      NSP_HIP(hipGetLastError());
+      std::swap(ea, eb);
+      std::swap(la, lb2);
+    }
+  }
 
-  // ---- tail T2 - Gamma_{l0+1} e_0 e_0^T (tridiagonal)
-  k_tail<<<nb(m2, 256), 256, 0, c->stream>>>(m2, xi, gam, l0 + 2, dd, ee);
-  NSP_HIP(hipGetLastError());
-  stedc(c, m2, dd, ee, u2, info);
-
-  // ---- rank-one merge with rho = Gamma_{l0+1}
-  const double* rho = gam + (l0 + 1);
-  k_merge_union<<<1, 1, 0, c->stream>>>(m1, m2, lam1, col1, u1, dd, u2, dvals, zc, src);
-  k_deflate<<<1, 1, 0, c->stream>>>(K, dvals, zc, rho, norm_t, sm);
-  k_roots<false><<<K, 64, 0, c->stream>>>(sm, rho, 0.0, 0.0);
-  k_lowner<false><<<nb(K, 128), 128, 0, c->stream>>>(sm, rho);
-  NSP_HIP(hipMemsetAsync(wn, 0, sizeof(double) * (size_t)K * K, c->stream));
-  k_vectors<false><<<K, 256, 0, c->stream>>>(sm, wn, K, 0);
-  k_order<false><<<1, 1, 0, c->stream>>>(sm, lam, colf);
-  k_deflated_cols<<<nb(K, 256), 256, 0, c->stream>>>(sm, wn, K, K);
-  k_unrotate<<<1, 1024, 0, c->stream>>>(sm, wn, K, K);
-  NSP_HIP(hipGetLastError());
-
-  // ---- eigenvectors of T = [U1 0; 0 U2] W, columns ascending
-  k_scatter<<<nb((int64_t)K * K, 256), 256, 0, c->stream>>>(K, m1, m2, wn, src, colf,
-                                                            w.b_wa.as<double>(), w.b_wt.as<double>());
-  NSP_HIP(hipGetLastError());
-  const double one = 1.0, zero = 0.0;
-  NSP_BLAS(rocblas_dgemm(c->blas, rocblas_operation_none, rocblas_operation_none, m1, K, m1, &one, u1,
-                         m1, w.b_wa.as<double>(), m1, &zero, evecs, K));
-  NSP_BLAS(rocblas_dgemm(c->blas, rocblas_operation_none, rocblas_operation_none, m2, K, m2, &one, u2,
-                         m2, w.b_wt.as<double>(), m2, &zero, evecs + m1, K));
-  NSP_HIP(hipMemcpyAsync(evals, lam, sizeof(double) * K, hipMemcpyDeviceToDevice, c->stream));
+  // ---- join arrowhead (m1) and tail (m2) with the d updates of tear slot 0
+  {
+    const int m = K, S = m + 2;
+    double* dp = dp0;
+    int* ip = ip0;
+    Sec sec = make_sec(dp, ip, 1, S);
+    double* lf = lb2;  // free eigenvalue buffer (la holds the arrowhead's)
+    k_union<<<1, 256, 0, c->stream>>>(m1, m2, la, 0, tl_lam, 0, poles, src, 0);
+    k_zfirst<<<dim3(nb(m, 256), 1), 256, 0, c->stream>>>(m1, m2, d, 0, ea, 0, m1, tl_vec, 0, m2p, src, 0, pm,
+                                                         sv, qm, 0, 0, zb, rho);
+    NSP_HIP(hipGetLastError());
+    double* wbuf = w.b_w.as<double>();
+    secular<false>(c, sec, S, 1, m, poles, 0, zb, 1, 0, rho, norm_t, bound, lf, 0, pos, 0, wbuf, 0, m);
+    double* wl = w.b_wl.as<double>();
+    double* wr = w.b_wr.as<double>();
+    k_split<<<dim3(nb((int64_t)m * m, 256), 1), 256, 0, c->stream>>>(m, m1, wbuf, 0, src, 0, wl, 0, wr, 0);
+    NSP_HIP(hipGetLastError());
+    // the final eigenvectors go to evecs after an odd number of dense updates
+    // behind the first, to eb otherwise, so that the last lands in evecs
+    double* cur = (d % 2 == 1) ? evecs : eb;
+    double* other = (d % 2 == 1) ? eb : evecs;
+    if (cur == eb && eb == ea) throw Error(NSP_ERR_ARG, "eig_restart: workspace aliasing");
+    gemm_batched(c, m1, m, m1, ea, m1, 0, wl, m1, 0, cur, K, 0, 1);
+    gemm_batched(c, m2, m, m2, tl_vec, m2p, 0, wr, m2, 0, cur + m1, K, 0, 1);
+    double* lcur = lf;
+    double* lother = la;
+    for (int i = 1; i < d; ++i) {
+      k_zvec<<<dim3(nb(m, 256), 1), 256, 0, c->stream>>>(m, m1, d, i, cur, 0, K, pm, sv, qm, 0, 0, zb, rho);
+      NSP_HIP(hipGetLastError());
+      secular<false>(c, sec, S, 1, m, lcur, 0, zb, 1, 0, rho, norm_t, bound, lother, 0, pos, 0, wbuf, 0, m);
+      gemm_batched(c, m, m, m, cur, K, 0, wbuf, m, 0, other, K, 0, 1);
+      std::swap(cur, other);
+      std::swap(lcur, lother);
+    }
+    NSP_HIP(hipMemcpyAsync(evals, lcur, sizeof(double) * K, hipMemcpyDeviceToDevice, c->stream));
+  }
 }
 
 EigWork* eig_work_new() { return new EigWork(); }

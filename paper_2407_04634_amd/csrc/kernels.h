@@ -74,13 +74,12 @@ void convert(nsp_ctx* c, int64_t cnt, const SRC* s, DST* o);
 template <typename SRC, typename DST>
 void copy_panel(nsp_ctx* c, int64_t rows, int cols, const SRC* s, int64_t lds, DST* o, int64_t ldo);
 
-// Ritz eigenproblem of the restart matrix for d = 1 (eig.hip)
+// Ritz eigenproblem of the restart matrix, any block size (eig.hip)
 struct EigWork;
 EigWork* eig_work_new();
 void eig_work_delete(EigWork* w);
-void eig_restart_d1(nsp_ctx* c, EigWork& w, int K, int kk, double norm_t, const double* theta,
-                    const double* f, const double* xi, const double* gam, double* evals,
-                    double* evecs, int* info_dev);
+void eig_restart(nsp_ctx* c, EigWork& w, int K, int d, int kk, double norm_t, const double* theta,
+                 const double* f, const double* xi, const double* gam, double* evals, double* evecs);
 
 // dense: refinement / backward
 void coldots(nsp_ctx* c, int64_t rows, int k, const double* a, const double* b, double* out,

@@ -479,10 +479,11 @@ struct Lanczos {
         NSP_HIP(hipMemcpy(hh.data(), ro_hist, sizeof(int) * (L + 3), hipMemcpyDeviceToHost));
         prof.collect(hh.data(), n, d, (int)sizeof(VT));
       }
-      // ---- Rayleigh-Ritz on T (Eq. "defT"): the structured solver for d = 1,
-      // dense FP64 rocSOLVER otherwise
-      if (d == 1 && !dense_eig) {
-        eig_restart_d1(c, *eigw, K, kk, norm_t, theta_kept, fmat, xi, gam, evals, T, flags + 4);
+      // ---- Rayleigh-Ritz on T (Eq. "defT"): the structured divide-and-conquer
+      // solver up to K = 4096 (its secular kernels stage a problem in 64 KB of
+      // LDS); dense FP64 rocSOLVER beyond, or with NSP_DENSE_EIG=1
+      if (!dense_eig && K <= 4096) {
+        eig_restart(c, *eigw, K, d, kk, norm_t, theta_kept, fmat, xi, gam, evals, T);
       } else {
         assemble_t(c, K, d, kk, theta_kept, fmat, xi, gam, T);
         syevd(c, K, T, evals, c->ework, b_info);

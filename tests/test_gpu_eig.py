@@ -1,4 +1,4 @@
-"""Structured Ritz eigensolver of the restart matrix (d = 1) vs LAPACK on the dense matrix."""
+"""Structured Ritz eigensolver of the restart matrix (block sizes 1 to 8) vs LAPACK on the dense matrix."""
 import numpy as np
 import pytest
 
@@ -56,6 +56,70 @@ def test_ritz_eig_matches_lapack(k, kk, kind):
     ref = np.linalg.eigvalsh(t)
     dev = lambda a: torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).cuda()  # noqa: E731
     ev, vec = ctx.ritz_eig(dev(theta), dev(f), dev(alpha), dev(beta))
+    ev, vec = ev.cpu().numpy(), vec.cpu().numpy()
+    nt = np.abs(t).sum(axis=1).max()
+    assert np.all(np.diff(ev) >= 0)
+    assert np.max(np.abs(ev - ref)) <= 1e-13 * nt
+    assert np.linalg.norm(t @ vec - vec * ev[None, :]) <= 1e-12 * nt * np.sqrt(k)
+    assert np.linalg.norm(vec.T @ vec - np.eye(k)) <= 1e-12 * k
+    ctx.close()
+
+
+def _block_case(d, kk, nbk, kind, seed):
+    """theta, F (d x kk), Xi blocks (nbk, d, d), Gamma blocks (nbk-1, d, d) and the dense T."""
+    rng = np.random.default_rng(seed)
+    theta = np.sort(rng.random(kk) * 10)
+    f = rng.standard_normal((d, kk))
+    xi = rng.standard_normal((nbk, d, d))
+    xi = xi + xi.transpose(0, 2, 1) + 5.0
+    gam = np.triu(rng.standard_normal((max(nbk - 1, 0), d, d))) + 0.3 * np.eye(d)
+    if kind == "cluster":  # a tight cluster near zero with tiny couplings (the perturbed null space)
+        nc = kk // 2
+        theta[:nc] = np.sort(1e-6 * rng.random(nc))
+        f[:, :nc] *= 1e-9
+    if kind == "deflate":  # zero couplings, repeated poles, a rank-deficient coupling block
+        f[:, ::3] = 0.0
+        theta[2::4] = theta[1::4][: len(theta[2::4])]
+        theta = np.sort(theta)
+        if nbk > 2:
+            gam[1][:, 0] = 0.0
+            gam[1][0, :] = 0.0
+    if kind == "weak" and nbk > 1:  # nearly decoupled tail
+        gam[0] *= 1e-14
+    k = kk + nbk * d
+    t = np.zeros((k, k))
+    t[np.arange(kk), np.arange(kk)] = theta
+    t[kk:kk + d, :kk] = f
+    t[:kk, kk:kk + d] = f.T
+    for j in range(nbk):
+        r = kk + j * d
+        t[r:r + d, r:r + d] = xi[j]
+        if j + 1 < nbk:
+            t[r + d:r + 2 * d, r:r + d] = gam[j]
+            t[r:r + d, r + d:r + 2 * d] = gam[j].T
+    return theta, f, xi, gam, t
+
+
+@pytest.mark.parametrize("d,kk,nbk,kind", [
+    (2, 0, 1, "plain"), (2, 0, 7, "plain"), (2, 6, 5, "plain"), (4, 0, 13, "plain"), (4, 16, 2, "plain"),
+    (4, 40, 30, "plain"), (4, 512, 128, "cluster"), (4, 300, 75, "deflate"), (8, 64, 40, "plain"),
+    (8, 128, 17, "weak"), (2, 200, 157, "cluster"), (1, 300, 211, "deflate"), (4, 612, 103, "plain"),
+])
+def test_block_ritz_eig_matches_lapack(d, kk, nbk, kind):
+    import torch
+    from tests.gpu_util import context
+    from workloads import generators as G
+
+    k = kk + nbk * d
+    print(f"[eig] blocks d={d} K={k} kk={kk} {kind}", flush=True)
+    c = G.config("er20")
+    ctx, _, _ = context(c, 0.01, d=1, max_dim=64)
+    theta, f, xi, gam, t = _block_case(d, kk, nbk, kind, seed=17 * d + k + kk)
+    ref = np.linalg.eigvalsh(t)
+    dev = lambda a: torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).cuda()  # noqa: E731
+    # column-major blocks: pass each block transposed
+    ev, vec = ctx.ritz_eig_blocks(d, dev(theta), dev(f.T), dev(xi.transpose(0, 2, 1)),
+                                  dev(gam.transpose(0, 2, 1)) if nbk > 1 else dev(np.zeros(1)))
     ev, vec = ev.cpu().numpy(), vec.cpu().numpy()
     nt = np.abs(t).sum(axis=1).max()
     assert np.all(np.diff(ev) >= 0)
