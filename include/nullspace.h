@@ -295,7 +295,7 @@ nsp_status nullspace_ritz_eig(nsp_ctx* ctx, int32_t K, int32_t kk, const double*
  *         [0            Gamma_1 Xi_2     ...]   (block tridiagonal below)
  * with K/d - kk/d diagonal blocks Xi_j (symmetric d x d) and the couplings
  * Gamma_j = T(block j+1, block j) (d x d) between consecutive ones.
- *  d      1..8, dividing K and kk; kk = 0 or kk <= K - 2d; K <= 4096.
+ *  d      1, 2, 4 or 8, dividing K and kk; kk = 0 or kk <= K - 2d; K <= 4096.
  *  theta  [kk] ascending; F [d x kk] column-major (ld d);
  *  xi     [(K-kk)/d blocks of d x d], each column-major, first block first;
  *  gam    [(K-kk)/d - 1 blocks of d x d] (may be NULL when there is one block);

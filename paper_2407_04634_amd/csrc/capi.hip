@@ -315,7 +315,7 @@ nsp_status nullspace_ritz_eig_blocks(nsp_ctx* ctx, int32_t K, int32_t d, int32_t
                                      double* evecs) {
   return guarded([&] {
     NSP_REQUIRE(ctx != nullptr, "ctx must not be NULL");
-    NSP_REQUIRE(d >= 1 && d <= nsp::kMaxD, "d must be in [1, 8]");
+    NSP_REQUIRE(d == 1 || d == 2 || d == 4 || d == 8, "d must be 1, 2, 4 or 8");
     NSP_REQUIRE(K >= d && K % d == 0 && kk % d == 0 && kk >= 0 && (kk == 0 || kk <= K - 2 * d),
                 "need K a multiple of d, kk a multiple of d, and kk = 0 or kk <= K - 2d");
     NSP_REQUIRE(K <= 4096, "K must not exceed 4096");

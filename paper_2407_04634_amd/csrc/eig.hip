@@ -79,73 +79,133 @@ __device__ __forceinline__ Sec sec_at(const Sec& s, int b, int S) {
   return r;
 }
 
+// block-wide exclusive scan of one int per thread (Hillis-Steele in LDS);
+// *total receives the block's sum in every thread
+__device__ int block_excl_scan(int v, int* scratch, int* total) {
+  const int t = threadIdx.x;
+  scratch[t] = v;
+  __syncthreads();
+  for (int off = 1; off < (int)blockDim.x; off <<= 1) {
+    const int add = t >= off ? scratch[t - off] : 0;
+    __syncthreads();
+    scratch[t] += add;
+    __syncthreads();
+  }
+  const int incl = scratch[t];
+  *total = scratch[blockDim.x - 1];
+  __syncthreads();
+  return incl - v;
+}
+
 // -------------------------------------------------------------------------
-// deflation (one block per problem: the poles and couplings are staged in LDS,
-// then one thread scans them in order)
+// deflation, one block of kDeflThreads per problem
 //   ARROW: rows 0..m-1 are the poles (value val[i], coupling cpl[i]); the
 //          arrow tip is row m; weight = cpl^2.
 //   RANK1: rows 0..m-1 are the poles (val[i] sorted ascending), coupling
 //          cpl[i]; weight = cpl^2 (rho applied in the root finder).
 // val of problem b at val + b vstride; coupling i at cpl[b cstride + i cinc].
+// A coupling is negligible when |cpl| (times |rho| for a merge) <= tol; of the
+// others, consecutive poles closer than tol form runs, and a Givens rotation
+// moves the coupling of each run member onto the next one, so that all but
+// the last of a run deflate and the last carries the run's combined coupling.
+// Kept poles and deflated values come out in index (= value) order, the
+// rotations run by run in the order they must be undone in reverse.
 // -------------------------------------------------------------------------
-template <bool LDS>
-__global__ __launch_bounds__(256) void k_deflate(int npoles, const double* __restrict__ val, int64_t vstride,
-                                                 const double* __restrict__ cpl, int cinc, int64_t cstride,
-                                                 const double* __restrict__ rho, double scale, Sec s0, int S) {
-  extern __shared__ double sh[];
+constexpr int kDeflThreads = 256;
+
+__global__ __launch_bounds__(kDeflThreads) void k_deflate(int npoles, const double* __restrict__ val,
+                                                          int64_t vstride, const double* __restrict__ cpl,
+                                                          int cinc, int64_t cstride,
+                                                          const double* __restrict__ rho, double scale, Sec s0,
+                                                          int S) {
+  extern __shared__ int shi[];
+  int* aidx = shi;                  // non-negligible pole indices (compacted), npoles
+  int* cpos = shi + npoles;         // close pairs before A position k, npoles
+  unsigned char* dfl = reinterpret_cast<unsigned char*>(shi + 2 * npoles);  // deflated flag per index
+  __shared__ int scan[kDeflThreads];
   const int b = blockIdx.x;
+  const int t = threadIdx.x, nt = blockDim.x;
   const Sec s = sec_at(s0, b, S);
   const double* v = val + (int64_t)b * vstride;
   const double* cp = cpl + (int64_t)b * cstride;
-  if (LDS) {
-    for (int i = threadIdx.x; i < npoles; i += blockDim.x) {
-      sh[i] = v[i];
-      sh[npoles + i] = cp[(int64_t)i * cinc];
-    }
-    __syncthreads();
-  }
-  if (threadIdx.x != 0) return;
   const double tol = 8.0 * kU * scale;
-  // a coupling is negligible when its contribution (times rho for a merge) is below tol
   const double cscale = rho ? fabs(rho[b]) : 1.0;
-  int np = 0, nr = 0, nd = 0;
-  int last = -1;         // row index of the last kept pole
-  double last_f = 0.0;   // its (rotated) coupling
-  double last_v = 0.0;
-  for (int i = 0; i < npoles; ++i) {
-    const double vi = LDS ? sh[i] : v[i];
-    double fi = LDS ? sh[npoles + i] : cp[(int64_t)i * cinc];
-    if (fabs(fi) * cscale <= tol) {
-      s.dval[nd] = vi;
-      s.didx[nd++] = i;
-      continue;
-    }
-    if (last >= 0 && vi - last_v <= tol) {
-      // rotate (last, i) so that the coupling of ``last`` vanishes; ``last`` deflates
-      const double r = hypot(last_f, fi);
-      const double c = fi / r, sn = last_f / r;
-      s.rot_i[nr] = last;
-      s.rot_j[nr] = i;
-      s.rot_c[nr] = c;
-      s.rot_s[nr++] = sn;
-      s.dval[nd] = last_v;
-      s.didx[nd++] = last;
-      --np;  // drop ``last`` from the kept poles
-      fi = r;
-    }
-    s.p[np] = vi;
-    s.w[np] = fi * fi;
-    s.idx[np] = i;
-    // the coupling sign is needed for the eigenvector signs: keep it in what
-    s.what[np] = fi;
-    ++np;
-    last = i;
-    last_f = fi;
-    last_v = vi;
+  auto f_of = [&](int i) { return cp[(int64_t)i * cinc]; };
+  // pass 1: negligible couplings; compaction of the others into aidx
+  const int ch = (npoles + nt - 1) / nt, i0 = min(npoles, t * ch), i1 = min(npoles, i0 + ch);
+  int cnt = 0;
+  for (int i = i0; i < i1; ++i) {
+    const bool neg = fabs(f_of(i)) * cscale <= tol;
+    dfl[i] = neg ? 1 : 0;
+    cnt += neg ? 0 : 1;
   }
-  s.cnt[0] = np;
-  s.cnt[1] = nr;
-  s.cnt[2] = nd;
+  int na;
+  int base = block_excl_scan(cnt, scan, &na);
+  for (int i = i0; i < i1; ++i)
+    if (!dfl[i]) aidx[base++] = i;
+  __syncthreads();
+  // pass 2: close pairs (k, k+1) of consecutive kept candidates
+  const int kc = (na + nt - 1) / nt, k0 = min(na, t * kc), k1 = min(na, k0 + kc);
+  auto close_at = [&](int k) { return k + 1 < na && v[aidx[k + 1]] - v[aidx[k]] <= tol; };
+  int ncl = 0;
+  for (int k = k0; k < k1; ++k) ncl += close_at(k) ? 1 : 0;
+  int nclose;
+  int cb = block_excl_scan(ncl, scan, &nclose);
+  for (int k = k0; k < k1; ++k) {
+    cpos[k] = cb;
+    if (close_at(k)) {
+      ++cb;
+      dfl[aidx[k]] = 1;
+    }
+  }
+  __syncthreads();
+  // kept poles (singletons here, run ends by their run's first member) and rotations
+  for (int k = k0; k < k1; ++k) {
+    const bool cl = close_at(k);
+    const bool prev_cl = k > 0 && close_at(k - 1);
+    if (!cl && !prev_cl) {
+      const int i = aidx[k], kp = k - cpos[k];
+      const double fi = f_of(i);
+      s.p[kp] = v[i];
+      s.w[kp] = fi * fi;
+      s.idx[kp] = i;
+      s.what[kp] = fi;  // the coupling sign is needed for the eigenvector signs
+    } else if (cl && !prev_cl) {
+      double last_f = f_of(aidx[k]);
+      int q = k;
+      while (close_at(q)) {
+        const double fn = f_of(aidx[q + 1]);
+        const double r = hypot(last_f, fn);
+        const int ri = cpos[q];
+        s.rot_i[ri] = aidx[q];
+        s.rot_j[ri] = aidx[q + 1];
+        s.rot_c[ri] = fn / r;
+        s.rot_s[ri] = last_f / r;
+        last_f = r;
+        ++q;
+      }
+      const int i = aidx[q], kp = q - cpos[q];
+      s.p[kp] = v[i];
+      s.w[kp] = last_f * last_f;
+      s.idx[kp] = i;
+      s.what[kp] = last_f;
+    }
+  }
+  // pass 3: deflated values in index order
+  int nd0 = 0;
+  for (int i = i0; i < i1; ++i) nd0 += dfl[i];
+  int nd;
+  int db = block_excl_scan(nd0, scan, &nd);
+  for (int i = i0; i < i1; ++i)
+    if (dfl[i]) {
+      s.dval[db] = v[i];
+      s.didx[db++] = i;
+    }
+  if (t == 0) {
+    s.cnt[0] = na - nclose;
+    s.cnt[1] = nclose;
+    s.cnt[2] = nd;
+  }
 }
 
 // secular functions in the shifted variable tau (lambda = p[o] + tau); one
@@ -165,6 +225,29 @@ __device__ double sec_eval(int np, const double* p, const double* w, int o, doub
   s = wave_sum64(s);
   if (ARROW) return (a_or_rho - po) - tau - s;  // decreasing in tau
   return 1.0 + a_or_rho * s;                    // increasing in tau (rho > 0)
+}
+
+// the secular function and its derivative in one pass
+template <bool ARROW>
+__device__ void sec_eval2(int np, const double* p, const double* w, int o, double tau, double a_or_rho,
+                          int lane, double& g, double& dg) {
+  const double po = p[o];
+  double s = 0.0, ds = 0.0;
+  for (int i = lane; i < np; i += 64) {
+    const double r = 1.0 / ((p[i] - po) - tau);
+    const double t = w[i] * r;
+    s += t;
+    ds += t * r;
+  }
+  s = wave_sum64(s);
+  ds = wave_sum64(ds);
+  if (ARROW) {
+    g = (a_or_rho - po) - tau - s;  // decreasing in tau
+    dg = -1.0 - ds;
+  } else {
+    g = 1.0 + a_or_rho * s;         // increasing in tau (rho > 0)
+    dg = a_or_rho * ds;
+  }
 }
 
 // roots: ARROW has n'+1 roots (one below p0, one per gap, one above), RANK1 has
@@ -226,17 +309,39 @@ __global__ __launch_bounds__(256) void k_roots(Sec s0, int S, const double* __re
       else { o = j + 1; lo = -0.5 * h; hi = 0.0; }
     }
   }
-  // bisection to floating-point resolution (all lanes take the same branches)
+  // Newton steps inside the bracket [lo, hi], which every evaluation shrinks.
+  // Near the pole the secular function behaves like c - w / tau, where Newton
+  // converges quadratically from the pole's far side and overshoots from the
+  // near side: a step that leaves the bracket, or one that is not at most half
+  // the previous step (no superlinear progress), is replaced by bisection.
+  // Ends when the step or the bracket reaches the rounding level of tau (all
+  // lanes take the same branches).
+  double tau = 0.5 * (lo + hi);
+  double prev_step = hi - lo;
   for (int it = 0; it < 200; ++it) {
+    double g, dg;
+    sec_eval2<ARROW>(np, p, w, o, tau, ar, lane, g, dg);
+    if (g == 0.0) {
+      lo = hi = tau;
+      break;
+    }
+    const bool right = ARROW ? (g > 0.0) : (g < 0.0);
+    if (right) lo = tau; else hi = tau;
     const double mid = 0.5 * (lo + hi);
     if (mid <= lo || mid >= hi) break;
-    const double g = sec_eval<ARROW>(np, p, w, o, mid, ar, lane);
-    const bool right = ARROW ? (g > 0.0) : (g < 0.0);
-    if (right) lo = mid; else hi = mid;
+    double tn = tau - g / dg;
+    if (!(tn > lo && tn < hi) || fabs(tn - tau) > 0.5 * prev_step) tn = mid;
+    const double step = fabs(tn - tau);
+    prev_step = step;
+    tau = tn;
+    if (step <= 2.0 * kU * fabs(tn)) {
+      lo = hi = tn;
+      break;
+    }
   }
   if (lane == 0) {
     s.ro[j] = o;
-    s.rt[j] = 0.5 * (lo + hi);
+    s.rt[j] = lo == hi ? lo : 0.5 * (lo + hi);
   }
 }
 
@@ -282,47 +387,20 @@ __global__ __launch_bounds__(256) void k_lowner(Sec s0, int S, const double* __r
 }
 
 // Ascending order of the eigenvalues: the secular roots (ascending by
-// construction) and the deflated values.  The deflated list is sorted first
-// (insertion sort in LDS by one thread: it is nearly sorted), then every
-// value finds its position by binary search in the other list (roots first on
-// ties).  Writes lam[position] and pos[source] = position, source = root r or
-// nroots + q for the q-th deflated value.
+// construction) and the deflated values (ascending: k_deflate writes them in
+// index order).  Every value finds its position by binary search in the other
+// list (roots first on ties).  Writes lam[position] and pos[source] =
+// position, source = root r or nroots + q for the q-th deflated value.
 template <bool ARROW>
 __global__ __launch_bounds__(256) void k_order(Sec s0, int S, double* __restrict__ lam, int64_t lstride,
                                                int* __restrict__ pos, int64_t pstride) {
-  extern __shared__ double sh[];
   const int b = blockIdx.x;
   const Sec s = sec_at(s0, b, S);
   const int np = s.cnt[0], nd = s.cnt[2];
   const int nroots = ARROW ? np + 1 : np;
-  double* dv = sh;
-  int* di = reinterpret_cast<int*>(sh + nd);
-  for (int q = threadIdx.x; q < nd; q += blockDim.x) {
-    dv[q] = s.dval[q];
-    di[q] = s.didx[q];
-  }
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    for (int a = 1; a < nd; ++a) {
-      const double v = dv[a];
-      const int id = di[a];
-      int c = a - 1;
-      while (c >= 0 && dv[c] > v) {
-        dv[c + 1] = dv[c];
-        di[c + 1] = di[c];
-        --c;
-      }
-      dv[c + 1] = v;
-      di[c + 1] = id;
-    }
-  }
-  __syncthreads();
+  const double* dv = s.dval;
   double* lb = lam + (int64_t)b * lstride;
   int* pb = pos + (int64_t)b * pstride;
-  for (int q = threadIdx.x; q < nd; q += blockDim.x) {
-    s.dval[q] = dv[q];
-    s.didx[q] = di[q];
-  }
   for (int r = threadIdx.x; r < nroots; r += blockDim.x) {
     const double v = root_val(s, r);
     int lo = 0, hi = nd;  // number of deflated values < v
@@ -416,105 +494,122 @@ __global__ void k_unrotate(Sec s0, int S, double* __restrict__ x, int64_t xstrid
 // tears, leaves, merges
 // -------------------------------------------------------------------------
 
-// SVD of a d x d matrix g (column-major) by one-sided Jacobi: g = P S Q^T.
+// SVD of a D x D matrix g (column-major) by one-sided Jacobi: g = P S Q^T.
 // Columns of P with s = 0 are returned as zero (their rank-one update has
-// rho = 0 and deflates whatever its coupling).
-__device__ void svd_small(int d, const double* g, double* pm, double* sv, double* qm) {
-  double a[kMaxD * kMaxD], v[kMaxD * kMaxD];
-  for (int i = 0; i < d * d; ++i) a[i] = g[i];
-  for (int c = 0; c < d; ++c)
-    for (int r = 0; r < d; ++r) v[r + c * d] = r == c ? 1.0 : 0.0;
+// rho = 0 and deflates whatever its coupling).  D is a template parameter so
+// that the unrolled loops keep the matrices in registers.
+template <int D>
+__device__ void svd_small(const double* g, double* pm, double* sv, double* qm) {
+  double a[D * D], v[D * D];
+#pragma unroll
+  for (int i = 0; i < D * D; ++i) {
+    a[i] = g[i];
+    v[i] = (i % D) == (i / D) ? 1.0 : 0.0;
+  }
   for (int sweep = 0; sweep < 40; ++sweep) {
     bool rotated = false;
-    for (int k = 0; k < d - 1; ++k)
-      for (int l = k + 1; l < d; ++l) {
+#pragma unroll
+    for (int k = 0; k < D - 1; ++k)
+#pragma unroll
+      for (int l = k + 1; l < D; ++l) {
         double al = 0.0, be = 0.0, ga = 0.0;
-        for (int r = 0; r < d; ++r) {
-          al += a[r + k * d] * a[r + k * d];
-          be += a[r + l * d] * a[r + l * d];
-          ga += a[r + k * d] * a[r + l * d];
+#pragma unroll
+        for (int r = 0; r < D; ++r) {
+          al += a[r + k * D] * a[r + k * D];
+          be += a[r + l * D] * a[r + l * D];
+          ga += a[r + k * D] * a[r + l * D];
         }
-        if (fabs(ga) <= 1e-17 * sqrt(al * be) || ga == 0.0) continue;
-        rotated = true;
-        const double ze = (be - al) / (2.0 * ga);
-        const double t = (ze >= 0.0 ? 1.0 : -1.0) / (fabs(ze) + sqrt(1.0 + ze * ze));
-        const double c = 1.0 / sqrt(1.0 + t * t), sn = c * t;
-        for (int r = 0; r < d; ++r) {
-          const double x = a[r + k * d], y = a[r + l * d];
-          a[r + k * d] = c * x - sn * y;
-          a[r + l * d] = sn * x + c * y;
-          const double vx = v[r + k * d], vy = v[r + l * d];
-          v[r + k * d] = c * vx - sn * vy;
-          v[r + l * d] = sn * vx + c * vy;
+        if (ga != 0.0 && fabs(ga) > 4.0 * kU * sqrt(al * be)) {
+          rotated = true;
+          const double ze = (be - al) / (2.0 * ga);
+          const double t = (ze >= 0.0 ? 1.0 : -1.0) / (fabs(ze) + sqrt(1.0 + ze * ze));
+          const double c = 1.0 / sqrt(1.0 + t * t), sn = c * t;
+#pragma unroll
+          for (int r = 0; r < D; ++r) {
+            const double x = a[r + k * D], y = a[r + l * D];
+            a[r + k * D] = c * x - sn * y;
+            a[r + l * D] = sn * x + c * y;
+            const double vx = v[r + k * D], vy = v[r + l * D];
+            v[r + k * D] = c * vx - sn * vy;
+            v[r + l * D] = sn * vx + c * vy;
+          }
         }
       }
     if (!rotated) break;
   }
-  for (int k = 0; k < d; ++k) {
+#pragma unroll
+  for (int k = 0; k < D; ++k) {
     double nr = 0.0;
-    for (int r = 0; r < d; ++r) nr += a[r + k * d] * a[r + k * d];
+#pragma unroll
+    for (int r = 0; r < D; ++r) nr += a[r + k * D] * a[r + k * D];
     nr = sqrt(nr);
     sv[k] = nr;
-    for (int r = 0; r < d; ++r) {
-      pm[r + k * d] = nr > 0.0 ? a[r + k * d] / nr : 0.0;
-      qm[r + k * d] = v[r + k * d];
+#pragma unroll
+    for (int r = 0; r < D; ++r) {
+      pm[r + k * D] = nr > 0.0 ? a[r + k * D] / nr : 0.0;
+      qm[r + k * D] = v[r + k * D];
     }
   }
 }
 
-// Eigen-decomposition of a symmetric d x d matrix (cyclic Jacobi), eigenvalues
-// ascending with their vectors.
-__device__ void eig_small(int d, double* a, double* lam, double* u) {
-  double v[kMaxD * kMaxD];
-  for (int c = 0; c < d; ++c)
-    for (int r = 0; r < d; ++r) v[r + c * d] = r == c ? 1.0 : 0.0;
+// Eigen-decomposition of a symmetric D x D matrix (cyclic Jacobi), eigenvalues
+// ascending with their vectors (u column-major).
+template <int D>
+__device__ void eig_small(double (&a)[D * D], double* lam, double* u) {
+  double v[D * D];
+#pragma unroll
+  for (int i = 0; i < D * D; ++i) v[i] = (i % D) == (i / D) ? 1.0 : 0.0;
   for (int sweep = 0; sweep < 50; ++sweep) {
     double off = 0.0, tot = 0.0;
-    for (int c = 0; c < d; ++c)
-      for (int r = 0; r < d; ++r) {
-        tot += a[r + c * d] * a[r + c * d];
-        if (r != c) off += a[r + c * d] * a[r + c * d];
-      }
-    if (off <= 1e-34 * tot || off == 0.0) break;
-    for (int k = 0; k < d - 1; ++k)
-      for (int l = k + 1; l < d; ++l) {
-        const double akl = a[k + l * d];
-        if (akl == 0.0) continue;
-        const double th = (a[l + l * d] - a[k + k * d]) / (2.0 * akl);
-        const double t = (th >= 0.0 ? 1.0 : -1.0) / (fabs(th) + sqrt(1.0 + th * th));
-        const double c = 1.0 / sqrt(1.0 + t * t), sn = c * t;
-        // A <- J^T A J with J the rotation in the plane (k, l)
-        for (int r = 0; r < d; ++r) {
-          const double x = a[r + k * d], y = a[r + l * d];
-          a[r + k * d] = c * x - sn * y;
-          a[r + l * d] = sn * x + c * y;
-        }
-        for (int r = 0; r < d; ++r) {
-          const double x = a[k + r * d], y = a[l + r * d];
-          a[k + r * d] = c * x - sn * y;
-          a[l + r * d] = sn * x + c * y;
-        }
-        for (int r = 0; r < d; ++r) {
-          const double x = v[r + k * d], y = v[r + l * d];
-          v[r + k * d] = c * x - sn * y;
-          v[r + l * d] = sn * x + c * y;
-        }
-      }
-  }
-  int ord[kMaxD];
-  for (int i = 0; i < d; ++i) ord[i] = i;
-  for (int i = 1; i < d; ++i) {
-    const int o = ord[i];
-    int j = i - 1;
-    while (j >= 0 && a[ord[j] + ord[j] * d] > a[o + o * d]) {
-      ord[j + 1] = ord[j];
-      --j;
+#pragma unroll
+    for (int i = 0; i < D * D; ++i) {
+      tot += a[i] * a[i];
+      if ((i % D) != (i / D)) off += a[i] * a[i];
     }
-    ord[j + 1] = o;
+    if (off == 0.0 || off <= 16.0 * kU * kU * tot) break;
+#pragma unroll
+    for (int k = 0; k < D - 1; ++k)
+#pragma unroll
+      for (int l = k + 1; l < D; ++l) {
+        const double akl = a[k + l * D];
+        if (akl != 0.0) {
+          const double th = (a[l + l * D] - a[k + k * D]) / (2.0 * akl);
+          const double t = (th >= 0.0 ? 1.0 : -1.0) / (fabs(th) + sqrt(1.0 + th * th));
+          const double c = 1.0 / sqrt(1.0 + t * t), sn = c * t;
+          // A <- J^T A J with J the rotation in the plane (k, l)
+#pragma unroll
+          for (int r = 0; r < D; ++r) {
+            const double x = a[r + k * D], y = a[r + l * D];
+            a[r + k * D] = c * x - sn * y;
+            a[r + l * D] = sn * x + c * y;
+          }
+#pragma unroll
+          for (int r = 0; r < D; ++r) {
+            const double x = a[k + r * D], y = a[l + r * D];
+            a[k + r * D] = c * x - sn * y;
+            a[l + r * D] = sn * x + c * y;
+          }
+#pragma unroll
+          for (int r = 0; r < D; ++r) {
+            const double x = v[r + k * D], y = v[r + l * D];
+            v[r + k * D] = c * x - sn * y;
+            v[r + l * D] = sn * x + c * y;
+          }
+        }
+      }
   }
-  for (int i = 0; i < d; ++i) {
-    lam[i] = a[ord[i] + ord[i] * d];
-    for (int r = 0; r < d; ++r) u[r + i * d] = v[r + ord[i] * d];
+  // selection order of the diagonal (D is small), ties by index
+#pragma unroll
+  for (int i = 0; i < D; ++i) {
+    int rank = 0;
+#pragma unroll
+    for (int j = 0; j < D; ++j) {
+      const double aj = a[j + j * D], ai = a[i + i * D];
+      rank += (aj < ai || (aj == ai && j < i)) ? 1 : 0;
+    }
+    lam[rank] = a[i + i * D];
+#pragma unroll
+    for (int r = 0; r < D; ++r) u[r + rank * D] = v[r + i * D];
   }
 }
 
@@ -522,21 +617,24 @@ __device__ void eig_small(int d, double* a, double* lam, double* u) {
 // coupling between chain blocks t and t+1; chain block 0 is the first block
 // listed in gam (gam + t d^2 is the coupling of chain blocks t, t+1).
 // Slots t >= nreal are decoupled padding: S = 0, P = 0, Q = I.
-__global__ void k_tear(int d, int nslots, int nreal, const double* __restrict__ gam, double* __restrict__ pm,
+template <int D>
+__global__ __launch_bounds__(64) void k_tear(int nslots, int nreal, const double* __restrict__ gam, double* __restrict__ pm,
                        double* __restrict__ sv, double* __restrict__ qm) {
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= nslots) return;
-  double* p = pm + (int64_t)t * d * d;
-  double* q = qm + (int64_t)t * d * d;
-  double* s = sv + (int64_t)t * d;
+  double* p = pm + (int64_t)t * D * D;
+  double* q = qm + (int64_t)t * D * D;
+  double* s = sv + (int64_t)t * D;
   if (t < nreal) {
-    svd_small(d, gam + (int64_t)t * d * d, p, s, q);
+    svd_small<D>(gam + (int64_t)t * D * D, p, s, q);
   } else {
-    for (int c = 0; c < d; ++c) {
+#pragma unroll
+    for (int c = 0; c < D; ++c) {
       s[c] = 0.0;
-      for (int r = 0; r < d; ++r) {
-        p[r + c * d] = 0.0;
-        q[r + c * d] = r == c ? 1.0 : 0.0;
+#pragma unroll
+      for (int r = 0; r < D; ++r) {
+        p[r + c * D] = 0.0;
+        q[r + c * D] = r == c ? 1.0 : 0.0;
       }
     }
   }
@@ -547,44 +645,52 @@ __global__ void k_tear(int d, int nslots, int nreal, const double* __restrict__ 
 // tear above it (slot toff + t - 1, which for t = 0 exists only when toff =
 // 1: the tear between the arrowhead and the tail).  Blocks t >= nb are
 // decoupled padding with eigenvalues big + t d + i.
-__global__ void k_leaf(int d, int nb, int nb2, int toff, double big, const double* __restrict__ xi0,
+template <int D>
+__global__ __launch_bounds__(64) void k_leaf(int nb, int nb2, int toff, double big, const double* __restrict__ xi0,
                        const double* __restrict__ pm, const double* __restrict__ sv,
                        const double* __restrict__ qm, double* __restrict__ lam, double* __restrict__ u) {
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= nb2) return;
-  double* lt = lam + (int64_t)t * d;
-  double* ut = u + (int64_t)t * d * d;
+  double* lt = lam + (int64_t)t * D;
+  double* ut = u + (int64_t)t * D * D;
   if (t >= nb) {
-    for (int c = 0; c < d; ++c) {
-      lt[c] = big + (double)(t * d + c);
-      for (int r = 0; r < d; ++r) ut[r + c * d] = r == c ? 1.0 : 0.0;
+#pragma unroll
+    for (int c = 0; c < D; ++c) {
+      lt[c] = big + (double)(t * D + c);
+#pragma unroll
+      for (int r = 0; r < D; ++r) ut[r + c * D] = r == c ? 1.0 : 0.0;
     }
     return;
   }
-  double a[kMaxD * kMaxD];
-  for (int i = 0; i < d * d; ++i) a[i] = xi0[(int64_t)t * d * d + i];
+  double a[D * D];
+#pragma unroll
+  for (int i = 0; i < D * D; ++i) a[i] = xi0[(int64_t)t * D * D + i];
   const int below = toff + t, above = toff + t - 1;
   if (t < nb - 1) {
-    const double* q = qm + (int64_t)below * d * d;
-    const double* s = sv + (int64_t)below * d;
-    for (int c = 0; c < d; ++c)
-      for (int r = 0; r < d; ++r) {
-        double acc = 0.0;
-        for (int k = 0; k < d; ++k) acc += q[r + k * d] * s[k] * q[c + k * d];
-        a[r + c * d] -= acc;
-      }
+    const double* q = qm + (int64_t)below * D * D;
+    const double* s = sv + (int64_t)below * D;
+#pragma unroll
+    for (int k = 0; k < D; ++k) {
+      const double sk = s[k];
+#pragma unroll
+      for (int c = 0; c < D; ++c)
+#pragma unroll
+        for (int r = 0; r < D; ++r) a[r + c * D] -= q[r + k * D] * sk * q[c + k * D];
+    }
   }
   if (above >= 0) {
-    const double* p = pm + (int64_t)above * d * d;
-    const double* s = sv + (int64_t)above * d;
-    for (int c = 0; c < d; ++c)
-      for (int r = 0; r < d; ++r) {
-        double acc = 0.0;
-        for (int k = 0; k < d; ++k) acc += p[r + k * d] * s[k] * p[c + k * d];
-        a[r + c * d] -= acc;
-      }
+    const double* p = pm + (int64_t)above * D * D;
+    const double* s = sv + (int64_t)above * D;
+#pragma unroll
+    for (int k = 0; k < D; ++k) {
+      const double sk = s[k];
+#pragma unroll
+      for (int c = 0; c < D; ++c)
+#pragma unroll
+        for (int r = 0; r < D; ++r) a[r + c * D] -= p[r + k * D] * sk * p[c + k * D];
+    }
   }
-  eig_small(d, a, lt, ut);
+  eig_small<D>(a, lt, ut);
 }
 
 // arrow tip block X = Xi_{l0+1} - Q S Q^T of the tear with the tail (slot 0)
@@ -765,21 +871,17 @@ void secular(nsp_ctx* c, Sec sec, int S, int nbat, int m, const double* vals, in
   const int nroots = ARROW ? m + 1 : m;
   const size_t lds2 = sizeof(double) * 2 * (size_t)m;
   const bool lds = lds2 <= (size_t)kLdsBytes;
-  if (lds)
-    k_deflate<true><<<nbat, 256, lds2, c->stream>>>(m, vals, vstride, cpl, cinc, cstride,
-                                                    ARROW ? nullptr : a_or_rho, scale, sec, S);
-  else
-    k_deflate<false><<<nbat, 256, 0, c->stream>>>(m, vals, vstride, cpl, cinc, cstride,
-                                                  ARROW ? nullptr : a_or_rho, scale, sec, S);
+  const size_t lds_d = (2 * sizeof(int) + 1) * (size_t)m + 16;
+  if (lds_d > (size_t)kLdsBytes) throw Error(NSP_ERR_ARG, "restart matrix too large for the eigensolver");
+  k_deflate<<<nbat, kDeflThreads, lds_d, c->stream>>>(m, vals, vstride, cpl, cinc, cstride,
+                                                      ARROW ? nullptr : a_or_rho, scale, sec, S);
   const dim3 gr(nb(nroots, 4), nbat);
   if (lds)
     k_roots<ARROW, true><<<gr, 256, lds2, c->stream>>>(sec, S, a_or_rho, -bound, bound);
   else
     k_roots<ARROW, false><<<gr, 256, 0, c->stream>>>(sec, S, a_or_rho, -bound, bound);
   k_lowner<ARROW><<<dim3(nb(m, 4), nbat), 256, 0, c->stream>>>(sec, S, a_or_rho);
-  const size_t lds_o = (sizeof(double) + sizeof(int)) * (size_t)(m + 1);
-  if (lds_o > (size_t)kLdsBytes) throw Error(NSP_ERR_ARG, "restart matrix too large for the eigensolver");
-  k_order<ARROW><<<nbat, 256, lds_o, c->stream>>>(sec, S, lam, lstride, pos, pstride);
+  k_order<ARROW><<<nbat, 256, 0, c->stream>>>(sec, S, lam, lstride, pos, pstride);
   const int xc = ARROW ? m + 1 : m;
   if (nbat == 1 || xstride == (int64_t)ldx * xc) {
     NSP_HIP(hipMemsetAsync(x, 0, sizeof(double) * (size_t)ldx * xc * nbat, c->stream));
@@ -855,7 +957,13 @@ void eig_restart(nsp_ctx* c, EigWork& w, int K, int d, int kk, double norm_t, co
     // slot 0 (arrow case): Gamma_{l0+1}; tail slots: Gamma_{jb0 + t}
     const int nreal = arrow ? nbt : std::max(nbt - 1, 0);  // couplings present in gam
     const double* g0 = gam + (int64_t)(arrow ? l0 + 1 : 1) * d * d;
-    k_tear<<<nb(nslots, 64), 64, 0, c->stream>>>(d, nslots, nreal, g0, pm, sv, qm);
+    switch (d) {
+      case 1: k_tear<1><<<nb(nslots, 64), 64, 0, c->stream>>>(nslots, nreal, g0, pm, sv, qm); break;
+      case 2: k_tear<2><<<nb(nslots, 64), 64, 0, c->stream>>>(nslots, nreal, g0, pm, sv, qm); break;
+      case 4: k_tear<4><<<nb(nslots, 64), 64, 0, c->stream>>>(nslots, nreal, g0, pm, sv, qm); break;
+      case 8: k_tear<8><<<nb(nslots, 64), 64, 0, c->stream>>>(nslots, nreal, g0, pm, sv, qm); break;
+      default: throw Error(NSP_ERR_ARG, "eig_restart: d must be 1, 2, 4 or 8");
+    }
     NSP_HIP(hipGetLastError());
   }
 
@@ -869,8 +977,14 @@ void eig_restart(nsp_ctx* c, EigWork& w, int K, int d, int kk, double norm_t, co
     double* lcur = lamb[0];
     double* lnext = lamb[1];
     double* ltmp = lamb[2];
-    k_leaf<<<nb(nb2, 64), 64, 0, c->stream>>>(d, nbt, nb2, toff, big, xi + (int64_t)jb0 * d * d, pm, sv, qm,
-                                              lcur, gcur);
+    const double* xi0 = xi + (int64_t)jb0 * d * d;
+    switch (d) {
+      case 1: k_leaf<1><<<nb(nb2, 64), 64, 0, c->stream>>>(nbt, nb2, toff, big, xi0, pm, sv, qm, lcur, gcur); break;
+      case 2: k_leaf<2><<<nb(nb2, 64), 64, 0, c->stream>>>(nbt, nb2, toff, big, xi0, pm, sv, qm, lcur, gcur); break;
+      case 4: k_leaf<4><<<nb(nb2, 64), 64, 0, c->stream>>>(nbt, nb2, toff, big, xi0, pm, sv, qm, lcur, gcur); break;
+      case 8: k_leaf<8><<<nb(nb2, 64), 64, 0, c->stream>>>(nbt, nb2, toff, big, xi0, pm, sv, qm, lcur, gcur); break;
+      default: throw Error(NSP_ERR_ARG, "eig_restart: d must be 1, 2, 4 or 8");
+    }
     NSP_HIP(hipGetLastError());
     for (int gs = d, lev = 0; gs < m2p; gs *= 2, ++lev) {
       const int m = 2 * gs, npair = m2p / m;

@@ -805,38 +805,18 @@ __global__ __launch_bounds__(256) void k_ts_gramfin(const int* cond, int nparts,
 }
 
 // C = C R^{-1} (NC columns), written back to the arrays and, if z0 is given,
-// to NC consecutive basis columns starting at z0.  With FUSED the block first
-// reduces the Gram partials of k_ts_nn_v itself and factors them (NC <= 8);
-// block 0 then stores R^{-1} and R in rinv.  Otherwise rinv comes from
-// k_ts_gramfin.
-template <typename VT, int DA, int NA, bool FUSED>
+// to NC consecutive basis columns starting at z0; R^{-1} comes from
+// k_ts_gramfin (one block reduces the Gram partials and factors them once).
+template <typename VT, int DA, int NA>
 __global__ __launch_bounds__(kThreads) void k_ts_scale(const int* cond, int64_t n,
                                                        CPair<VT, DA, NA> cc,
-                                                       const double* __restrict__ part_c,
-                                                       int nparts, double* rinv,
-                                                       VT* __restrict__ z0, int64_t ldz,
-                                                       int* flags) {
+                                                       const double* __restrict__ rinv,
+                                                       VT* __restrict__ z0, int64_t ldz) {
   constexpr int NC = DA * NA;
   constexpr int NV = NC * NC;
   if (cond && *cond == 0) return;
   __shared__ double ri[NV];
-  if constexpr (FUSED) {
-    __shared__ double smem[kThreads];
-    __shared__ double res[NV];
-    reduce_partials<NV>(part_c, nparts, res, smem);
-    if (threadIdx.x == 0) {
-      double r[NV], rv[NV];
-      const bool ok = chol_upper_inv(NC, res, r, rv);
-      for (int i = 0; i < NV; ++i) ri[i] = rv[i];
-      if (blockIdx.x == 0) {
-        if (!ok) atomicOr(flags + 1, 1);
-        if (cond && !kahan_parlett_ok(NC, res)) atomicOr(flags + 1, 2);
-        for (int i = 0; i < NV; ++i) { rinv[i] = rv[i]; rinv[NV + i] = r[i]; }
-      }
-    }
-  } else {
-    if (threadIdx.x < NV) ri[threadIdx.x] = rinv[threadIdx.x];
-  }
+  if (threadIdx.x < NV) ri[threadIdx.x] = rinv[threadIdx.x];
   __syncthreads();
   for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < n;
        r += (int64_t)gridDim.x * blockDim.x) {
@@ -1165,9 +1145,10 @@ static void ts_proj_t(nsp_ctx* c, const int* cond, int64_t n, const VT* z, int64
   if (ev_red) NSP_HIP(hipEventRecord(ev_red, c->stream));
   if constexpr (NC <= 8) {
     constexpr int nt = ts_nn_waves<VT, NC>() * kWave;
-    if (gram)
+    if (gram) {
       k_ts_nn_v<VT, DA, NA, true><<<nnblocks, nt, 0, c->stream>>>(cond, n, z, ldz, k, h, cc, part_c);
-    else if (k > 0)
+      k_ts_gramfin<NC><<<1, 256, 0, c->stream>>>(cond, (int)nnblocks, part_c, rinv, c->flags.as<int>());
+    } else if (k > 0)
       k_ts_nn_v<VT, DA, NA, false><<<nnblocks, nt, 0, c->stream>>>(cond, n, z, ldz, k, h, cc,
                                                                    nullptr);
   } else {
@@ -1189,15 +1170,9 @@ static void ts_scale_t(nsp_ctx* c, const int* cond, int64_t n, VT* a0, VT* a1, c
                        double* rinv, VT* z0, int64_t ldz) {
   constexpr int NC = DA * NA;
   CPair<VT, DA, NA> cc{a0, a1};
-  constexpr int TR = ts_nn_rows<VT, NC>();
-  const int nparts = (int)((n + TR - 1) / TR);
+  (void)part_c;  // the Gram partials were reduced by k_ts_gramfin
   const unsigned grid = cap_grid(n, kThreads, 2048);
-  if constexpr (NC <= 8)
-    k_ts_scale<VT, DA, NA, true><<<grid, kThreads, 0, c->stream>>>(cond, n, cc, part_c, nparts, rinv,
-                                                                   z0, ldz, c->flags.as<int>());
-  else
-    k_ts_scale<VT, DA, NA, false><<<grid, kThreads, 0, c->stream>>>(cond, n, cc, part_c, nparts, rinv,
-                                                                    z0, ldz, c->flags.as<int>());
+  k_ts_scale<VT, DA, NA><<<grid, kThreads, 0, c->stream>>>(cond, n, cc, rinv, z0, ldz);
   NSP_HIP(hipGetLastError());
 }
 
