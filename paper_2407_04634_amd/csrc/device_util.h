@@ -59,7 +59,15 @@ __device__ __forceinline__ void reduce_partials(const double* __restrict__ part,
   double s = 0.0;
   if (t < groups * NV) {
     const int v = t % NV, g = t / NV;
-    for (int b = g; b < nparts; b += groups) s += part[(size_t)b * NV + v];
+    // eight independent partial sums keep eight loads in flight per thread
+    double acc[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    int b = g;
+    for (; b + 7 * groups < nparts; b += 8 * groups) {
+#pragma unroll
+      for (int u = 0; u < 8; ++u) acc[u] += part[(size_t)(b + u * groups) * NV + v];
+    }
+    for (int u = 0; b < nparts; b += groups, ++u) acc[u & 7] += part[(size_t)b * NV + v];
+    s = ((acc[0] + acc[1]) + (acc[2] + acc[3])) + ((acc[4] + acc[5]) + (acc[6] + acc[7]));
   }
   smem[t] = s;
   __syncthreads();

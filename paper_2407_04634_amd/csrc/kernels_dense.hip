@@ -25,43 +25,61 @@ static inline unsigned cap_grid(int64_t work, int per, int cap) {
 // G (k x k, column-major, symmetric positive definite) = R^T R, R upper.
 // Writes R and R^{-1}; returns false if a pivot is not positive relative to
 // the largest diagonal entry (rank loss) or not finite.
-__device__ bool chol_upper_inv(int k, const double* g, double* r, double* ri) {
+// K is a template parameter so that the unrolled loops keep R and R^{-1} in
+// registers (with a runtime size they go to per-lane scratch memory).
+template <int K>
+__device__ bool chol_upper_inv(const double* g, double* r, double* ri) {
   double gmax = 0.0;
-  for (int i = 0; i < k; ++i) gmax = fmax(gmax, g[i + i * k]);
+#pragma unroll
+  for (int i = 0; i < K; ++i) gmax = fmax(gmax, g[i + i * K]);
   bool ok = isfinite(gmax) && gmax > 0.0;
-  for (int i = 0; i < k * k; ++i) { r[i] = 0.0; ri[i] = 0.0; }
-  for (int j = 0; j < k && ok; ++j) {
+#pragma unroll
+  for (int i = 0; i < K * K; ++i) { r[i] = 0.0; ri[i] = 0.0; }
+#pragma unroll
+  for (int j = 0; j < K; ++j) {
+#pragma unroll
     for (int i = 0; i <= j; ++i) {
-      double s = g[i + j * k];
-      for (int l = 0; l < i; ++l) s -= r[l + i * k] * r[l + j * k];
+      double s = g[i + j * K];
+#pragma unroll
+      for (int l = 0; l < i; ++l) s -= r[l + i * K] * r[l + j * K];
       if (i == j) {
-        if (!(s > 1e-24 * gmax) || !isfinite(s)) { ok = false; break; }
-        r[j + j * k] = sqrt(s);
+        if (!(s > 1e-24 * gmax) || !isfinite(s)) {
+          ok = false;  // rank loss: finish with a dummy pivot, the result is replaced below
+          s = 1.0;
+        }
+        r[j + j * K] = sqrt(s);
       } else {
-        r[i + j * k] = s / r[i + i * k];
+        r[i + j * K] = s / r[i + i * K];
       }
     }
   }
   if (!ok) {
-    for (int i = 0; i < k * k; ++i) { r[i] = 0.0; ri[i] = 0.0; }
-    for (int i = 0; i < k; ++i) { r[i + i * k] = 1.0; ri[i + i * k] = 1.0; }
+#pragma unroll
+    for (int i = 0; i < K * K; ++i) { r[i] = 0.0; ri[i] = 0.0; }
+#pragma unroll
+    for (int i = 0; i < K; ++i) { r[i + i * K] = 1.0; ri[i + i * K] = 1.0; }
     return false;
   }
   // inverse of the upper triangular R, column by column
-  for (int j = 0; j < k; ++j) {
-    ri[j + j * k] = 1.0 / r[j + j * k];
+#pragma unroll
+  for (int j = 0; j < K; ++j) {
+    ri[j + j * K] = 1.0 / r[j + j * K];
+#pragma unroll
     for (int i = j - 1; i >= 0; --i) {
       double s = 0.0;
-      for (int l = i + 1; l <= j; ++l) s += r[i + l * k] * ri[l + j * k];
-      ri[i + j * k] = -s / r[i + i * k];
+#pragma unroll
+      for (int l = i + 1; l <= j; ++l) s += r[i + l * K] * ri[l + j * K];
+      ri[i + j * K] = -s / r[i + i * K];
     }
   }
   return true;
 }
 
-__device__ double fro(int k, const double* a) {
+template <int K>
+__device__ double fro(const double* a) {
   double s = 0.0;
-  for (int i = 0; i < k * k; ++i) s += a[i] * a[i];
+#pragma unroll
+  for (int i = 0; i < K * K; ++i) s += a[i] * a[i];
   return sqrt(s);
 }
 
@@ -249,14 +267,14 @@ __global__ __launch_bounds__(kThreads) void k_scale(int64_t n, const VT* p,
   reduce_partials<NV>(part_g, nparts, res, smem);
   if (threadIdx.x == 0) {
     double r[NV], rv[NV];
-    const bool ok = chol_upper_inv(D, res, r, rv);
+    const bool ok = chol_upper_inv<D>(res, r, rv);
     for (int i = 0; i < NV; ++i) ri[i] = rv[i];
-    gi_s = fro(D, rv);
+    gi_s = fro<D>(rv);
     if (blockIdx.x == 0) {
       if (!ok) atomicOr(flags + 1, 1);
       if (gam_out)
         for (int i = 0; i < NV; ++i) gam_out[i] = r[i];
-      if (nrm_gam) *nrm_gam = fro(D, r);
+      if (nrm_gam) *nrm_gam = fro<D>(r);
       if (nrm_ginv) *nrm_ginv = gi_s;
     }
   }
@@ -320,7 +338,7 @@ __global__ __launch_bounds__(kThreads) void k_scale2(int64_t n, const double* __
   reduce_partials<NV>(part_g2, nparts, res, smem);
   if (threadIdx.x == 0) {
     double r2[NV], r2i[NV];
-    const bool ok = chol_upper_inv(D, res, r2, r2i);
+    const bool ok = chol_upper_inv<D>(res, r2, r2i);
     for (int i = 0; i < NV; ++i) ri[i] = r2i[i];
     if (blockIdx.x == 0) {
       if (!ok) atomicOr(flags + 1, 1);
@@ -328,18 +346,25 @@ __global__ __launch_bounds__(kThreads) void k_scale2(int64_t n, const double* __
         double g0[NV], g0i[NV], gn[NV], gni[NV];
         for (int i = 0; i < NV; ++i) g0[i] = gam[i];
         // inverse of the upper triangular old Gamma
+#pragma unroll
         for (int i = 0; i < NV; ++i) g0i[i] = 0.0;
+#pragma unroll
         for (int j = 0; j < D; ++j) {
           g0i[j + j * D] = 1.0 / g0[j + j * D];
+#pragma unroll
           for (int i = j - 1; i >= 0; --i) {
             double s = 0.0;
+#pragma unroll
             for (int l = i + 1; l <= j; ++l) s += g0[i + l * D] * g0i[l + j * D];
             g0i[i + j * D] = -s / g0[i + i * D];
           }
         }
+#pragma unroll
         for (int i = 0; i < D; ++i)
+#pragma unroll
           for (int j = 0; j < D; ++j) {
             double s = 0.0, t = 0.0;
+#pragma unroll
             for (int l = 0; l < D; ++l) {
               s += r2[i + l * D] * g0[l + j * D];
               t += g0i[i + l * D] * r2i[l + j * D];
@@ -348,8 +373,8 @@ __global__ __launch_bounds__(kThreads) void k_scale2(int64_t n, const double* __
             gni[i + j * D] = t;
           }
         for (int i = 0; i < NV; ++i) gam[i] = gn[i];
-        if (nrm_gam) *nrm_gam = fro(D, gn);
-        gi_s = fro(D, gni);
+        if (nrm_gam) *nrm_gam = fro<D>(gn);
+        gi_s = fro<D>(gni);
         if (nrm_ginv) *nrm_ginv = gi_s;
       }
     }
@@ -798,7 +823,7 @@ __global__ __launch_bounds__(256) void k_ts_gramfin(const int* cond, int nparts,
   reduce_partials<NV>(part_c, nparts, res, smem);
   if (threadIdx.x == 0) {
     double r[NV], ri[NV];
-    if (!chol_upper_inv(NC, res, r, ri)) atomicOr(flags + 1, 1);
+    if (!chol_upper_inv<NC>(res, r, ri)) atomicOr(flags + 1, 1);
     if (cond && !kahan_parlett_ok(NC, res)) atomicOr(flags + 1, 2);
     for (int i = 0; i < NV; ++i) { rinv[i] = ri[i]; rinv[NV + i] = r[i]; }
   }
