@@ -208,13 +208,34 @@ __global__ __launch_bounds__(kDeflThreads) void k_deflate(int npoles, const doub
   }
 }
 
+// Sum over a wavefront, returned in every lane, with DPP lane moves (a few
+// cycles each) instead of LDS permutes: within each row of 16 lanes an
+// inclusive scan by row shifts 1, 2, 4, 8; then the row broadcasts of lanes 15
+// and 31 carry the row totals up, so lane 63 holds the wavefront's sum, which
+// readlane broadcasts.  The wavefront must be converged.
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ double dpp_move(double v) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)b, CTRL, ROW_MASK, 0xF, true);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, ROW_MASK, 0xF, true);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+__device__ __forceinline__ double wave_sum64(double v) {
+  v += dpp_move<0x111, 0xF>(v);  // row_shr:1
+  v += dpp_move<0x112, 0xF>(v);  // row_shr:2
+  v += dpp_move<0x114, 0xF>(v);  // row_shr:4
+  v += dpp_move<0x118, 0xF>(v);  // row_shr:8
+  v += dpp_move<0x142, 0xA>(v);  // row_bcast:15 into rows 1 and 3
+  v += dpp_move<0x143, 0xC>(v);  // row_bcast:31 into rows 2 and 3
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane((int)b, 63);
+  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), 63);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
 // secular functions in the shifted variable tau (lambda = p[o] + tau); one
 // wavefront evaluates the sum, every lane returns the same value
-__device__ __forceinline__ double wave_sum64(double v) {
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-  return v;
-}
 
 template <bool ARROW>
 __device__ double sec_eval(int np, const double* p, const double* w, int o, double tau, double a_or_rho,
@@ -317,6 +338,72 @@ __global__ __launch_bounds__(256) void k_roots(Sec s0, int S, const double* __re
   // Ends when the step or the bracket reaches the rounding level of tau (all
   // lanes take the same branches).
   double tau = 0.5 * (lo + hi);
+  if (!ARROW && j < np - 1) {
+    // Interior root of a rank-one update: the sum is split at the root's
+    // interval into psi (poles j and below) and phi (poles j+1 and above),
+    // each modelled by one pole plus a constant fitted to its value and
+    // derivative (the "middle way" of rational secular solvers); the model's
+    // root in the interval comes from a quadratic.  Bisection when the model
+    // step leaves the bracket.
+    const double po = p[o];
+    const double dl = p[j] - po, dr = p[j + 1] - po;
+    for (int it = 0; it < 200; ++it) {
+      double ps = 0.0, dps = 0.0, ph = 0.0, dph = 0.0;
+      for (int i = lane; i < np; i += 64) {
+        const double r = 1.0 / ((p[i] - po) - tau);
+        const double t = w[i] * r;
+        if (i <= j) { ps += t; dps += t * r; }
+        else { ph += t; dph += t * r; }
+      }
+      ps = wave_sum64(ps);
+      dps = wave_sum64(dps);
+      ph = wave_sum64(ph);
+      dph = wave_sum64(dph);
+      const double g = 1.0 + ar * (ps + ph);
+      if (g == 0.0) {
+        lo = hi = tau;
+        break;
+      }
+      if (g < 0.0) lo = tau; else hi = tau;
+      const double mid = 0.5 * (lo + hi);
+      if (mid <= lo || mid >= hi) break;
+      // model c + rho s1/(a - x) + rho s2/(b - x) = 0 for the step x, with the
+      // distances a < 0 < b from tau to the two poles
+      const double a = dl - tau, bq = dr - tau;
+      const double s1 = dps * a * a, s2 = dph * bq * bq;
+      const double cm = 1.0 + ar * (ps - s1 / a + ph - s2 / bq);
+      const double qa = cm, qb = -(cm * (a + bq) + ar * (s1 + s2)), qc = cm * a * bq + ar * (s1 * bq + s2 * a);
+      double tn = mid;
+      const double disc = qb * qb - 4.0 * qa * qc;
+      if (disc >= 0.0) {
+        const double q = -0.5 * (qb + copysign(sqrt(disc), qb));
+        const double x1 = qa != 0.0 ? q / qa : NAN;
+        const double x2 = q != 0.0 ? qc / q : NAN;
+        const double x = (x1 > a && x1 < bq) ? x1 : x2;
+        if (x > a && x < bq) {
+          // a model step at the rounding level of tau: converged (tau has just
+          // become an end of the bracket, so it must not be tested against it)
+          if (fabs(x) <= 2.0 * kU * fabs(tau)) {
+            lo = hi = tau;
+            break;
+          }
+          tn = tau + x;
+        }
+      }
+      if (!(tn > lo && tn < hi)) tn = mid;
+      const double step = fabs(tn - tau);
+      tau = tn;
+      if (step <= 2.0 * kU * fabs(tn)) {
+        lo = hi = tn;
+        break;
+      }
+    }
+    if (lane == 0) {
+      s.ro[j] = o;
+      s.rt[j] = lo == hi ? lo : 0.5 * (lo + hi);
+    }
+    return;
+  }
   double prev_step = hi - lo;
   for (int it = 0; it < 200; ++it) {
     double g, dg;
@@ -330,6 +417,10 @@ __global__ __launch_bounds__(256) void k_roots(Sec s0, int S, const double* __re
     const double mid = 0.5 * (lo + hi);
     if (mid <= lo || mid >= hi) break;
     double tn = tau - g / dg;
+    if (fabs(tn - tau) <= 2.0 * kU * fabs(tau)) {  // converged (see the interior case)
+      lo = hi = tau;
+      break;
+    }
     if (!(tn > lo && tn < hi) || fabs(tn - tau) > 0.5 * prev_step) tn = mid;
     const double step = fabs(tn - tau);
     prev_step = step;
