@@ -166,6 +166,29 @@ def test_diag_example_recovered_with_d1():
     assert exact.max_angle_sine(r["V"], np.eye(n)[:, :z]) < 0.1
 
 
+def test_table1_unperturbed_block_lanczos_dimensions():
+    """Sec. 1, Table "tabintro": plain block Lanczos (no perturbation: D = 0),
+    full reorthogonalisation, 1024 products with A and eigenvalues of T below
+    1e-4 counted as zero reports the printed dimensions on the matrix of Eq.
+    (matrixA): fewer than 64 for small blocks, always more than d, all 64 from
+    d = 32 on.  Algorithm 1 with D = 0 and 3 eps = 1e-4 is that experiment."""
+    g = json.load(open(os.path.join(GOLDEN, "diag_example.json")))
+    t1 = json.load(open(os.path.join(GOLDEN, "table1_dims.json")))
+    n, z = g["n"], g["zeros"]
+    diag = np.concatenate([np.zeros(z), 1.0 + g["tail_step"] * np.arange(1, n - z + 1)])
+    a = sp.diags(diag).tocsr()
+    eps = t1["zero_threshold"] / 3.0
+    for d, dim in zip(t1["block_sizes"], t1["dimensions"]):
+        r = lanczos.algorithm1(a, eps, np.zeros(n), G.gaussian_start_block(n, d, 1),
+                               t1["matvecs"] // d, op="sym")
+        assert r["N"] == dim, (d, r["N"], dim)
+        # what is counted is (nearly) null: a unit Ritz vector v with Rayleigh
+        # quotient below the threshold has ||v outside span(e_1..e_64)||^2 <=
+        # threshold / 1.0001, the smallest nonzero entry
+        lim = np.sqrt(t1["zero_threshold"] / g["smallest_nonzero_singular_value"])
+        assert np.all(np.linalg.norm(r["V"][z:, :], axis=0) <= lim)
+
+
 def test_full_column_rank_stops_with_nullity_zero():
     """Reading R12: a matrix of full column rank has no Ritz value below 3 eps;
     the run stops once the smallest one has converged above it, well before the

@@ -245,6 +245,21 @@ def zipf_component_laplacian(n: int = 4_000_000, n_comp: int = 1000, mean_degree
                                              "n_comp": n_comp, "sizes": sizes, "seed": seed})
 
 
+def diagonal_cluster(n_zero: int = 64, n_nonzero: int = 10000) -> CSR:
+    """The diagonal matrix of the introduction's example (Sec. 1, Eq. "matrixA").
+
+    diag(0, ..., 0, 1 + 1/n_nonzero, 1 + 2/n_nonzero, ..., 2): ``n_zero`` zero
+    entries (the null space is spanned by the first ``n_zero`` unit vectors)
+    followed by ``n_nonzero`` equispaced values in (1, 2].  The zeros are
+    stored explicitly, so every row holds one entry.  No randomness.
+    """
+    n = n_zero + n_nonzero
+    vals = np.concatenate([np.zeros(n_zero), 1.0 + np.arange(1, n_nonzero + 1) / n_nonzero])
+    return CSR(m=n, n=n, rowptr=np.arange(n + 1, dtype=np.int64),
+               colind=np.arange(n, dtype=np.int32), vals=vals,
+               meta={"kind": "diagonal", "n_zero": n_zero, "n_nonzero": n_nonzero})
+
+
 def fd_instance(seed: int = BASE_SEED + 4) -> CSR:
     """Small planted instance (m=300, n=280, nullity 8) used for finite differences."""
     return planted_nullity(300, 280, 8, seed=seed)
@@ -294,4 +309,6 @@ def config(name: str, scale: str = "full") -> CSR:
         return column_scaled(base, 2.0, BASE_SEED + 7)
     if name == "fd300":
         return fd_instance()
+    if name == "diag10064":  # the introduction's example; small: 16 zeros + 1000 values
+        return diagonal_cluster(16, 1000) if small else diagonal_cluster(64, 10000)
     raise KeyError(name)
