@@ -248,26 +248,34 @@ __device__ double sec_eval(int np, const double* p, const double* w, int o, doub
   return 1.0 + a_or_rho * s;                    // increasing in tau (rho > 0)
 }
 
-// the secular function and its derivative in one pass
+// the secular function, its derivative and the rounding level of the computed
+// value in one pass.  The level bounds what evaluating g at tau can resolve:
+// each term w/d carries a few roundings (d's relative error is a few units
+// since tau stays within half a gap of the pole), the sum adds its own, and
+// one unit of tau moves g by |tau g'|; a root solver stops once |g| is below it.
 template <bool ARROW>
 __device__ void sec_eval2(int np, const double* p, const double* w, int o, double tau, double a_or_rho,
-                          int lane, double& g, double& dg) {
+                          int lane, double& g, double& dg, double& eg) {
   const double po = p[o];
-  double s = 0.0, ds = 0.0;
+  double s = 0.0, ds = 0.0, sa = 0.0;
   for (int i = lane; i < np; i += 64) {
     const double r = 1.0 / ((p[i] - po) - tau);
     const double t = w[i] * r;
     s += t;
     ds += t * r;
+    sa += fabs(t);
   }
   s = wave_sum64(s);
   ds = wave_sum64(ds);
+  sa = wave_sum64(sa);
   if (ARROW) {
     g = (a_or_rho - po) - tau - s;  // decreasing in tau
     dg = -1.0 - ds;
+    eg = kU * (fabs(a_or_rho - po) + fabs(tau) + 8.0 * sa + 3.0 * fabs(tau * dg));
   } else {
     g = 1.0 + a_or_rho * s;         // increasing in tau (rho > 0)
     dg = a_or_rho * ds;
+    eg = kU * (8.0 * (1.0 + a_or_rho * sa) + 3.0 * fabs(tau * dg));
   }
 }
 
@@ -360,7 +368,10 @@ __global__ __launch_bounds__(256) void k_roots(Sec s0, int S, const double* __re
       ph = wave_sum64(ph);
       dph = wave_sum64(dph);
       const double g = 1.0 + ar * (ps + ph);
-      if (g == 0.0) {
+      // at the rounding level of the evaluation (see sec_eval2; psi's terms are
+      // all negative and phi's all positive, so |psi| + |phi| sums |w/d|)
+      const double eg = kU * (8.0 * (1.0 + ar * (fabs(ps) + fabs(ph))) + 3.0 * fabs(tau) * ar * (dps + dph));
+      if (fabs(g) <= eg) {
         lo = hi = tau;
         break;
       }
@@ -406,9 +417,9 @@ __global__ __launch_bounds__(256) void k_roots(Sec s0, int S, const double* __re
   }
   double prev_step = hi - lo;
   for (int it = 0; it < 200; ++it) {
-    double g, dg;
-    sec_eval2<ARROW>(np, p, w, o, tau, ar, lane, g, dg);
-    if (g == 0.0) {
+    double g, dg, eg;
+    sec_eval2<ARROW>(np, p, w, o, tau, ar, lane, g, dg, eg);
+    if (fabs(g) <= eg) {
       lo = hi = tau;
       break;
     }

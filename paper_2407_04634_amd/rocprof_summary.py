@@ -1,7 +1,7 @@
 """Summarise rocprofv3 CSV output (kernel statistics and per-dispatch counters).
 
     python -m paper_2407_04634_amd.rocprof_summary OUTDIR [--kernel REGEX] [--top N] [--split-us T]
-                                                   [--grid-x X1,X2,...]
+                                                   [--grid-x X1,X2,...] [--by-grid]
 
 OUTDIR is a rocprofv3 ``-d`` directory written with ``--output-format csv``.
 For ``*_kernel_stats.csv`` it prints calls, average and total duration per
@@ -91,6 +91,27 @@ def trace_split(path, pat, split_us, grid_x=None):
     return "\n".join(lines)
 
 
+def trace_by_grid(path, pat, top):
+    """Dispatches of the matching kernels grouped by grid shape (work-items in
+    x and y): count, mean and total duration, the ``top`` shapes by total time."""
+    acc = defaultdict(lambda: [0, 0.0])
+    with open(path) as f:
+        for r in csv.DictReader(f):
+            name = _find(r, "Kernel_Name", "KernelName", "Name")
+            if pat and not re.search(pat, name):
+                continue
+            gx = int(float(_find(r, "Grid_Size_X", "Grid_Size", "Grid_X")))
+            gy = int(float(_find(r, "Grid_Size_Y", "Grid_Y")))
+            us = (float(_find(r, "End_Timestamp")) - float(_find(r, "Start_Timestamp"))) / 1e3
+            a = acc[(name, gx, gy)]
+            a[0] += 1
+            a[1] += us
+    lines = [f"{'grid_x':>9} {'grid_y':>7} {'calls':>7} {'avg_us':>9} {'total_ms':>9}  kernel"]
+    for (name, gx, gy), (n, t) in sorted(acc.items(), key=lambda kv: -kv[1][1])[:top]:
+        lines.append(f"{gx:>9d} {gy:>7d} {n:>7d} {t / n:>9.2f} {t / 1e3:>9.2f}  {name[:120]}")
+    return "\n".join(lines)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("outdir")
@@ -102,6 +123,8 @@ def main():
                     help="also split the matching kernels' dispatches in *_kernel_trace.csv at this duration")
     ap.add_argument("--grid-x", default="",
                     help="comma-separated grid x extents (work-items) the split keeps")
+    ap.add_argument("--by-grid", action="store_true",
+                    help="also group the matching kernels' dispatches in *_kernel_trace.csv by grid shape")
     a = ap.parse_args()
     gx = {int(v) for v in a.grid_x.split(",") if v} or None
     for p in sorted(glob.glob(os.path.join(a.outdir, "**", "*kernel_stats.csv"), recursive=True)):
@@ -111,6 +134,10 @@ def main():
         for p in sorted(glob.glob(os.path.join(a.outdir, "**", "*kernel_trace.csv"), recursive=True)):
             print(f"== {os.path.basename(p)}")
             print(trace_split(p, a.kernel, a.split_us, gx))
+    if a.by_grid:
+        for p in sorted(glob.glob(os.path.join(a.outdir, "**", "*kernel_trace.csv"), recursive=True)):
+            print(f"== {os.path.basename(p)} by grid shape")
+            print(trace_by_grid(p, a.kernel, a.top))
     for p in sorted(glob.glob(os.path.join(a.outdir, "**", "*counter_collection.csv"), recursive=True)):
         print(f"== {os.path.basename(p)}")
         print(counters(p, a.kernel))
