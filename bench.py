@@ -391,6 +391,49 @@ def leg_gather(name="zipf4m", reps=20):
     return out
 
 
+def leg_table1():
+    """The introduction's diagonal example (Sec. 1, Eq. "matrixA", Table "tabintro").
+
+    Plain block Lanczos on A (D = 0, so B = A; reorthogonalisation at every
+    step; 1024 products; Ritz values below 3 eps = 1e-4 counted) for each
+    block size the library supports, next to the paper's printed dimensions;
+    then the method itself (D uniform, eps = 0.1 * 1.0001, Krylov dimension
+    128, d = 1 and 4) with the sine of the largest principal angle to
+    span(e_1..e_64)."""
+    import torch
+    from paper_2407_04634_amd import Context, OP_SYM
+    from workloads import generators as G
+
+    c = G.config("diag10064")
+    z = c.meta["n_zero"]
+    dev = (torch.from_numpy(c.rowptr).cuda(), torch.from_numpy(c.colind).cuda(),
+           torch.from_numpy(c.vals).cuda())
+    paper = dict(zip((1, 2, 4, 8, 16, 32, 64), (45, 46, 48, 48, 48, 64, 64)))
+    out = {"workload": "diag10064", "unperturbed": [], "method": []}
+    for d in (1, 2, 4, 8):
+        om = torch.from_numpy(np.ascontiguousarray(G.gaussian_start_block(c.n, d, 1))).cuda()
+        ctx = Context(*dev, c.m, c.n, D=torch.zeros(c.n, dtype=torch.float64, device="cuda"), Omega=om,
+                      eps=1e-4 / 3, d=d, max_dim=1024, max_matvec=1024, ro_tol=1e-300, refine=0, op=OP_SYM)
+        st = ctx.lanczos_run(allow_noconv=True)
+        ctx.close()
+        out["unperturbed"].append({"d": d, "dimension": st["nullity"], "paper": paper[d],
+                                   "matvecs": st["matvecs"]})
+    for d in (1, 4):
+        om = torch.from_numpy(np.ascontiguousarray(G.gaussian_start_block(c.n, d, 1))).cuda()
+        ctx = Context(*dev, c.m, c.n, D=torch.from_numpy(G.perturbation_diagonal(c.n, 1)).cuda(), Omega=om,
+                      eps=0.1 * 1.0001, d=d, max_dim=128, max_matvec=20_000, op=OP_SYM)
+        t0 = time.perf_counter()
+        st = ctx.lanczos_run()
+        t1 = time.perf_counter()
+        v = np.linalg.qr(ctx.extract_basis().cpu().numpy())[0]
+        ctx.close()
+        # with orthonormal V the sine of the largest principal angle to
+        # span(e_1..e_64) is the 2-norm of V's rows outside the first 64
+        out["method"].append({"d": d, "nullity": st["nullity"], "matvecs": st["matvecs"], "s": t1 - t0,
+                              "sin_angle": float(np.linalg.norm(v[z:, :], 2)) if v.shape[1] else None})
+    return out
+
+
 def leg_backward(ctx_args):
     """Backward pass at the planted50k size: L = ||P X||_F^2, X seeded n x 8."""
     import torch
@@ -436,7 +479,8 @@ def main():
     ap.add_argument("--legs", default="",
                     help="comma-separated extra measurements: spmv (streaming SpMV pair on the 4M-vertex "
                          "Laplacian and the 1M-point coboundary, normal form), gather (pure gather and streaming-copy "
-                         "references on the workload's pattern), backward (planted50k)")
+                         "references on the workload's pattern), backward (planted50k), table1 (the introduction's "
+                         "diagonal example: plain block Lanczos vs the method)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run the plain copy that scales the rocprofv3 byte counters")
     args = ap.parse_args()
@@ -524,6 +568,9 @@ def main():
     if "gather" in legs:
         line["gather_reference"] = leg_gather(args.workload)
         log(f"gather {json.dumps(line['gather_reference'])}")
+    if "table1" in legs:
+        line["table1"] = leg_table1()
+        log(f"table1 {json.dumps(line['table1'])}")
     if "backward" in legs:
         line["backward"] = leg_backward({})
         log(f"backward {json.dumps(line['backward'])}")

@@ -189,6 +189,21 @@ def test_table1_unperturbed_block_lanczos_dimensions():
         assert np.all(np.linalg.norm(r["V"][z:, :], axis=0) <= lim)
 
 
+def test_table1_matrix_method_finds_whole_null_space():
+    """The method on the matrix of Eq. (matrixA) in the symmetric form of Sec.
+    5.1 (B = A + eps D, eps below a third of the smallest nonzero entry):
+    d = 1 finds all 64 null vectors, in fewer products than the 1024 with which
+    plain block Lanczos reports 45 (Table "tabintro")."""
+    g = json.load(open(os.path.join(GOLDEN, "diag_example.json")))
+    c = G.config("diag10064")
+    z = g["zeros"]
+    eps = 0.1 * g["smallest_nonzero_singular_value"]
+    r = lanczos.algorithm2(c.to_scipy(), eps, G.perturbation_diagonal(c.n, 1),
+                           G.gaussian_start_block(c.n, 1, 1), 128, max_matvec=20_000, op="sym")
+    assert r["converged"] and r["N"] == g["nullity"] and r["matvecs"] < 1024
+    assert exact.max_angle_sine(r["V"], np.eye(c.n)[:, :z]) < 1e-8
+
+
 def test_full_column_rank_stops_with_nullity_zero():
     """Reading R12: a matrix of full column rank has no Ritz value below 3 eps;
     the run stops once the smallest one has converged above it, well before the
