@@ -248,37 +248,6 @@ __device__ double sec_eval(int np, const double* p, const double* w, int o, doub
   return 1.0 + a_or_rho * s;                    // increasing in tau (rho > 0)
 }
 
-// the secular function, its derivative and the rounding level of the computed
-// value in one pass.  The level bounds what evaluating g at tau can resolve:
-// each term w/d carries a few roundings (d's relative error is a few units
-// since tau stays within half a gap of the pole), the sum adds its own, and
-// one unit of tau moves g by |tau g'|; a root solver stops once |g| is below it.
-template <bool ARROW>
-__device__ void sec_eval2(int np, const double* p, const double* w, int o, double tau, double a_or_rho,
-                          int lane, double& g, double& dg, double& eg) {
-  const double po = p[o];
-  double s = 0.0, ds = 0.0, sa = 0.0;
-  for (int i = lane; i < np; i += 64) {
-    const double r = 1.0 / ((p[i] - po) - tau);
-    const double t = w[i] * r;
-    s += t;
-    ds += t * r;
-    sa += fabs(t);
-  }
-  s = wave_sum64(s);
-  ds = wave_sum64(ds);
-  sa = wave_sum64(sa);
-  if (ARROW) {
-    g = (a_or_rho - po) - tau - s;  // decreasing in tau
-    dg = -1.0 - ds;
-    eg = kU * (fabs(a_or_rho - po) + fabs(tau) + 8.0 * sa + 3.0 * fabs(tau * dg));
-  } else {
-    g = 1.0 + a_or_rho * s;         // increasing in tau (rho > 0)
-    dg = a_or_rho * ds;
-    eg = kU * (8.0 * (1.0 + a_or_rho * sa) + 3.0 * fabs(tau * dg));
-  }
-}
-
 // roots: ARROW has n'+1 roots (one below p0, one per gap, one above), RANK1 has
 // n'; one wavefront per root, four per block (grid.y = problem), the poles and
 // weights staged in LDS when they fit.  a_or_rho: tip or rho per problem.
@@ -338,103 +307,106 @@ __global__ __launch_bounds__(256) void k_roots(Sec s0, int S, const double* __re
       else { o = j + 1; lo = -0.5 * h; hi = 0.0; }
     }
   }
-  // Newton steps inside the bracket [lo, hi], which every evaluation shrinks.
-  // Near the pole the secular function behaves like c - w / tau, where Newton
-  // converges quadratically from the pole's far side and overshoots from the
-  // near side: a step that leaves the bracket, or one that is not at most half
-  // the previous step (no superlinear progress), is replaced by bisection.
-  // Ends when the step or the bracket reaches the rounding level of tau (all
-  // lanes take the same branches).
+  // Model steps inside the bracket [lo, hi], which every evaluation shrinks;
+  // a step that leaves it is replaced by bisection.  The models are fitted to
+  // the value and the derivative at tau, so each is exact when only the poles
+  // it keeps (and, for the arrowhead, its linear term) contribute.
+  //   Interior root between poles jl and jl+1: the sum is split there into psi
+  //   (poles jl and below, all terms of one sign) and phi (the rest, the other
+  //   sign), each modelled by its pole plus a constant (the "middle way" of
+  //   rational secular solvers); the arrowhead's linear term adds its slope
+  //   to the nearer pole's weight.  The step solves a quadratic.
+  //   Outermost root (next to pole o only): the rank-one update's models the
+  //   sum by pole o plus a constant, c + e / (0 - x); the arrowhead's by
+  //   C - x + S / x (pole o and the linear term), a quadratic again.
+  // Plain Newton steps from a far bracket end need dozens of bisections when
+  // a weight is tiny and the root sits within rounding distance of its pole.
+  // A root is accepted once |g| is below the rounding level of its evaluation
+  // or once a step reaches the rounding level of tau.  The level bounds what
+  // evaluating g at tau can resolve: each term w/d carries a few roundings
+  // (d's relative error is a few units, tau staying within half a gap of the
+  // pole), the sum adds its own, and one unit of tau moves g by |tau g'|.
   double tau = 0.5 * (lo + hi);
-  if (!ARROW && j < np - 1) {
-    // Interior root of a rank-one update: the sum is split at the root's
-    // interval into psi (poles j and below) and phi (poles j+1 and above),
-    // each modelled by one pole plus a constant fitted to its value and
-    // derivative (the "middle way" of rational secular solvers); the model's
-    // root in the interval comes from a quadratic.  Bisection when the model
-    // step leaves the bracket.
-    const double po = p[o];
-    const double dl = p[j] - po, dr = p[j + 1] - po;
-    for (int it = 0; it < 200; ++it) {
-      double ps = 0.0, dps = 0.0, ph = 0.0, dph = 0.0;
-      for (int i = lane; i < np; i += 64) {
-        const double r = 1.0 / ((p[i] - po) - tau);
-        const double t = w[i] * r;
-        if (i <= j) { ps += t; dps += t * r; }
-        else { ph += t; dph += t * r; }
-      }
-      ps = wave_sum64(ps);
-      dps = wave_sum64(dps);
-      ph = wave_sum64(ph);
-      dph = wave_sum64(dph);
-      const double g = 1.0 + ar * (ps + ph);
-      // at the rounding level of the evaluation (see sec_eval2; psi's terms are
-      // all negative and phi's all positive, so |psi| + |phi| sums |w/d|)
-      const double eg = kU * (8.0 * (1.0 + ar * (fabs(ps) + fabs(ph))) + 3.0 * fabs(tau) * ar * (dps + dph));
-      if (fabs(g) <= eg) {
-        lo = hi = tau;
-        break;
-      }
-      if (g < 0.0) lo = tau; else hi = tau;
-      const double mid = 0.5 * (lo + hi);
-      if (mid <= lo || mid >= hi) break;
-      // model c + rho s1/(a - x) + rho s2/(b - x) = 0 for the step x, with the
+  const bool outer = ARROW ? (j == 0 || j == np) : (j == np - 1);
+  const int jl = ARROW ? j - 1 : j;  // interior: the poles left and right of the root
+  const double po = p[o];
+  const double dl = outer ? 0.0 : p[jl] - po, dr = outer ? 0.0 : p[jl + 1] - po;
+  const double kf = ARROW ? -1.0 : ar;  // model: cm + kf (s1 / (a - x) + s2 / (b - x))
+  for (int it = 0; it < 200; ++it) {
+    double ps = 0.0, dps = 0.0, ph = 0.0, dph = 0.0;
+    for (int i = lane; i < np; i += 64) {
+      const double r = 1.0 / ((p[i] - po) - tau);
+      const double t = w[i] * r;
+      if (i <= jl) { ps += t; dps += t * r; }
+      else { ph += t; dph += t * r; }
+    }
+    ps = wave_sum64(ps);
+    dps = wave_sum64(dps);
+    ph = wave_sum64(ph);
+    dph = wave_sum64(dph);
+    // psi's terms are all of one sign and phi's of the other, so |psi| + |phi|
+    // is the sum of |w / d| the rounding level needs
+    const double sa = fabs(ps) + fabs(ph);
+    double g, dg, eg;
+    if (ARROW) {
+      g = (ar - po) - tau - (ps + ph);  // decreasing in tau
+      dg = -1.0 - (dps + dph);
+      eg = kU * (fabs(ar - po) + fabs(tau) + 8.0 * sa + 3.0 * fabs(tau * dg));
+    } else {
+      g = 1.0 + ar * (ps + ph);         // increasing in tau (rho > 0)
+      dg = ar * (dps + dph);
+      eg = kU * (8.0 * (1.0 + ar * sa) + 3.0 * fabs(tau * dg));
+    }
+    if (fabs(g) <= eg) {
+      lo = hi = tau;
+      break;
+    }
+    if (ARROW ? g > 0.0 : g < 0.0) lo = tau; else hi = tau;
+    const double mid = 0.5 * (lo + hi);
+    if (mid <= lo || mid >= hi) break;
+    double x = NAN;  // the model's step, tau + x its root
+    if (!outer) {
       // distances a < 0 < b from tau to the two poles
       const double a = dl - tau, bq = dr - tau;
-      const double s1 = dps * a * a, s2 = dph * bq * bq;
-      const double cm = 1.0 + ar * (ps - s1 / a + ph - s2 / bq);
-      const double qa = cm, qb = -(cm * (a + bq) + ar * (s1 + s2)), qc = cm * a * bq + ar * (s1 * bq + s2 * a);
-      double tn = mid;
+      double s1 = dps * a * a, s2 = dph * bq * bq;
+      if (ARROW) {
+        if (o == jl) s1 += a * a; else s2 += bq * bq;
+      }
+      const double cm = g - kf * (s1 / a + s2 / bq);
+      const double qa = cm, qb = -(cm * (a + bq) + kf * (s1 + s2)), qc = cm * a * bq + kf * (s1 * bq + s2 * a);
       const double disc = qb * qb - 4.0 * qa * qc;
       if (disc >= 0.0) {
         const double q = -0.5 * (qb + copysign(sqrt(disc), qb));
         const double x1 = qa != 0.0 ? q / qa : NAN;
         const double x2 = q != 0.0 ? qc / q : NAN;
-        const double x = (x1 > a && x1 < bq) ? x1 : x2;
-        if (x > a && x < bq) {
-          // a model step at the rounding level of tau: converged (tau has just
-          // become an end of the bracket, so it must not be tested against it)
-          if (fabs(x) <= 2.0 * kU * fabs(tau)) {
-            lo = hi = tau;
-            break;
-          }
-          tn = tau + x;
-        }
+        x = (x1 > a && x1 < bq) ? x1 : x2;
+        if (!(x > a && x < bq)) x = NAN;
       }
-      if (!(tn > lo && tn < hi)) tn = mid;
-      const double step = fabs(tn - tau);
-      tau = tn;
-      if (step <= 2.0 * kU * fabs(tn)) {
-        lo = hi = tn;
+    } else if (ARROW) {
+      // C - x + S / x = 0 with S = -(g' + 1) tau^2 >= 0; the root on tau's side
+      // of the pole (positive for j = np, negative for j = 0), taken from the
+      // form without cancellation
+      const double sq = -(dg + 1.0) * tau * tau;
+      const double cc = g + tau - sq / tau;
+      const double rt = sqrt(cc * cc + 4.0 * sq);
+      const double sg = j == np ? 1.0 : -1.0;
+      x = sg * cc >= 0.0 ? 0.5 * (cc + sg * rt) - tau : -2.0 * sq / (cc - sg * rt) - tau;
+    } else {
+      // c + e / (0 - x) = 0 fitted at tau: e = g' tau^2, c = g + g' tau
+      x = dg * tau * tau / (g + dg * tau) - tau;
+    }
+    double tn = mid;
+    if (x == x) {
+      // a model step at the rounding level of tau: converged (tau has just
+      // become an end of the bracket, so it must not be tested against it)
+      if (fabs(x) <= 2.0 * kU * fabs(tau)) {
+        lo = hi = tau;
         break;
       }
+      tn = tau + x;
     }
-    if (lane == 0) {
-      s.ro[j] = o;
-      s.rt[j] = lo == hi ? lo : 0.5 * (lo + hi);
-    }
-    return;
-  }
-  double prev_step = hi - lo;
-  for (int it = 0; it < 200; ++it) {
-    double g, dg, eg;
-    sec_eval2<ARROW>(np, p, w, o, tau, ar, lane, g, dg, eg);
-    if (fabs(g) <= eg) {
-      lo = hi = tau;
-      break;
-    }
-    const bool right = ARROW ? (g > 0.0) : (g < 0.0);
-    if (right) lo = tau; else hi = tau;
-    const double mid = 0.5 * (lo + hi);
-    if (mid <= lo || mid >= hi) break;
-    double tn = tau - g / dg;
-    if (fabs(tn - tau) <= 2.0 * kU * fabs(tau)) {  // converged (see the interior case)
-      lo = hi = tau;
-      break;
-    }
-    if (!(tn > lo && tn < hi) || fabs(tn - tau) > 0.5 * prev_step) tn = mid;
+    if (!(tn > lo && tn < hi)) tn = mid;
     const double step = fabs(tn - tau);
-    prev_step = step;
     tau = tn;
     if (step <= 2.0 * kU * fabs(tn)) {
       lo = hi = tn;
