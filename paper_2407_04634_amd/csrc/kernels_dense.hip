@@ -859,6 +859,53 @@ __global__ __launch_bounds__(kThreads) void k_ts_scale(const int* cond, int64_t 
   }
 }
 
+// k_ts_scale with the factor computed in the kernel: every block sums the Gram
+// partials of k_ts_nn_v in the same fixed order (so all blocks hold the same
+// R) and factors them; block 0 stores R^{-1} and R and raises the breakdown
+// flags as k_ts_gramfin does.  One launch fewer per reorthogonalisation step
+// where the partials are few enough for every block to read them all.
+template <typename VT, int DA, int NA>
+__global__ __launch_bounds__(kThreads) void k_ts_scale_fin(const int* cond, int64_t n,
+                                                           CPair<VT, DA, NA> cc, int nparts,
+                                                           const double* __restrict__ part_c,
+                                                           double* __restrict__ rinv, int* flags,
+                                                           VT* __restrict__ z0, int64_t ldz) {
+  constexpr int NC = DA * NA;
+  constexpr int NV = NC * NC;
+  if (cond && *cond == 0) return;
+  __shared__ double smem[kThreads];
+  __shared__ double res[NV];
+  __shared__ double ri[NV];
+  reduce_partials<NV>(part_c, nparts, res, smem);
+  if (threadIdx.x == 0) {
+    double r[NV], rv[NV];
+    const bool ok = chol_upper_inv<NC>(res, r, rv);
+#pragma unroll
+    for (int i = 0; i < NV; ++i) ri[i] = rv[i];
+    if (blockIdx.x == 0) {
+      if (!ok) atomicOr(flags + 1, 1);
+      if (cond && !kahan_parlett_ok(NC, res)) atomicOr(flags + 1, 2);
+#pragma unroll
+      for (int i = 0; i < NV; ++i) { rinv[i] = rv[i]; rinv[NV + i] = r[i]; }
+    }
+  }
+  __syncthreads();
+  for (int64_t row = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; row < n;
+       row += (int64_t)gridDim.x * blockDim.x) {
+    double v[NC];
+#pragma unroll
+    for (int c = 0; c < NC; ++c) v[c] = (double)cc.get(row, c);
+#pragma unroll
+    for (int a = 0; a < NC; ++a) {
+      double t = 0.0;
+#pragma unroll
+      for (int b = 0; b <= a; ++b) t = fma(v[b], ri[b + a * NC], t);
+      cc.set(row, a, VT(t));
+      if (z0) z0[row + (int64_t)a * ldz] = VT(t);
+    }
+  }
+}
+
 // ---------------------------------------------------------------------------
 // restart and extraction helpers
 // ---------------------------------------------------------------------------
@@ -1147,6 +1194,15 @@ int64_t ts_chunk_rows(int64_t n, int k, int nc, int esize) {
   return (rows + 255) / 256 * 256;
 }
 
+// Whether the factor of the reorthogonalised block's Gram matrix is computed
+// inside k_ts_scale_fin (every block reads all partials of k_ts_nn_v: at most
+// 4096 doubles, up to 4 columns) instead of by the one-block k_ts_gramfin.
+template <typename VT, int NC>
+static bool ts_fin_fused(int64_t n) {
+  constexpr int TR = ts_nn_rows<VT, NC>();
+  return NC <= 4 && ((n + TR - 1) / TR) * NC * NC <= 4096;
+}
+
 template <typename VT, int DA, int NA>
 static void ts_proj_t(nsp_ctx* c, const int* cond, int64_t n, const VT* z, int64_t ldz, int k,
                       VT* a0, VT* a1, double* h, double* hpart, bool gram, double* part_c,
@@ -1172,7 +1228,8 @@ static void ts_proj_t(nsp_ctx* c, const int* cond, int64_t n, const VT* z, int64
     constexpr int nt = ts_nn_waves<VT, NC>() * kWave;
     if (gram) {
       k_ts_nn_v<VT, DA, NA, true><<<nnblocks, nt, 0, c->stream>>>(cond, n, z, ldz, k, h, cc, part_c);
-      k_ts_gramfin<NC><<<1, 256, 0, c->stream>>>(cond, (int)nnblocks, part_c, rinv, c->flags.as<int>());
+      if (!ts_fin_fused<VT, NC>(n))
+        k_ts_gramfin<NC><<<1, 256, 0, c->stream>>>(cond, (int)nnblocks, part_c, rinv, c->flags.as<int>());
     } else if (k > 0)
       k_ts_nn_v<VT, DA, NA, false><<<nnblocks, nt, 0, c->stream>>>(cond, n, z, ldz, k, h, cc,
                                                                    nullptr);
@@ -1195,8 +1252,17 @@ static void ts_scale_t(nsp_ctx* c, const int* cond, int64_t n, VT* a0, VT* a1, c
                        double* rinv, VT* z0, int64_t ldz) {
   constexpr int NC = DA * NA;
   CPair<VT, DA, NA> cc{a0, a1};
-  (void)part_c;  // the Gram partials were reduced by k_ts_gramfin
   const unsigned grid = cap_grid(n, kThreads, 2048);
+  if constexpr (NC <= 4) {
+    if (ts_fin_fused<VT, NC>(n)) {
+      constexpr int TR = ts_nn_rows<VT, NC>();
+      k_ts_scale_fin<VT, DA, NA><<<grid, kThreads, 0, c->stream>>>(
+          cond, n, cc, (int)((n + TR - 1) / TR), part_c, rinv, c->flags.as<int>(), z0, ldz);
+      NSP_HIP(hipGetLastError());
+      return;
+    }
+  }
+  // the Gram partials were reduced and factored by k_ts_gramfin
   k_ts_scale<VT, DA, NA><<<grid, kThreads, 0, c->stream>>>(cond, n, cc, rinv, z0, ldz);
   NSP_HIP(hipGetLastError());
 }
