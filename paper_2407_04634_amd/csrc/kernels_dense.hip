@@ -1014,66 +1014,98 @@ __global__ __launch_bounds__(kThreads) void k_coldots_partial(int64_t rows, int 
   }
 }
 
-// out[v] = sum_b part[b * nv + v]: 8 values x 32 partial groups per block,
-// combined in a fixed order
-__global__ __launch_bounds__(256) void k_reduce_parts(int nparts, int nv,
+// out[v] = sum_b part[b * nv + v]: vb values per block (1, 2, 4 or 8, fewer
+// for small nv so that all 256 threads work), 256 / vb partial groups each
+// with four independent sums (four loads in flight), then a fixed-order tree
+// over the groups in LDS
+__global__ __launch_bounds__(256) void k_reduce_parts(int nparts, int nv, int vb,
                                                       const double* __restrict__ part,
                                                       double* __restrict__ out) {
   __shared__ double sm[256];
-  const int vl = threadIdx.x % 8, g = threadIdx.x / 8;
-  const int v = blockIdx.x * 8 + vl;
-  double s = 0.0;
-  if (v < nv)
-    for (int b = g; b < nparts; b += 32) s += part[(size_t)b * nv + v];
-  sm[threadIdx.x] = s;
+  const int groups = 256 / vb;
+  const int vl = (int)threadIdx.x % vb, g = (int)threadIdx.x / vb;
+  const int v = (int)blockIdx.x * vb + vl;
+  double acc[4] = {0.0, 0.0, 0.0, 0.0};
+  if (v < nv) {
+    int b = g;
+    for (; b + 3 * groups < nparts; b += 4 * groups) {
+#pragma unroll
+      for (int u = 0; u < 4; ++u) acc[u] += part[(size_t)(b + u * groups) * nv + v];
+    }
+    for (int u = 0; b < nparts; b += groups, ++u) acc[u & 3] += part[(size_t)b * nv + v];
+  }
+  sm[threadIdx.x] = (acc[0] + acc[1]) + (acc[2] + acc[3]);
   __syncthreads();
-  if (threadIdx.x < 8 && v < nv) {
-    double r = 0.0;
-    for (int q = 0; q < 32; ++q) r += sm[q * 8 + vl];
-    out[v] = r;
+  for (int h = groups / 2; h > 0; h >>= 1) {
+    if (g < h) sm[threadIdx.x] += sm[threadIdx.x + h * vb];
+    __syncthreads();
+  }
+  if (g == 0 && v < nv) out[v] = sm[vl];
+}
+
+// Elementwise updates of row-major blocks (rows x k): block (bx, by) covers
+// rows bx * kUpdRows .. + kUpdRows of the 256-column tile by, one thread per
+// column, so each thread's column and its coefficient are fixed (no 64-bit
+// division per element) and every row of a tile is one coalesced 2 KB access.
+constexpr int kUpdRows = 16;
+
+// CGLS update: alpha_c = gamma_c / qq_c (0 for inactive columns)
+//   x += alpha p (n rows) ; s -= alpha q (m rows)
+__global__ __launch_bounds__(256) void k_cgls_xs(int64_t n, int64_t m, int k,
+                                                 const double* __restrict__ gamma,
+                                                 const double* __restrict__ qq,
+                                                 const int* __restrict__ active, double* __restrict__ x,
+                                                 const double* __restrict__ p, double* __restrict__ s,
+                                                 const double* __restrict__ q) {
+  const int c = (int)blockIdx.y * 256 + (int)threadIdx.x;
+  if (c >= k) return;
+  const double al = (active[c] && qq[c] > 0.0) ? gamma[c] / qq[c] : 0.0;
+  if (al == 0.0) return;
+  const int64_t r0 = (int64_t)blockIdx.x * kUpdRows;
+#pragma unroll 4
+  for (int t = 0; t < kUpdRows; ++t) {
+    const int64_t row = r0 + t;
+    const int64_t i = row * k + c;
+    if (row < n) x[i] = fma(al, p[i], x[i]);
+    if (row < m) s[i] = fma(-al, q[i], s[i]);
   }
 }
 
-// CGLS update: alpha_c = gamma_c / qq_c (0 for inactive columns)
-//   x += alpha p ; s -= alpha q
-__global__ void k_cgls_xs(int64_t n, int64_t m, int k, const double* __restrict__ gamma,
-                          const double* __restrict__ qq, const int* __restrict__ active,
-                          double* __restrict__ x, const double* __restrict__ p,
-                          double* __restrict__ s, const double* __restrict__ q) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const int64_t tot = (n > m ? n : m) * k;
-  if (i >= tot) return;
-  const int c = (int)(i % k);
-  const double al = (active[c] && qq[c] > 0.0) ? gamma[c] / qq[c] : 0.0;
-  if (al == 0.0) return;
-  if (i < n * k) x[i] = fma(al, p[i], x[i]);
-  if (i < m * k) s[i] = fma(-al, q[i], s[i]);
-}
-
 // CGLS direction: beta_c = gnew_c / gamma_c ; p = r + beta p (active columns only)
-__global__ void k_cgls_p(int64_t n, int k, const double* __restrict__ gnew,
-                         const double* __restrict__ gamma, const int* __restrict__ active,
-                         const double* __restrict__ r, double* __restrict__ p) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n * k) return;
-  const int c = (int)(i % k);
-  if (!active[c]) return;
+__global__ __launch_bounds__(256) void k_cgls_p(int64_t n, int k, const double* __restrict__ gnew,
+                                                const double* __restrict__ gamma,
+                                                const int* __restrict__ active,
+                                                const double* __restrict__ r, double* __restrict__ p) {
+  const int c = (int)blockIdx.y * 256 + (int)threadIdx.x;
+  if (c >= k || !active[c]) return;
   const double be = gamma[c] > 0.0 ? gnew[c] / gamma[c] : 0.0;
-  p[i] = fma(be, p[i], r[i]);
+  const int64_t r0 = (int64_t)blockIdx.x * kUpdRows;
+  const int rows = (int)(n - r0 < kUpdRows ? n - r0 : kUpdRows);
+#pragma unroll 4
+  for (int t = 0; t < rows; ++t) {
+    const int64_t i = (r0 + t) * k + c;
+    p[i] = fma(be, p[i], r[i]);
+  }
 }
 
 // CG on A^T A: alpha = rr / pq ; w += alpha p ; r -= alpha q
-__global__ void k_cg_wr(int64_t n, int k, const double* __restrict__ rr, const double* __restrict__ pq,
-                        const int* __restrict__ active, double* __restrict__ w,
-                        const double* __restrict__ p, double* __restrict__ r,
-                        const double* __restrict__ q) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n * k) return;
-  const int c = (int)(i % k);
+__global__ __launch_bounds__(256) void k_cg_wr(int64_t n, int k, const double* __restrict__ rr,
+                                               const double* __restrict__ pq,
+                                               const int* __restrict__ active, double* __restrict__ w,
+                                               const double* __restrict__ p, double* __restrict__ r,
+                                               const double* __restrict__ q) {
+  const int c = (int)blockIdx.y * 256 + (int)threadIdx.x;
+  if (c >= k) return;
   const double al = (active[c] && pq[c] > 0.0) ? rr[c] / pq[c] : 0.0;
   if (al == 0.0) return;
-  w[i] = fma(al, p[i], w[i]);
-  r[i] = fma(-al, q[i], r[i]);
+  const int64_t r0 = (int64_t)blockIdx.x * kUpdRows;
+  const int rows = (int)(n - r0 < kUpdRows ? n - r0 : kUpdRows);
+#pragma unroll 4
+  for (int t = 0; t < rows; ++t) {
+    const int64_t i = (r0 + t) * k + c;
+    w[i] = fma(al, p[i], w[i]);
+    r[i] = fma(-al, q[i], r[i]);
+  }
 }
 
 // x -= y (elementwise)
@@ -1360,7 +1392,8 @@ void coldots(nsp_ctx* c, int64_t rows, int k, const double* a, const double* b, 
 
 void reduce_parts(nsp_ctx* c, int nparts, int nv, const double* part, double* out) {
   if (nv <= 0) return;
-  k_reduce_parts<<<nblk(nv, 8), 256, 0, c->stream>>>(nparts, nv, part, out);
+  const int vb = nv >= 8 ? 8 : nv >= 4 ? 4 : nv >= 2 ? 2 : 1;
+  k_reduce_parts<<<nblk(nv, vb), 256, 0, c->stream>>>(nparts, nv, vb, part, out);
   NSP_HIP(hipGetLastError());
 }
 
@@ -1371,20 +1404,25 @@ int64_t coldots_parts(int64_t rows) {
 
 void cgls_xs(nsp_ctx* c, int64_t n, int64_t m, int k, const double* gamma, const double* qq,
              const int* active, double* x, const double* p, double* s, const double* q) {
-  const int64_t tot = std::max(n, m) * k;
-  k_cgls_xs<<<nblk(tot, 256), 256, 0, c->stream>>>(n, m, k, gamma, qq, active, x, p, s, q);
+  if (k <= 0) return;
+  const dim3 grid((unsigned)((std::max(n, m) + kUpdRows - 1) / kUpdRows), (unsigned)((k + 255) / 256));
+  k_cgls_xs<<<grid, 256, 0, c->stream>>>(n, m, k, gamma, qq, active, x, p, s, q);
   NSP_HIP(hipGetLastError());
 }
 
 void cgls_p(nsp_ctx* c, int64_t n, int k, const double* gnew, const double* gamma, const int* active,
             const double* r, double* p) {
-  k_cgls_p<<<nblk(n * k, 256), 256, 0, c->stream>>>(n, k, gnew, gamma, active, r, p);
+  if (k <= 0 || n <= 0) return;
+  const dim3 grid((unsigned)((n + kUpdRows - 1) / kUpdRows), (unsigned)((k + 255) / 256));
+  k_cgls_p<<<grid, 256, 0, c->stream>>>(n, k, gnew, gamma, active, r, p);
   NSP_HIP(hipGetLastError());
 }
 
 void cg_wr(nsp_ctx* c, int64_t n, int k, const double* rr, const double* pq, const int* active,
            double* w, const double* p, double* r, const double* q) {
-  k_cg_wr<<<nblk(n * k, 256), 256, 0, c->stream>>>(n, k, rr, pq, active, w, p, r, q);
+  if (k <= 0 || n <= 0) return;
+  const dim3 grid((unsigned)((n + kUpdRows - 1) / kUpdRows), (unsigned)((k + 255) / 256));
+  k_cg_wr<<<grid, 256, 0, c->stream>>>(n, k, rr, pq, active, w, p, r, q);
   NSP_HIP(hipGetLastError());
 }
 
