@@ -391,6 +391,34 @@ def leg_gather(name="zipf4m", reps=20):
     return out
 
 
+def leg_stream(gib=8, reps=10):
+    """Reference rates of plain streaming on this GPU for the HBM-bound kernels'
+    rooflines: a read-only pass (torch.sum over a resident buffer, FP32 and
+    FP64) and a copy (read + write), each over ``gib`` GiB, best of ``reps``."""
+    import torch
+
+    n = (gib << 30) // 4
+    out = {"bytes": gib << 30}
+    src = torch.ones(n, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    for tag, fn, nbytes in (("read_fp32", lambda: src.sum(), gib << 30),
+                            ("read_fp64", lambda: src.view(torch.float64).sum(), gib << 30),
+                            ("copy", lambda: dst.copy_(src), 2 * (gib << 30))):
+        fn()
+        torch.cuda.synchronize()
+        best = float("inf")
+        for _ in range(reps):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            fn()
+            e1.record()
+            torch.cuda.synchronize()
+            best = min(best, e0.elapsed_time(e1) * 1e-3)
+        out[f"{tag}_gbs"] = nbytes / best / 1e9
+    del src, dst
+    return out
+
+
 def leg_table1():
     """The introduction's diagonal example (Sec. 1, Eq. "matrixA", Table "tabintro").
 
@@ -480,7 +508,8 @@ def main():
                     help="comma-separated extra measurements: spmv (streaming SpMV pair on the 4M-vertex "
                          "Laplacian and the 1M-point coboundary, normal form), gather (pure gather and streaming-copy "
                          "references on the workload's pattern), backward (planted50k), table1 (the introduction's "
-                         "diagonal example: plain block Lanczos vs the method)")
+                         "diagonal example: plain block Lanczos vs the method), stream (plain read and copy "
+                         "rates over 8 GiB)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run the plain copy that scales the rocprofv3 byte counters")
     args = ap.parse_args()
@@ -568,6 +597,9 @@ def main():
     if "gather" in legs:
         line["gather_reference"] = leg_gather(args.workload)
         log(f"gather {json.dumps(line['gather_reference'])}")
+    if "stream" in legs:
+        line["stream_reference"] = leg_stream()
+        log(f"stream {json.dumps(line['stream_reference'])}")
     if "table1" in legs:
         line["table1"] = leg_table1()
         log(f"table1 {json.dumps(line['table1'])}")
