@@ -509,7 +509,7 @@ def main():
                          "Laplacian and the 1M-point coboundary, normal form), gather (pure gather and streaming-copy "
                          "references on the workload's pattern), backward (planted50k), table1 (the introduction's "
                          "diagonal example: plain block Lanczos vs the method), stream (plain read and copy "
-                         "rates over 8 GiB)")
+                         "rates over 8 GiB; also run when no leg is named)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run the plain copy that scales the rocprofv3 byte counters")
     args = ap.parse_args()
@@ -597,7 +597,7 @@ def main():
     if "gather" in legs:
         line["gather_reference"] = leg_gather(args.workload)
         log(f"gather {json.dumps(line['gather_reference'])}")
-    if "stream" in legs:
+    if "stream" in legs or not legs:  # cheap (a few seconds): part of the default run
         line["stream_reference"] = leg_stream()
         log(f"stream {json.dumps(line['stream_reference'])}")
     if "table1" in legs:
