@@ -18,7 +18,9 @@ Modules
   backward  -- gradient of a loss on the null projector w.r.t. A's nonzeros
 
 Pinned by tests/test_oracle_*.py against closed forms, invariants, bounds the
-paper proves and brute force on tiny inputs.  Parity unpinned: iteration and
-matvec counts (they depend on rounding order and on random draws the paper
-does not print); see the "parity unpinned" notes in lanczos.py.
+paper proves, brute force on tiny inputs and the values the paper prints for
+its worked example (the null space dimensions plain block Lanczos reports on
+the diagonal matrix of Sec. 1, its first table).  Parity unpinned: iteration
+and matvec counts of the method itself (they depend on rounding order and on
+random draws the paper does not print).
 """
