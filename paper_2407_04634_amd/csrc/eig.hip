@@ -316,9 +316,10 @@ __global__ __launch_bounds__(256) void k_roots(Sec s0, int S, const double* __re
   //   sign), each modelled by its pole plus a constant (the "middle way" of
   //   rational secular solvers); the arrowhead's linear term adds its slope
   //   to the nearer pole's weight.  The step solves a quadratic.
-  //   Outermost root (next to pole o only): the rank-one update's models the
-  //   sum by pole o plus a constant, c + e / (0 - x); the arrowhead's by
-  //   C - x + S / x (pole o and the linear term), a quadratic again.
+  //   Outermost root (poles on one side only): for the rank-one update the
+  //   sum is modelled by pole o plus a constant, c + e / (0 - x); for the
+  //   arrowhead by C - x + S / x (pole o and the linear term), a quadratic
+  //   again.
   // Plain Newton steps from a far bracket end need dozens of bisections when
   // a weight is tiny and the root sits within rounding distance of its pole.
   // A root is accepted once |g| is below the rounding level of its evaluation
