@@ -649,6 +649,10 @@ def main():
                             "launches": ("per launch that reorthogonalised" if "ts_" in dom["kernel"]
                                          else "per launch")}
         line["reorth_active_frac"] = frac
+        # sampled steps whose W flag was clear: the projection and update
+        # launches there return at once; their summed time per such step
+        idle = st["ro_samples"] - st["ro_active"]
+        line["reorth_idle_launch_us"] = st["ro_idle_ms"] * 1e3 / idle if idle > 0 else None
         line["kernels"] = kr
         line["spmv_hbm"] = [dict(r, prec=p, workload=args.workload) for p in precs for r in kr[p]
                             if r["kernel"].startswith("k_csr") or r["kernel"].startswith("k_spmm")]
