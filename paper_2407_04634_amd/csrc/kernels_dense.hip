@@ -211,15 +211,9 @@ __global__ __launch_bounds__(kThreads) void k_sub_gram(int64_t n, VT* __restrict
   double g[NV];
 #pragma unroll
   for (int i = 0; i < NV; ++i) g[i] = 0.0;
-  for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < n;
-       r += (int64_t)gridDim.x * blockDim.x) {
-    double v[D];  // FP64 arithmetic, one rounding to the working precision on store
-#pragma unroll
-    for (int j = 0; j < D; ++j) v[j] = p[r * D + j];
+  // one row: FP64 arithmetic, one rounding to the working precision on store
+  auto row = [&](int64_t r, double (&v)[D], const double (&xr)[D]) {
     if constexpr (SUB) {
-      double xr[D];
-#pragma unroll
-      for (int j = 0; j < D; ++j) xr[j] = x[r * D + j];
       double w[D];
 #pragma unroll
       for (int a = 0; a < D; ++a) {
@@ -239,6 +233,32 @@ __global__ __launch_bounds__(kThreads) void k_sub_gram(int64_t n, VT* __restrict
     for (int a = 0; a < D; ++a)
 #pragma unroll
       for (int b = 0; b < D; ++b) g[a + b * D] += v[a] * v[b];
+  };
+  // U rows per thread and pass, all their loads issued first (the rows are
+  // then processed in the same order as one at a time, so the sums are too)
+  constexpr int U = D <= 2 ? 4 : (D == 4 ? 2 : 1);
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  for (; r + (U - 1) * stride < n; r += U * stride) {
+    double v[U][D], xr[U][D];
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+#pragma unroll
+      for (int j = 0; j < D; ++j) {
+        v[u][j] = p[(r + u * stride) * D + j];
+        xr[u][j] = SUB ? (double)x[(r + u * stride) * D + j] : 0.0;
+      }
+#pragma unroll
+    for (int u = 0; u < U; ++u) row(r + u * stride, v[u], xr[u]);
+  }
+  for (; r < n; r += stride) {
+    double v[D], xr[D];
+#pragma unroll
+    for (int j = 0; j < D; ++j) {
+      v[j] = p[r * D + j];
+      xr[j] = SUB ? (double)x[r * D + j] : 0.0;
+    }
+    row(r, v, xr);
   }
   block_sum<NV>(g, smem);
   if (threadIdx.x == 0) {
@@ -292,11 +312,9 @@ __global__ __launch_bounds__(kThreads) void k_scale(int64_t n, const VT* p,
 #pragma unroll
   for (int i = 0; i < NG; ++i) g[i] = 0.0;
   const int b0 = WREC ? 1 : 0;
-  for (int64_t r = (int64_t)(blockIdx.x - b0) * blockDim.x + threadIdx.x; r < n;
-       r += (int64_t)(gridDim.x - b0) * blockDim.x) {
-    double v[D], o[D];  // FP64 arithmetic, one rounding on store
-#pragma unroll
-    for (int j = 0; j < D; ++j) v[j] = p[r * D + j];
+  // one row: FP64 arithmetic, one rounding on store
+  auto row = [&](int64_t r, const double (&v)[D]) {
+    double o[D];
 #pragma unroll
     for (int a = 0; a < D; ++a) {
       double s = 0.0;
@@ -313,6 +331,25 @@ __global__ __launch_bounds__(kThreads) void k_scale(int64_t n, const VT* p,
 #pragma unroll
         for (int b = 0; b < D; ++b) g[a + b * D] += o[a] * o[b];
     }
+  };
+  // U rows per thread and pass with their loads issued first (same row order)
+  constexpr int U = D <= 2 ? 4 : (D == 4 ? 2 : 1);
+  const int64_t stride = (int64_t)(gridDim.x - b0) * blockDim.x;
+  int64_t r = (int64_t)(blockIdx.x - b0) * blockDim.x + threadIdx.x;
+  for (; r + (U - 1) * stride < n; r += U * stride) {
+    double v[U][D];
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+#pragma unroll
+      for (int j = 0; j < D; ++j) v[u][j] = p[(r + u * stride) * D + j];
+#pragma unroll
+    for (int u = 0; u < U; ++u) row(r + u * stride, v[u]);
+  }
+  for (; r < n; r += stride) {
+    double v[D];
+#pragma unroll
+    for (int j = 0; j < D; ++j) v[j] = p[r * D + j];
+    row(r, v);
   }
   if constexpr (GRAM) {
     block_sum<NG>(g, smem);
