@@ -71,7 +71,14 @@ __device__ __forceinline__ void reduce_partials(const double* __restrict__ part,
   }
   smem[t] = s;
   __syncthreads();
-  if (t < NV) {
+  if ((groups & (groups - 1)) == 0) {
+    // groups a power of two (block sizes and NV are): a fixed-order tree in LDS
+    for (int h = groups / 2; h > 0; h >>= 1) {
+      if (t < h * NV) smem[t] += smem[t + h * NV];
+      __syncthreads();
+    }
+    if (t < NV) res[t] = smem[t];
+  } else if (t < NV) {
     double r = 0.0;
     for (int g = 0; g < groups; ++g) r += smem[g * NV + t];
     res[t] = r;
