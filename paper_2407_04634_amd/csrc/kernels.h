@@ -51,6 +51,14 @@ void w_reset(nsp_ctx* c, int col0, int ncols, double u_d, double* w, int ldw);
 // dense: tall-skinny projection pair (one CGS pass) and final scaling
 int64_t ts_chunk_rows(int64_t n, int k, int nc, int esize = 8);
 int64_t ts_part_c_len(int64_t n, int nc);
+// FP64 projection h = Z^T C (k x d, basis-column major) and update C -= Z h on
+// their own, C row-interleaved n x d (d = 1, 2, 4, 8), Z column-major with an
+// even ldz; hpart holds ts_tn_parts_len(n, k, d) doubles
+int64_t ts_tn_parts_len(int64_t n, int k, int d);
+void ts_tn_only(nsp_ctx* c, int d, int64_t n, const double* z, int64_t ldz, int k, const double* a0,
+                double* h, double* hpart);
+void ts_nn_only(nsp_ctx* c, int d, int64_t n, const double* z, int64_t ldz, int k, const double* h,
+                double* a0);
 template <typename VT>
 void ts_project(nsp_ctx* c, const int* cond, int d, int na, int64_t n, const VT* z, int64_t ldz,
                 int k, VT* a0, VT* a1, double* h, double* hpart, bool gram, double* part_c,

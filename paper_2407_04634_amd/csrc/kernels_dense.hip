@@ -1080,11 +1080,18 @@ __global__ __launch_bounds__(256) void k_reduce_parts(int nparts, int nv, int vb
   if (g == 0 && v < nv) out[v] = sm[vl];
 }
 
-// Elementwise updates of row-major blocks (rows x k): block (bx, by) covers
-// rows bx * kUpdRows .. + kUpdRows of the 256-column tile by, one thread per
-// column, so each thread's column and its coefficient are fixed (no 64-bit
-// division per element) and every row of a tile is one coalesced 2 KB access.
+// Elementwise updates of row-major blocks (rows x k).  A block's 256 threads
+// cover kc = min(k, 256) consecutive columns (tile blockIdx.y) of 256 / kc
+// rows at a time, kUpdRows such row steps per block: each thread's column and
+// its coefficient are fixed (no 64-bit division per element), consecutive
+// threads touch consecutive addresses, and narrow blocks (few columns) still
+// use every thread.
 constexpr int kUpdRows = 16;
+
+struct UpdMap {
+  int kc, rpt;  // columns per tile, rows per row step
+  __host__ __device__ UpdMap(int k) : kc(k < 256 ? k : 256), rpt(256 / (k < 256 ? k : 256)) {}
+};
 
 // CGLS update: alpha_c = gamma_c / qq_c (0 for inactive columns)
 //   x += alpha p (n rows) ; s -= alpha q (m rows)
@@ -1094,14 +1101,17 @@ __global__ __launch_bounds__(256) void k_cgls_xs(int64_t n, int64_t m, int k,
                                                  const int* __restrict__ active, double* __restrict__ x,
                                                  const double* __restrict__ p, double* __restrict__ s,
                                                  const double* __restrict__ q) {
-  const int c = (int)blockIdx.y * 256 + (int)threadIdx.x;
+  const UpdMap mp(k);
+  const int t = (int)threadIdx.x;
+  if (t >= mp.rpt * mp.kc) return;
+  const int c = (int)blockIdx.y * mp.kc + t % mp.kc;
   if (c >= k) return;
   const double al = (active[c] && qq[c] > 0.0) ? gamma[c] / qq[c] : 0.0;
   if (al == 0.0) return;
-  const int64_t r0 = (int64_t)blockIdx.x * kUpdRows;
+  const int64_t r0 = (int64_t)blockIdx.x * mp.rpt * kUpdRows + t / mp.kc;
 #pragma unroll 4
-  for (int t = 0; t < kUpdRows; ++t) {
-    const int64_t row = r0 + t;
+  for (int u = 0; u < kUpdRows; ++u) {
+    const int64_t row = r0 + (int64_t)u * mp.rpt;
     const int64_t i = row * k + c;
     if (row < n) x[i] = fma(al, p[i], x[i]);
     if (row < m) s[i] = fma(-al, q[i], s[i]);
@@ -1113,14 +1123,18 @@ __global__ __launch_bounds__(256) void k_cgls_p(int64_t n, int k, const double* 
                                                 const double* __restrict__ gamma,
                                                 const int* __restrict__ active,
                                                 const double* __restrict__ r, double* __restrict__ p) {
-  const int c = (int)blockIdx.y * 256 + (int)threadIdx.x;
+  const UpdMap mp(k);
+  const int t = (int)threadIdx.x;
+  if (t >= mp.rpt * mp.kc) return;
+  const int c = (int)blockIdx.y * mp.kc + t % mp.kc;
   if (c >= k || !active[c]) return;
   const double be = gamma[c] > 0.0 ? gnew[c] / gamma[c] : 0.0;
-  const int64_t r0 = (int64_t)blockIdx.x * kUpdRows;
-  const int rows = (int)(n - r0 < kUpdRows ? n - r0 : kUpdRows);
+  const int64_t r0 = (int64_t)blockIdx.x * mp.rpt * kUpdRows + t / mp.kc;
 #pragma unroll 4
-  for (int t = 0; t < rows; ++t) {
-    const int64_t i = (r0 + t) * k + c;
+  for (int u = 0; u < kUpdRows; ++u) {
+    const int64_t row = r0 + (int64_t)u * mp.rpt;
+    if (row >= n) break;
+    const int64_t i = row * k + c;
     p[i] = fma(be, p[i], r[i]);
   }
 }
@@ -1131,15 +1145,19 @@ __global__ __launch_bounds__(256) void k_cg_wr(int64_t n, int k, const double* _
                                                const int* __restrict__ active, double* __restrict__ w,
                                                const double* __restrict__ p, double* __restrict__ r,
                                                const double* __restrict__ q) {
-  const int c = (int)blockIdx.y * 256 + (int)threadIdx.x;
+  const UpdMap mp(k);
+  const int t = (int)threadIdx.x;
+  if (t >= mp.rpt * mp.kc) return;
+  const int c = (int)blockIdx.y * mp.kc + t % mp.kc;
   if (c >= k) return;
   const double al = (active[c] && pq[c] > 0.0) ? rr[c] / pq[c] : 0.0;
   if (al == 0.0) return;
-  const int64_t r0 = (int64_t)blockIdx.x * kUpdRows;
-  const int rows = (int)(n - r0 < kUpdRows ? n - r0 : kUpdRows);
+  const int64_t r0 = (int64_t)blockIdx.x * mp.rpt * kUpdRows + t / mp.kc;
 #pragma unroll 4
-  for (int t = 0; t < rows; ++t) {
-    const int64_t i = (r0 + t) * k + c;
+  for (int u = 0; u < kUpdRows; ++u) {
+    const int64_t row = r0 + (int64_t)u * mp.rpt;
+    if (row >= n) break;
+    const int64_t i = row * k + c;
     w[i] = fma(al, p[i], w[i]);
     r[i] = fma(-al, q[i], r[i]);
   }
@@ -1316,6 +1334,61 @@ static void ts_proj_t(nsp_ctx* c, const int* cond, int64_t n, const VT* z, int64
 
 int64_t ts_part_c_len(int64_t n, int nc) { return ((n + kWave - 1) / kWave) * nc * nc; }
 
+// The projection and the update of the tall-skinny pair on their own, for a
+// DA-column row-interleaved block C and two different bases (the deflated CG's
+// directions are projected with one matrix and corrected with another):
+// h (k x DA, basis-column major) = Z^T C, and C -= Z h.
+int64_t ts_tn_parts_len(int64_t n, int k, int d) {
+  const int64_t chunk = ts_chunk_rows(n, k, d, 8);
+  return ((n + chunk - 1) / chunk) * (int64_t)k * d;
+}
+
+template <int DA>
+static void ts_tn_only_t(nsp_ctx* c, int64_t n, const double* z, int64_t ldz, int k, const double* a0,
+                         double* h, double* hpart) {
+  CPair<double, DA, 1> cc{const_cast<double*>(a0), nullptr};
+  const int64_t chunk = ts_chunk_rows(n, k, DA, 8);
+  const unsigned nchunks = (unsigned)((n + chunk - 1) / chunk);
+  const unsigned gy = (unsigned)((k + TsShape<DA, 8>::JB - 1) / TsShape<DA, 8>::JB);
+  k_ts_tn<double, DA, 1><<<dim3(nchunks, gy), TsShape<DA, 8>::NWT * kWave, 0, c->stream>>>(
+      nullptr, n, chunk, z, ldz, k, cc, hpart);
+  k_reduce_cols<<<nblk((int64_t)k * DA, 32), 256, 0, c->stream>>>(nullptr, (int)nchunks, k * DA, hpart, h);
+  NSP_HIP(hipGetLastError());
+}
+
+template <int DA>
+static void ts_nn_only_t(nsp_ctx* c, int64_t n, const double* z, int64_t ldz, int k, const double* h,
+                         double* a0) {
+  CPair<double, DA, 1> cc{a0, nullptr};
+  constexpr int TR = ts_nn_rows<double, DA>();
+  constexpr int nt = ts_nn_waves<double, DA>() * kWave;
+  k_ts_nn_v<double, DA, 1, false><<<(unsigned)((n + TR - 1) / TR), nt, 0, c->stream>>>(
+      nullptr, n, z, ldz, k, h, cc, nullptr);
+  NSP_HIP(hipGetLastError());
+}
+
+void ts_tn_only(nsp_ctx* c, int d, int64_t n, const double* z, int64_t ldz, int k, const double* a0,
+                double* h, double* hpart) {
+  switch (d) {
+    case 1: ts_tn_only_t<1>(c, n, z, ldz, k, a0, h, hpart); break;
+    case 2: ts_tn_only_t<2>(c, n, z, ldz, k, a0, h, hpart); break;
+    case 4: ts_tn_only_t<4>(c, n, z, ldz, k, a0, h, hpart); break;
+    case 8: ts_tn_only_t<8>(c, n, z, ldz, k, a0, h, hpart); break;
+    default: throw Error(NSP_ERR_ARG, "ts_tn_only: d must be 1, 2, 4 or 8");
+  }
+}
+
+void ts_nn_only(nsp_ctx* c, int d, int64_t n, const double* z, int64_t ldz, int k, const double* h,
+                double* a0) {
+  switch (d) {
+    case 1: ts_nn_only_t<1>(c, n, z, ldz, k, h, a0); break;
+    case 2: ts_nn_only_t<2>(c, n, z, ldz, k, h, a0); break;
+    case 4: ts_nn_only_t<4>(c, n, z, ldz, k, h, a0); break;
+    case 8: ts_nn_only_t<8>(c, n, z, ldz, k, h, a0); break;
+    default: throw Error(NSP_ERR_ARG, "ts_nn_only: d must be 1, 2, 4 or 8");
+  }
+}
+
 template <typename VT, int DA, int NA>
 static void ts_scale_t(nsp_ctx* c, const int* cond, int64_t n, VT* a0, VT* a1, const double* part_c,
                        double* rinv, VT* z0, int64_t ldz) {
@@ -1442,7 +1515,10 @@ int64_t coldots_parts(int64_t rows) {
 void cgls_xs(nsp_ctx* c, int64_t n, int64_t m, int k, const double* gamma, const double* qq,
              const int* active, double* x, const double* p, double* s, const double* q) {
   if (k <= 0) return;
-  const dim3 grid((unsigned)((std::max(n, m) + kUpdRows - 1) / kUpdRows), (unsigned)((k + 255) / 256));
+  const UpdMap mp(k);
+  const int64_t rows_per_block = (int64_t)mp.rpt * kUpdRows;
+  const dim3 grid((unsigned)((std::max(n, m) + rows_per_block - 1) / rows_per_block),
+                  (unsigned)((k + mp.kc - 1) / mp.kc));
   k_cgls_xs<<<grid, 256, 0, c->stream>>>(n, m, k, gamma, qq, active, x, p, s, q);
   NSP_HIP(hipGetLastError());
 }
@@ -1450,7 +1526,9 @@ void cgls_xs(nsp_ctx* c, int64_t n, int64_t m, int k, const double* gamma, const
 void cgls_p(nsp_ctx* c, int64_t n, int k, const double* gnew, const double* gamma, const int* active,
             const double* r, double* p) {
   if (k <= 0 || n <= 0) return;
-  const dim3 grid((unsigned)((n + kUpdRows - 1) / kUpdRows), (unsigned)((k + 255) / 256));
+  const UpdMap mp(k);
+  const int64_t rows_per_block = (int64_t)mp.rpt * kUpdRows;
+  const dim3 grid((unsigned)((n + rows_per_block - 1) / rows_per_block), (unsigned)((k + mp.kc - 1) / mp.kc));
   k_cgls_p<<<grid, 256, 0, c->stream>>>(n, k, gnew, gamma, active, r, p);
   NSP_HIP(hipGetLastError());
 }
@@ -1458,7 +1536,9 @@ void cgls_p(nsp_ctx* c, int64_t n, int k, const double* gnew, const double* gamm
 void cg_wr(nsp_ctx* c, int64_t n, int k, const double* rr, const double* pq, const int* active,
            double* w, const double* p, double* r, const double* q) {
   if (k <= 0 || n <= 0) return;
-  const dim3 grid((unsigned)((n + kUpdRows - 1) / kUpdRows), (unsigned)((k + 255) / 256));
+  const UpdMap mp(k);
+  const int64_t rows_per_block = (int64_t)mp.rpt * kUpdRows;
+  const dim3 grid((unsigned)((n + rows_per_block - 1) / rows_per_block), (unsigned)((k + mp.kc - 1) / mp.kc));
   k_cg_wr<<<grid, 256, 0, c->stream>>>(n, k, rr, pq, active, w, p, r, q);
   NSP_HIP(hipGetLastError());
 }

@@ -236,6 +236,91 @@ __global__ __launch_bounds__(kThreads) void k_sddmm(int64_t nrows, int k, const 
   }
 }
 
+// k_spmm_wide for narrow blocks (k <= 4 LPR columns): LPR lanes per row with
+// 4 columns each, 64 / LPR rows per wavefront, so that a block of a few
+// columns (the backward pass's right-hand sides) keeps every lane busy.  The
+// same products, sums and partials (part[block * k + c], rows and waves
+// summed in a fixed order) as k_spmm_wide.
+template <bool VEC, int RED, int LPR>
+__global__ __launch_bounds__(kThreads) void k_spmm_narrow(int64_t nrows, int k,
+                                                          const int32_t* __restrict__ rp,
+                                                          const int32_t* __restrict__ ci,
+                                                          const double* __restrict__ av,
+                                                          const double* __restrict__ x,
+                                                          double* __restrict__ y,
+                                                          double* __restrict__ part) {
+  constexpr int CPL = 4;
+  constexpr int RPW = kWave / LPR;
+  constexpr int NWB = kThreads / kWave;
+  constexpr bool SQ = RED != 0;
+  __shared__ double red[SQ ? kThreads * CPL : 1];
+  const int lane = threadIdx.x % kWave, wid = threadIdx.x / kWave;
+  const int sub = lane / LPR;         // the lane's row within the wavefront's group
+  const int cb = (lane % LPR) * CPL;  // the lane's first column
+  const bool full = cb + CPL <= k;
+  const int64_t nw = (int64_t)gridDim.x * NWB;
+  double sq[CPL];
+#pragma unroll
+  for (int t = 0; t < CPL; ++t) sq[t] = 0.0;
+  for (int64_t g = (int64_t)blockIdx.x * NWB + wid; g * RPW < nrows; g += nw) {
+    const int64_t row = g * RPW + sub;
+    if (row >= nrows || cb >= k) continue;
+    const int beg = rp[row], end = rp[row + 1];
+    double acc[CPL];
+#pragma unroll
+    for (int t = 0; t < CPL; ++t) acc[t] = 0.0;
+    for (int p = beg; p < end; ++p) {
+      const double a = av[p];
+      const double* xr = x + (int64_t)ci[p] * k + cb;
+      if (VEC && full) {
+        const double2 u = *reinterpret_cast<const double2*>(xr);
+        const double2 v = *reinterpret_cast<const double2*>(xr + 2);
+        acc[0] = fma(a, u.x, acc[0]);
+        acc[1] = fma(a, u.y, acc[1]);
+        acc[2] = fma(a, v.x, acc[2]);
+        acc[3] = fma(a, v.y, acc[3]);
+      } else {
+#pragma unroll
+        for (int t = 0; t < CPL; ++t)
+          if (cb + t < k) acc[t] = fma(a, xr[t], acc[t]);
+      }
+    }
+    double* yr = y + row * k + cb;
+    if (VEC && full) {
+      *reinterpret_cast<double2*>(yr) = make_double2(acc[0], acc[1]);
+      *reinterpret_cast<double2*>(yr + 2) = make_double2(acc[2], acc[3]);
+    } else {
+#pragma unroll
+      for (int t = 0; t < CPL; ++t)
+        if (cb + t < k) yr[t] = acc[t];
+    }
+    if constexpr (RED == 1) {
+#pragma unroll
+      for (int t = 0; t < CPL; ++t) sq[t] = fma(acc[t], acc[t], sq[t]);
+    } else if constexpr (RED == 2) {
+      const double* xo = x + row * k + cb;
+#pragma unroll
+      for (int t = 0; t < CPL; ++t)
+        if (cb + t < k) sq[t] = fma(acc[t], xo[t], sq[t]);
+    }
+  }
+  if constexpr (SQ) {
+#pragma unroll
+    for (int t = 0; t < CPL; ++t) red[threadIdx.x * CPL + t] = sq[t];
+    __syncthreads();
+    // column j = l * CPL + t: its lanes are l, l + LPR, ... of every wavefront
+    const int j = threadIdx.x;
+    if (j < k) {
+      const int l = j / CPL, t = j % CPL;
+      double s4[4] = {0.0, 0.0, 0.0, 0.0};
+      for (int w = 0; w < NWB; ++w)
+#pragma unroll 4
+        for (int r = 0; r < RPW; ++r) s4[r & 3] += red[(w * kWave + r * LPR + l) * CPL + t];
+      part[(int64_t)blockIdx.x * k + j] = (s4[0] + s4[1]) + (s4[2] + s4[3]);
+    }
+  }
+}
+
 // ---------------------------------------------------------------------------
 // set-up kernels
 // ---------------------------------------------------------------------------
@@ -653,9 +738,25 @@ int spmm_wide(nsp_ctx* c, const Csr& a, int k, const double* x, double* y, doubl
   if (a.rows == 0 || k == 0) return 0;
   static_assert(kThreads == 4 * kWave, "one 256-column panel per block");
   if (dot) NSP_REQUIRE(a.rows == a.cols, "the fused x . Ax sums need a square A");
-  const int grid = (int)std::min<int64_t>(nblocks(a.rows, kThreads / kWave), kWideBlocks);
   const bool vec = k % 2 == 0;
   const int red = part ? (dot ? 2 : 1) : 0;
+  if (k <= 64) {
+    // narrow block: LPR lanes of 4 columns per row, 64 / LPR rows per wavefront
+    const int lpr = k <= 4 ? 1 : k <= 8 ? 2 : k <= 16 ? 4 : k <= 32 ? 8 : 16;
+    const int64_t groups = (a.rows + kWave / lpr - 1) / (kWave / lpr);
+    const int grid = (int)std::min<int64_t>(nblocks(groups, kThreads / kWave), kWideBlocks);
+#define NSP_N(V, R, L) k_spmm_narrow<V, R, L><<<grid, kThreads, 0, c->stream>>>(a.rows, k, a.rowptr, a.colind, a.val, x, y, part)
+#define NSP_NL(V, R) switch (lpr) { case 1: NSP_N(V, R, 1); break; case 2: NSP_N(V, R, 2); break; \
+    case 4: NSP_N(V, R, 4); break; case 8: NSP_N(V, R, 8); break; default: NSP_N(V, R, 16); }
+#define NSP_NV(R) if (vec) { NSP_NL(true, R) } else { NSP_NL(false, R) }
+    if (red == 2) { NSP_NV(2); } else if (red == 1) { NSP_NV(1); } else { NSP_NV(0); }
+#undef NSP_NV
+#undef NSP_NL
+#undef NSP_N
+    NSP_HIP(hipGetLastError());
+    return grid;
+  }
+  const int grid = (int)std::min<int64_t>(nblocks(a.rows, kThreads / kWave), kWideBlocks);
 #define NSP_W(V, R) k_spmm_wide<V, R><<<grid, kThreads, 0, c->stream>>>(a.rows, k, a.rowptr, a.colind, a.val, x, y, part)
 #define NSP_WV(R) if (vec) NSP_W(true, R); else NSP_W(false, R)
   if (red == 2) { NSP_WV(2); } else if (red == 1) { NSP_WV(1); } else { NSP_WV(0); }

@@ -1153,7 +1153,27 @@ void run_backward(nsp_ctx* c, const double* dLdV, int64_t ld, double* grad, doub
   if (rd > 0) tol = std::max(tol, 1e-12);  // the deflated recurrence's attainable level
   DBuf b_mu;
   double* mu = rd > 0 ? alloc_as<double>(b_mu, (size_t)kc * rd) : nullptr;
+  // For a right-hand side of 1, 2, 4 or 8 columns the two products of every
+  // iteration are the tall-skinny pair of the reorthogonalisation (HBM
+  // streaming kernels) on column-major copies of W and M W_s; a library GEMM
+  // with a few columns reads the long operand far below the HBM rate.
+  const bool ts_defl = rd > 0 && (kc == 1 || kc == 2 || kc == 4 || kc == 8);
+  const int64_t ldd = (n + 63) / 64 * 64;
+  DBuf b_wcm, b_mcm, b_hp;
+  double *wcm = nullptr, *mcm = nullptr, *hp = nullptr;
+  if (ts_defl) {
+    wcm = alloc_as<double>(b_wcm, (size_t)(ldd * rd));
+    mcm = alloc_as<double>(b_mcm, (size_t)(ldd * rd));
+    rows_to_colmajor(c, n, rd, c->dfW.as<double>(), wcm, ldd);
+    rows_to_colmajor(c, n, rd, c->dfMWs.as<double>(), mcm, ldd);
+    hp = alloc_as<double>(b_hp, (size_t)ts_tn_parts_len(n, rd, kc));
+  }
   auto deflate_direction = [&](const double* res, double* dir) {
+    if (ts_defl) {
+      ts_tn_only(c, kc, n, mcm, ldd, rd, res, mu, hp);
+      ts_nn_only(c, kc, n, wcm, ldd, rd, mu, dir);
+      return;
+    }
     dgemm_nt_long(c, kc, rd, n, res, kc, c->dfMWs.as<double>(), rd, mu, b_long);
     dgemm(c, rocblas_operation_none, rocblas_operation_none, kc, n, rd, -1.0, mu, kc,
           c->dfW.as<double>(), rd, 1.0, dir, kc);
