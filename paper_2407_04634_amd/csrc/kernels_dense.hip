@@ -471,7 +471,7 @@ struct CPair {
 // Basis columns per wave (JW) and per block (JB) of the projection kernel.
 // Each column is one 16-byte load per lane and row group, kept in its storage
 // precision until its FMAs, so FP32 keeps as many loads in flight as FP64.
-constexpr int ts_jw(int nc) { return nc >= 16 ? 2 : (nc >= 4 ? 4 : 8); }
+constexpr int ts_jw(int nc) { return nc >= 16 ? 4 : (nc >= 4 ? 4 : 8); }
 constexpr int kTsWaves = 4;  // waves per block (8 measured slower: fewer, heavier blocks)
 template <int NC, int ESIZE = 8> struct TsShape {
   static constexpr int JW = ts_jw(NC);
