@@ -451,7 +451,7 @@ __global__ void k_w_reset(int col0, int ncols, double u_d, double* w, int ldw) {
 // Tall-skinny pair of the (partial) reorthogonalisation, classical
 // Gram-Schmidt (Sec. 4.2):
 //   H = Z^T C   (k x NC)  k_ts_tn writes per-row-chunk partials, k_reduce_cols sums them
-//   C = C - Z H           k_ts_nn_v (NC <= 8), k_ts_nn (wider)
+//   C = C - Z H           k_ts_nn_v (NC <= 8, and 16 in FP64), k_ts_nn (16 in FP32)
 // C is NC columns held as NA row-interleaved arrays of DA columns each
 // (NC = NA * DA): for the reorthogonalisation of [Q_ell, Q_ell+1] NA = 2.
 // When ``cond`` is non-null the kernels do nothing unless *cond != 0.
@@ -645,7 +645,7 @@ __global__ __launch_bounds__(256) void k_reduce_cols(const int* cond, int nparts
   }
 }
 
-// C -= Z H for C wider than 8 columns (d = 8 pair).  A block handles 64 rows;
+// C -= Z H for the 16-column FP32 pair (d = 8).  A block handles 64 rows;
 // its 4 waves split the k columns and the partial sums are combined in LDS.
 // With GRAM the block also writes the partial Gram matrix of the updated rows
 // (for the final Cholesky QR).
@@ -667,7 +667,18 @@ __global__ __launch_bounds__(kThreads) void k_ts_nn(const int* cond, int64_t n,
   for (int c = 0; c < NC; ++c) acc[c] = 0.0;
   if (r < n) {
     const VT* zr = z + r;
-    for (int j = jb; j < je; ++j) {
+    // four column loads in flight, the products still in column order
+    int j = jb;
+    for (; j + 3 < je; j += 4) {
+      double zv[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) zv[u] = (double)zr[(int64_t)(j + u) * ldz];
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+#pragma unroll
+        for (int c = 0; c < NC; ++c) acc[c] = fma(zv[u], h[(int64_t)(j + u) * NC + c], acc[c]);
+    }
+    for (; j < je; ++j) {
       const double zv = (double)zr[(int64_t)j * ldz];
 #pragma unroll
       for (int c = 0; c < NC; ++c) acc[c] = fma(zv, h[(int64_t)j * NC + c], acc[c]);
@@ -676,32 +687,35 @@ __global__ __launch_bounds__(kThreads) void k_ts_nn(const int* cond, int64_t n,
 #pragma unroll
   for (int c = 0; c < NC; ++c) red[wid][lane][c] = acc[c];
   __syncthreads();
+  // the block's updated rows, for the Gram partials
+  __shared__ double orow[GRAM ? kWave : 1][NC];
   if (wid == 0) {
-    constexpr int NG = GRAM ? NC * NC : 1;
-    double g[NG];
+    double o[NC];
 #pragma unroll
-    for (int i = 0; i < NG; ++i) g[i] = 0.0;
+    for (int c = 0; c < NC; ++c) o[c] = 0.0;
     if (r < n) {
-      double o[NC];
 #pragma unroll
       for (int c = 0; c < NC; ++c) {
         const double s = red[0][lane][c] + red[1][lane][c] + red[2][lane][c] + red[3][lane][c];
         o[c] = (double)VT((double)cc.get(r, c) - s);
         cc.set(r, c, VT(o[c]));
       }
-      if constexpr (GRAM) {
-#pragma unroll
-        for (int a = 0; a < NC; ++a)
-#pragma unroll
-          for (int b = 0; b < NC; ++b) g[a + b * NC] += o[a] * o[b];
-      }
     }
     if constexpr (GRAM) {
 #pragma unroll
-      for (int i = 0; i < NG; ++i) {
-        const double v = wave_sum(g[i]);
-        if (lane == 0) part_c[(size_t)blockIdx.x * NG + i] = v;
-      }
+      for (int c = 0; c < NC; ++c) orow[lane][c] = o[c];
+    }
+  }
+  if constexpr (GRAM) {
+    // entry (a, b) of the block's partial Gram matrix per thread, summed over
+    // the block's rows in order (no per-thread NC x NC accumulator)
+    __syncthreads();
+    constexpr int NG = NC * NC;
+    for (int i = threadIdx.x; i < NG; i += blockDim.x) {
+      const int a = i % NC, b = i / NC;
+      double g = 0.0;
+      for (int l = 0; l < kWave; ++l) g = fma(orow[l][a], orow[l][b], g);
+      part_c[(size_t)blockIdx.x * NG + i] = g;
     }
   }
 }
@@ -712,7 +726,12 @@ template <typename VT, int NC> constexpr int ts_nn_waves() {
   return 8 * NC * kWave * RowVec<VT>::R * 8 > 65536 ? 4 : 8;
 }
 
-// C -= Z H for NC <= 8.  A block owns 64 * RV consecutive rows (RV rows per
+// Whether the C -= Z H update of NC columns takes the vectorised kernel
+// k_ts_nn_v: up to 8 columns, and the 16-column FP64 pair (its per-wave partial
+// sums still fit 64 KB of LDS with 4 waves).
+template <typename VT, int NC> constexpr bool ts_nn_vec() { return NC <= 8 || (NC == 16 && sizeof(VT) == 8); }
+
+// C -= Z H, vectorised.  A block owns 64 * RV consecutive rows (RV rows per
 // lane, one 16-byte load per basis column); its waves split the k columns,
 // unrolled by 4 so every wave keeps several loads in flight, and combine the
 // partial sums in LDS.  With GRAM it also writes the block's partial Gram
@@ -727,7 +746,7 @@ __global__ __launch_bounds__(512) void k_ts_nn_v(const int* cond, int64_t n,
   constexpr int RV = RowVec<VT>::R;
   constexpr int NW = ts_nn_waves<VT, NC>();
   constexpr int TR = kWave * RV;  // rows per block
-  static_assert(NC <= 8, "wider C uses k_ts_nn");
+  static_assert(ts_nn_vec<VT, NC>(), "other widths use k_ts_nn");
   if (cond && *cond == 0) return;
   __shared__ double red[NW][NC][TR];
   // the wave index is uniform: said explicitly, the column indices and the
@@ -846,7 +865,9 @@ __device__ bool kahan_parlett_ok(int k, const double* g) {
 }
 
 // Rows per block of the C -= Z H kernel (and so the number of Gram partials).
-template <typename VT, int NC> constexpr int ts_nn_rows() { return NC <= 8 ? kWave * RowVec<VT>::R : kWave; }
+template <typename VT, int NC> constexpr int ts_nn_rows() {
+  return ts_nn_vec<VT, NC>() ? kWave * RowVec<VT>::R : kWave;
+}
 
 // One block: Gram of C from the partials, Cholesky; writes R^{-1} then R (NC x NC each).
 template <int NC>
@@ -1311,7 +1332,7 @@ static void ts_proj_t(nsp_ctx* c, const int* cond, int64_t n, const VT* z, int64
     NSP_HIP(hipEventRecord(ev_tn, c->stream));
   }
   if (ev_red) NSP_HIP(hipEventRecord(ev_red, c->stream));
-  if constexpr (NC <= 8) {
+  if constexpr (ts_nn_vec<VT, NC>()) {
     constexpr int nt = ts_nn_waves<VT, NC>() * kWave;
     if (gram) {
       k_ts_nn_v<VT, DA, NA, true><<<nnblocks, nt, 0, c->stream>>>(cond, n, z, ldz, k, h, cc, part_c);
