@@ -625,6 +625,100 @@ __global__ __launch_bounds__(kThreads) void k_ts_tn(const int* cond, int64_t n, 
     }
 }
 
+// H = Z^T C for the 16-column FP64 pair (d = 8) on the matrix cores.  With 16
+// columns of C the projection is a dense contraction: v_mfma_f64_16x16x4f64
+// multiplies a 16 x 4 slice of Z^T (16 basis columns, 4 rows) by the 4 x 16
+// slice of C on the same rows, so every C value a lane loads serves kMfTiles
+// x 16 basis columns (the vector kernel reloads C for every 4 columns and
+// keeps 64 accumulators per lane).  A block owns kMfCols basis columns and a
+// row chunk; its 4 waves take interleaved 32-row steps of the chunk (lane
+// group g = lane / 16 holds rows g*8 .. g*8+7 of the step, lane % 16 names the
+// basis column in the A operand and the C column in the B operand) and their
+// 16 x 16 tiles are summed in LDS in wave order.  Operand and output layout of
+// the instruction (checked on the device with random operands): lane l gives
+// A(l % 16, l / 16) and B(l / 16, l % 16); register v of lane l holds D(l / 16
+// + 4 v, l % 16).
+constexpr int kMfTiles = 4;               // 16-column tiles per block
+constexpr int kMfCols = 16 * kMfTiles;    // basis columns per block
+constexpr int kMfRows = 8;                // rows per lane group and step
+typedef double mf_v4d __attribute__((ext_vector_type(4)));
+
+template <int DA, int NA>
+__global__ __launch_bounds__(kThreads) void k_ts_tn_mfma(const int* cond, int64_t n, int64_t chunk,
+                                                         const double* __restrict__ z, int64_t ldz,
+                                                         int k, CPair<double, DA, NA> cc,
+                                                         double* __restrict__ hpart) {
+  static_assert(DA * NA == 16 && NA == 2, "the 16-column pair");
+  static_assert(kThreads == 4 * kWave, "four waves per block");
+  constexpr int NC = 16;
+  constexpr int STEP = 4 * kMfRows;  // rows per wave step
+  if (cond && *cond == 0) return;
+  __shared__ double red[4][kMfTiles][4][kWave];
+  const int lane = threadIdx.x % kWave, wid = threadIdx.x / kWave;
+  const int col = lane % 16, grp = lane / 16;
+  const int64_t r0 = (int64_t)blockIdx.x * chunk;
+  const int64_t r1 = min(n, r0 + chunk);
+  const int j0 = blockIdx.y * kMfCols;
+  mf_v4d acc[kMfTiles];
+#pragma unroll
+  for (int t = 0; t < kMfTiles; ++t) acc[t] = mf_v4d{0.0, 0.0, 0.0, 0.0};
+  // the C column this lane feeds to the B operand
+  const double* cp = col < DA ? cc.a0 + col : cc.a1 + (col - DA);
+  const bool fullc = j0 + kMfCols <= k;  // all of the block's basis columns exist
+  for (int64_t rb = r0 + (int64_t)wid * STEP; rb < r1; rb += 4 * STEP) {
+    const int64_t rr = rb + grp * kMfRows;
+    double b[kMfRows];
+    double a[kMfTiles][kMfRows];
+    if (fullc && rb + STEP <= r1) {
+      // whole step: every load issued before the first product
+#pragma unroll
+      for (int s = 0; s < kMfRows; ++s) b[s] = cp[(rr + s) * DA];
+#pragma unroll
+      for (int t = 0; t < kMfTiles; ++t) {
+        const double2* zp =
+            reinterpret_cast<const double2*>(z + (int64_t)(j0 + 16 * t + col) * ldz + rr);
+#pragma unroll
+        for (int s = 0; s < kMfRows; s += 2) {
+          const double2 v = zp[s / 2];
+          a[t][s] = v.x;
+          a[t][s + 1] = v.y;
+        }
+      }
+    } else {
+      // ragged step (rows past the chunk or columns past k read as zero)
+#pragma unroll
+      for (int s = 0; s < kMfRows; ++s) b[s] = rr + s < r1 ? cp[(rr + s) * DA] : 0.0;
+#pragma unroll
+      for (int t = 0; t < kMfTiles; ++t) {
+        const int jj = j0 + 16 * t + col;
+#pragma unroll
+        for (int s = 0; s < kMfRows; s += 2) {
+          double2 v = double2{0.0, 0.0};
+          if (jj < k) v = load_vec<double>(z + (int64_t)jj * ldz, rr + s, r1);
+          a[t][s] = v.x;
+          a[t][s + 1] = v.y;
+        }
+      }
+    }
+#pragma unroll
+    for (int s = 0; s < kMfRows; ++s)
+#pragma unroll
+      for (int t = 0; t < kMfTiles; ++t)
+        acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[t][s], b[s], acc[t], 0, 0, 0);
+  }
+#pragma unroll
+  for (int t = 0; t < kMfTiles; ++t)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) red[wid][t][v][lane] = acc[t][v];
+  __syncthreads();
+  for (int e = threadIdx.x; e < kMfTiles * 4 * kWave; e += kThreads) {
+    const int l = e % kWave, v = (e / kWave) % 4, t = e / (4 * kWave);
+    const double sum = ((red[0][t][v][l] + red[1][t][v][l]) + red[2][t][v][l]) + red[3][t][v][l];
+    const int j = j0 + 16 * t + l / 16 + 4 * v;
+    if (j < k) hpart[((int64_t)blockIdx.x * k + j) * NC + (l % 16)] = sum;
+  }
+}
+
 // out[v] = sum_b part[b * nv + v]  (fixed order); 32 values x 8 part-groups per block
 __global__ __launch_bounds__(256) void k_reduce_cols(const int* cond, int nparts, int nv,
                                                      const double* __restrict__ part,
@@ -1292,9 +1386,12 @@ void w_reset(nsp_ctx* c, int col0, int ncols, double u_d, double* w, int ldw) {
 // at least 1024 rows (so each lane accumulates >= 16 rows before the wave sum).
 // Row chunk of the H = Z^T C kernel: about 2048 blocks over (chunks x column
 // groups), at least 1024 rows, a multiple of 256 rows (aligned vector loads).
+// Whether the projection of NC columns runs on the matrix cores (k_ts_tn_mfma).
+constexpr bool ts_tn_mfma(int nc, int esize) { return nc == 16 && esize == 8; }
+
 int64_t ts_chunk_rows(int64_t n, int k, int nc, int esize) {
-  const int jb = kTsWaves * ts_jw(nc);  // TsShape<NC, esize>::JB
-  (void)esize;
+  // basis columns per block: TsShape<NC, esize>::JB, or kMfCols on the matrix cores
+  const int jb = ts_tn_mfma(nc, esize) ? kMfCols : kTsWaves * ts_jw(nc);
   const int64_t col_groups = std::max<int64_t>(1, (k + jb - 1) / jb);
   const int64_t chunks = std::max<int64_t>(1, 2048 / col_groups);
   int64_t rows = (n + chunks - 1) / chunks;
@@ -1322,9 +1419,15 @@ static void ts_proj_t(nsp_ctx* c, const int* cond, int64_t n, const VT* z, int64
   if (k > 0) {
     const int64_t chunk = ts_chunk_rows(n, k, NC, (int)sizeof(VT));
     const unsigned nchunks = (unsigned)((n + chunk - 1) / chunk);
-    const unsigned gy = (unsigned)((k + TsShape<NC, sizeof(VT)>::JB - 1) / TsShape<NC, sizeof(VT)>::JB);
-    k_ts_tn<VT, DA, NA><<<dim3(nchunks, gy), TsShape<NC, sizeof(VT)>::NWT * kWave, 0, c->stream>>>(
-        cond, n, chunk, z, ldz, k, cc, hpart);
+    if constexpr (ts_tn_mfma(NC, sizeof(VT))) {
+      const unsigned gy = (unsigned)((k + kMfCols - 1) / kMfCols);
+      k_ts_tn_mfma<DA, NA><<<dim3(nchunks, gy), kThreads, 0, c->stream>>>(cond, n, chunk, z, ldz, k,
+                                                                          cc, hpart);
+    } else {
+      const unsigned gy = (unsigned)((k + TsShape<NC, sizeof(VT)>::JB - 1) / TsShape<NC, sizeof(VT)>::JB);
+      k_ts_tn<VT, DA, NA><<<dim3(nchunks, gy), TsShape<NC, sizeof(VT)>::NWT * kWave, 0, c->stream>>>(
+          cond, n, chunk, z, ldz, k, cc, hpart);
+    }
     if (ev_tn) NSP_HIP(hipEventRecord(ev_tn, c->stream));
     k_reduce_cols<<<nblk((int64_t)k * NC, 32), 256, 0, c->stream>>>(cond, (int)nchunks, k * NC,
                                                                     hpart, h);
