@@ -22,6 +22,37 @@ __device__ __forceinline__ T group_sum(T v) {
   return v;
 }
 
+// Sums of X(:, i) P(:, j) over the rows of two row-interleaved n x 8 blocks
+// on the matrix cores (v_mfma_f64_16x16x4f64), for the 8 x 8 Gram-type
+// matrices of block size 8.  A wave takes 8 consecutive rows at a time, lane l
+// holding row g8_row(l) and column l % 8 of them (the 64 values are read in
+// one coalesced pass).  Lane l gives A(l % 16, l / 16) and B(l / 16, l % 16),
+// so with X's value as A and P's as B the product's diagonal 8 x 8 blocks are
+// the sums over rows 0..3 (D(i, j)) and rows 4..7 (D(8 + i, 8 + j)); the
+// off-diagonal blocks mix rows and are dropped.  Register v of lane l holds
+// D(l / 16 + 4 v, l % 16) (layout checked on the device).
+typedef double g8_acc __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ int g8_row(int lane) { return 4 * ((lane >> 3) & 1) + (lane >> 4); }
+__device__ __forceinline__ int g8_off(int lane) { return g8_row(lane) * 8 + (lane & 7); }
+__device__ __forceinline__ g8_acc g8_step(double xv, double pv, g8_acc acc) {
+  return __builtin_amdgcn_mfma_f64_16x16x4f64(xv, pv, acc, 0, 0, 0);
+}
+// out[i * 8 + j] = the block's sum: the two diagonal blocks of every wave, the
+// waves in order.  tile: shared, (blockDim.x / 64) * 256 doubles.  Every thread
+// of the block calls it.
+__device__ __forceinline__ void g8_finish(const g8_acc& acc, double* tile, double* out) {
+  const int lane = threadIdx.x % kWave, wid = threadIdx.x / kWave, nw = blockDim.x / kWave;
+#pragma unroll
+  for (int v = 0; v < 4; ++v) tile[wid * 256 + (lane / 16 + 4 * v) * 16 + lane % 16] = acc[v];
+  __syncthreads();
+  if (threadIdx.x < 64) {
+    const int i = threadIdx.x / 8, j = threadIdx.x % 8;
+    double s = 0.0;
+    for (int w = 0; w < nw; ++w) s += tile[w * 256 + i * 16 + j] + tile[w * 256 + (8 + i) * 16 + 8 + j];
+    out[threadIdx.x] = s;
+  }
+}
+
 // Sum NV per-thread values over the block; the result is valid in thread 0.
 // smem must hold (blockDim.x / 64) * NV doubles.
 template <int NV>

@@ -35,6 +35,10 @@ struct WArgs {
 };
 
 // dense: Lanczos step.  Each returns its grid size = number of partials written.
+// Xi partials X^T P for block size 8 (n x 8 row-interleaved X and P) on the
+// matrix cores; returns the number of partials written to part.
+template <typename VT>
+int xi8_parts(nsp_ctx* c, int64_t n, const VT* x, const VT* p, double* part);
 template <typename VT>
 int sub_gram(nsp_ctx* c, int d, int64_t n, VT* p, const VT* x, const double* part_xi, int nparts_xi,
              double* xi_out, double* nrm_xi, double* part_g);

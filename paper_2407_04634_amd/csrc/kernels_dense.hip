@@ -267,6 +267,131 @@ __global__ __launch_bounds__(kThreads) void k_sub_gram(int64_t n, VT* __restrict
   }
 }
 
+// k_sub_gram for block size 8 on the matrix cores: the same Xi, the same
+// subtraction (per value, in the same order, so P is bit-identical), and the
+// Gram partials of P from g8_step with P's value as both operands.  Grid-stride
+// over 8-row groups, one group per wave and step; grid <= kRedBlocks.
+template <typename VT, bool XI, bool SUB>
+__global__ __launch_bounds__(kThreads) void k_sub_gram8(int64_t n, VT* __restrict__ p,
+                                                        const VT* __restrict__ x,
+                                                        const double* __restrict__ part_xi,
+                                                        int nparts_xi, double* xi_out,
+                                                        double* nrm_xi, double* __restrict__ part_g) {
+  constexpr int D = 8, NV = D * D;
+  __shared__ double smem[kSmem];
+  __shared__ double res[NV];
+  __shared__ double xs[NV];
+  if constexpr (XI) {
+    reduce_partials<NV>(part_xi, nparts_xi, res, smem);
+    if (threadIdx.x < NV) {
+      const int a = threadIdx.x % D, b = threadIdx.x / D;
+      xs[threadIdx.x] = 0.5 * (res[a + b * D] + res[b + a * D]);
+    }
+    __syncthreads();
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+      double f2 = 0.0;
+      for (int i = 0; i < NV; ++i) { xi_out[i] = xs[i]; f2 += xs[i] * xs[i]; }
+      if (nrm_xi) *nrm_xi = sqrt(f2);
+    }
+  }
+  const int lane = threadIdx.x % kWave, wid = threadIdx.x / kWave;
+  const int col = lane & 7, off = g8_off(lane);
+  const int64_t nv = n * D;
+  g8_acc acc = {0.0, 0.0, 0.0, 0.0};
+  auto value = [&](int64_t idx, double v, const double (&xr)[D]) {
+    if constexpr (SUB) {
+      double s = v;
+#pragma unroll
+      for (int b = 0; b < D; ++b) s = fma(-xr[b], xs[b + col * D], s);
+      const VT o = VT(s);
+      p[idx] = o;
+      v = (double)o;
+    }
+    return v;
+  };
+  constexpr int U = 2;  // groups per step, all loads first
+  const int64_t ng = (n + 7) / 8, stride = (int64_t)gridDim.x * (kThreads / kWave);
+  int64_t g = (int64_t)blockIdx.x * (kThreads / kWave) + wid;
+  for (; g + (U - 1) * stride < ng; g += U * stride) {
+    double v[U], xr[U][D];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int64_t idx = (g + u * stride) * 64 + off;
+      const bool in = idx < nv;
+      v[u] = in ? (double)p[idx] : 0.0;
+#pragma unroll
+      for (int b = 0; b < D; ++b) xr[u][b] = SUB && in ? (double)x[idx - col + b] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int64_t idx = (g + u * stride) * 64 + off;
+      const double w = idx < nv ? value(idx, v[u], xr[u]) : 0.0;
+      acc = g8_step(w, w, acc);
+    }
+  }
+  for (; g < ng; g += stride) {
+    const int64_t idx = g * 64 + off;
+    double w = 0.0;
+    if (idx < nv) {
+      double xr[D];
+#pragma unroll
+      for (int b = 0; b < D; ++b) xr[b] = SUB ? (double)x[idx - col + b] : 0.0;
+      w = value(idx, (double)p[idx], xr);
+    }
+    acc = g8_step(w, w, acc);
+  }
+  __syncthreads();  // smem is reused as the tile
+  g8_finish(acc, smem, part_g + (size_t)blockIdx.x * NV);
+}
+
+// Xi partials for block size 8 (X^T P over the block's rows), on the matrix
+// cores; the product kernel runs without its own Xi sums then.
+template <typename VT>
+__global__ __launch_bounds__(kThreads) void k_xi8(int64_t n, const VT* __restrict__ x,
+                                                  const VT* __restrict__ p,
+                                                  double* __restrict__ part) {
+  __shared__ double tile[(kThreads / kWave) * 256];
+  const int lane = threadIdx.x % kWave, wid = threadIdx.x / kWave;
+  const int off = g8_off(lane);
+  const int64_t nv = n * 8;
+  g8_acc acc = {0.0, 0.0, 0.0, 0.0};
+  constexpr int U = 4;
+  const int64_t ng = (n + 7) / 8, stride = (int64_t)gridDim.x * (kThreads / kWave);
+  int64_t g = (int64_t)blockIdx.x * (kThreads / kWave) + wid;
+  for (; g + (U - 1) * stride < ng; g += U * stride) {
+    double xv[U], pv[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int64_t idx = (g + u * stride) * 64 + off;
+      xv[u] = idx < nv ? (double)x[idx] : 0.0;
+      pv[u] = idx < nv ? (double)p[idx] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) acc = g8_step(xv[u], pv[u], acc);
+  }
+  for (; g < ng; g += stride) {
+    const int64_t idx = g * 64 + off;
+    acc = g8_step(idx < nv ? (double)x[idx] : 0.0, idx < nv ? (double)p[idx] : 0.0, acc);
+  }
+  g8_finish(acc, tile, part + (size_t)blockIdx.x * 64);
+}
+
+// Grid of the block-size-8 kernels above: one 8-row group per wave and step.
+static unsigned g8_grid(int64_t n) {
+  const int64_t groups = (n + 7) / 8, waves = kThreads / kWave;
+  return (unsigned)std::max<int64_t>(1, std::min<int64_t>((groups + waves - 1) / waves, kRedBlocks));
+}
+
+template <typename VT>
+int xi8_parts(nsp_ctx* c, int64_t n, const VT* x, const VT* p, double* part) {
+  const unsigned grid = g8_grid(n);
+  k_xi8<VT><<<grid, kThreads, 0, c->stream>>>(n, x, p, part);
+  NSP_HIP(hipGetLastError());
+  return (int)grid;
+}
+template int xi8_parts<double>(nsp_ctx*, int64_t, const double*, const double*, double*);
+template int xi8_parts<float>(nsp_ctx*, int64_t, const float*, const float*, double*);
+
 // k_scale: G = sum of the Gram partials; Cholesky G = R^T R (every block, one
 // thread); Xn = P R^{-1} written to the ring slot ``xn`` and, when zcol is not
 // null, to D basis columns.  Block 0 stores R (the new Gamma), ||R||_F and
@@ -358,6 +483,67 @@ __global__ __launch_bounds__(kThreads) void k_scale(int64_t n, const VT* p,
       for (int i = 0; i < NG; ++i) part_g2[(size_t)blockIdx.x * NG + i] = g[i];
     }
   }
+}
+
+// k_scale for block size 8 with the Gram partials of Xn (first Cholesky-QR
+// pass) on the matrix cores.  Lane l computes value (row, l % 8) of an 8-row
+// group from the whole row (the same products in the same order as k_scale,
+// so Xn is bit-identical) and feeds it to g8_step as both operands.  P and Xn
+// may be the same array: a row is read and written by one wave, the loads
+// before the stores.  Grid-stride over 8-row groups; grid <= kRedBlocks.
+template <typename VT>
+__global__ __launch_bounds__(kThreads) void k_scale8(int64_t n, const VT* p,
+                                                     const double* __restrict__ part_g, int nparts,
+                                                     VT* xn, VT* __restrict__ zcol, int64_t ldz,
+                                                     double* gam_out, double* nrm_gam,
+                                                     double* nrm_ginv, double* __restrict__ part_g2,
+                                                     int* flags) {
+  constexpr int D = 8, NV = D * D;
+  __shared__ double smem[kSmem];
+  __shared__ double res[NV];
+  __shared__ double ri[NV];
+  reduce_partials<NV>(part_g, nparts, res, smem);
+  if (threadIdx.x == 0) {
+    double r[NV], rv[NV];
+    const bool ok = chol_upper_inv<D>(res, r, rv);
+    for (int i = 0; i < NV; ++i) ri[i] = rv[i];
+    if (blockIdx.x == 0) {
+      if (!ok) atomicOr(flags + 1, 1);
+      if (gam_out)
+        for (int i = 0; i < NV; ++i) gam_out[i] = r[i];
+      if (nrm_gam) *nrm_gam = fro<D>(r);
+      if (nrm_ginv) *nrm_ginv = fro<D>(rv);
+    }
+  }
+  __syncthreads();
+  const int lane = threadIdx.x % kWave, wid = threadIdx.x / kWave;
+  const int col = lane & 7, off = g8_off(lane);
+  double rc[D];  // column ``col`` of R^{-1} (upper triangular)
+#pragma unroll
+  for (int b = 0; b < D; ++b) rc[b] = b <= col ? ri[b + col * D] : 0.0;
+  const int64_t nv = n * D;
+  g8_acc acc = {0.0, 0.0, 0.0, 0.0};
+  const int64_t ng = (n + 7) / 8, stride = (int64_t)gridDim.x * (kThreads / kWave);
+  for (int64_t g = (int64_t)blockIdx.x * (kThreads / kWave) + wid; g < ng; g += stride) {
+    const int64_t idx = g * 64 + off;
+    double o = 0.0;
+    if (idx < nv) {
+      double v[D];
+#pragma unroll
+      for (int b = 0; b < D; ++b) v[b] = (double)p[idx - col + b];
+      double s = 0.0;
+#pragma unroll
+      for (int b = 0; b < D; ++b)
+        if (b <= col) s = fma(v[b], rc[b], s);
+      const VT q = VT(s);
+      o = (double)q;
+      xn[idx] = q;
+      if (zcol) zcol[idx / D + (int64_t)col * ldz] = q;
+    }
+    acc = g8_step(o, o, acc);
+  }
+  __syncthreads();  // smem is reused as the tile
+  g8_finish(acc, smem, part_g2 + (size_t)blockIdx.x * NV);
 }
 
 // Second Cholesky-QR pass (d > 1): R2 from the Gram partials of Xn; Xn <- Xn R2^{-1};
@@ -963,17 +1149,87 @@ template <typename VT, int NC> constexpr int ts_nn_rows() {
   return ts_nn_vec<VT, NC>() ? kWave * RowVec<VT>::R : kWave;
 }
 
+// chol_upper_inv for K = 16 by the threads of a block, in shared memory (R and
+// R^{-1} of that size do not fit one thread's registers and went to scratch):
+// row i of R from rows 0..i-1 with its entries in parallel (each entry by the
+// same formula and summation order as chol_upper_inv), then the columns of
+// R^{-1} in parallel (each column as there).  g, r, ri: shared, K * K doubles;
+// bad: shared int.  Every thread calls it; the result is valid in all threads.
+template <int K>
+__device__ bool chol_upper_inv_par(const double* g, double* r, double* ri, int* bad) {
+  const int t = threadIdx.x;
+  double gmax = 0.0;
+  for (int i = 0; i < K; ++i) gmax = fmax(gmax, g[i + i * K]);
+  const bool ok0 = isfinite(gmax) && gmax > 0.0;
+  if (t == 0) *bad = ok0 ? 0 : 1;
+  for (int i = t; i < K * K; i += blockDim.x) { r[i] = 0.0; ri[i] = 0.0; }
+  __syncthreads();
+  for (int i = 0; i < K; ++i) {
+    if (t == 0) {
+      double s = g[i + i * K];
+      for (int l = 0; l < i; ++l) s -= r[l + i * K] * r[l + i * K];
+      if (!(s > 1e-24 * gmax) || !isfinite(s)) {
+        *bad = 1;  // rank loss: dummy pivot, the result is replaced below
+        s = 1.0;
+      }
+      r[i + i * K] = sqrt(s);
+    }
+    __syncthreads();
+    const int j = i + 1 + t;
+    if (j < K) {
+      double s = g[i + j * K];
+      for (int l = 0; l < i; ++l) s -= r[l + i * K] * r[l + j * K];
+      r[i + j * K] = s / r[i + i * K];
+    }
+    __syncthreads();
+  }
+  if (*bad) {
+    __syncthreads();
+    for (int i = t; i < K * K; i += blockDim.x) {
+      const double e = (i % K == i / K) ? 1.0 : 0.0;
+      r[i] = e;
+      ri[i] = e;
+    }
+    __syncthreads();
+    return false;
+  }
+  if (t < K) {
+    const int j = t;
+    ri[j + j * K] = 1.0 / r[j + j * K];
+    for (int i = j - 1; i >= 0; --i) {
+      double s = 0.0;
+      for (int l = i + 1; l <= j; ++l) s += r[i + l * K] * ri[l + j * K];
+      ri[i + j * K] = -s / r[i + i * K];
+    }
+  }
+  __syncthreads();
+  return true;
+}
+
+// Threads of k_ts_gramfin: 1024 for 16 columns (four groups of threads per
+// Gram entry in the partial sums; the factor in parallel), else 256.
+template <int NC> constexpr int ts_gramfin_threads() { return NC >= 16 ? 1024 : 256; }
+
 // One block: Gram of C from the partials, Cholesky; writes R^{-1} then R (NC x NC each).
 template <int NC>
-__global__ __launch_bounds__(256) void k_ts_gramfin(const int* cond, int nparts,
-                                                    const double* __restrict__ part_c,
-                                                    double* rinv, int* flags) {
+__global__ __launch_bounds__(ts_gramfin_threads<NC>()) void k_ts_gramfin(
+    const int* cond, int nparts, const double* __restrict__ part_c, double* rinv, int* flags) {
   constexpr int NV = NC * NC;
+  constexpr int NT = ts_gramfin_threads<NC>();
   if (cond && *cond == 0) return;
-  __shared__ double smem[256];
+  __shared__ double smem[NT];
   __shared__ double res[NV];
   reduce_partials<NV>(part_c, nparts, res, smem);
-  if (threadIdx.x == 0) {
+  if constexpr (NC >= 16) {
+    __shared__ double r[NV], ri[NV];
+    __shared__ int bad;
+    const bool ok = chol_upper_inv_par<NC>(res, r, ri, &bad);
+    if (threadIdx.x == 0) {
+      if (!ok) atomicOr(flags + 1, 1);
+      if (cond && !kahan_parlett_ok(NC, res)) atomicOr(flags + 1, 2);
+    }
+    for (int i = threadIdx.x; i < NV; i += NT) { rinv[i] = ri[i]; rinv[NV + i] = r[i]; }
+  } else if (threadIdx.x == 0) {
     double r[NV], ri[NV];
     if (!chol_upper_inv<NC>(res, r, ri)) atomicOr(flags + 1, 1);
     if (cond && !kahan_parlett_ok(NC, res)) atomicOr(flags + 1, 2);
@@ -1299,6 +1555,20 @@ __global__ void k_scale_rows(int64_t rows, int k, const double* __restrict__ s, 
 template <typename VT>
 int sub_gram(nsp_ctx* c, int d, int64_t n, VT* p, const VT* x, const double* part_xi, int nparts_xi,
              double* xi_out, double* nrm_xi, double* part_g) {
+  if (d == 8) {
+    const unsigned g8 = g8_grid(n);
+    if (part_xi && x)
+      k_sub_gram8<VT, true, true><<<g8, kThreads, 0, c->stream>>>(n, p, x, part_xi, nparts_xi, xi_out,
+                                                                  nrm_xi, part_g);
+    else if (part_xi)
+      k_sub_gram8<VT, true, false><<<g8, kThreads, 0, c->stream>>>(n, p, x, part_xi, nparts_xi, xi_out,
+                                                                   nrm_xi, part_g);
+    else
+      k_sub_gram8<VT, false, false><<<g8, kThreads, 0, c->stream>>>(n, p, x, part_xi, nparts_xi,
+                                                                    xi_out, nrm_xi, part_g);
+    NSP_HIP(hipGetLastError());
+    return (int)g8;
+  }
   const unsigned grid = cap_grid(n, kThreads, kRedBlocks);
 #define NSP_SG(D)                                                                              \
   case D:                                                                                      \
@@ -1312,7 +1582,7 @@ int sub_gram(nsp_ctx* c, int d, int64_t n, VT* p, const VT* x, const double* par
       k_sub_gram<VT, D, false, false><<<grid, kThreads, 0, c->stream>>>(                       \
           n, p, x, part_xi, nparts_xi, xi_out, nrm_xi, part_g);                                \
     break;
-  switch (d) { NSP_SG(1) NSP_SG(2) NSP_SG(4) NSP_SG(8) default: throw Error(NSP_ERR_ARG, "d"); }
+  switch (d) { NSP_SG(1) NSP_SG(2) NSP_SG(4) default: throw Error(NSP_ERR_ARG, "d"); }
 #undef NSP_SG
   NSP_HIP(hipGetLastError());
   return (int)grid;
@@ -1326,8 +1596,15 @@ template <typename VT>
 int scale_block(nsp_ctx* c, int d, int64_t n, const VT* p, const double* part_g, int nparts,
                 VT* xn, VT* zcol, int64_t ldz, double* gam_out, double* nrm_gam, double* nrm_ginv,
                 double* part_g2, const WArgs* wa) {
-  const unsigned grid = cap_grid(n, kThreads, kRedBlocks);
   int* flags = c->flags.as<int>();
+  if (d == 8 && part_g2 && !wa) {
+    const unsigned g8 = g8_grid(n);
+    k_scale8<VT><<<g8, kThreads, 0, c->stream>>>(n, p, part_g, nparts, xn, zcol, ldz, gam_out, nrm_gam,
+                                                 nrm_ginv, part_g2, flags);
+    NSP_HIP(hipGetLastError());
+    return (int)g8;
+  }
+  const unsigned grid = cap_grid(n, kThreads, kRedBlocks);
   WArgs w{};
   if (wa) w = *wa;
 #define NSP_SC(D)                                                                              \
@@ -1440,14 +1717,16 @@ static void ts_proj_t(nsp_ctx* c, const int* cond, int64_t n, const VT* z, int64
     if (gram) {
       k_ts_nn_v<VT, DA, NA, true><<<nnblocks, nt, 0, c->stream>>>(cond, n, z, ldz, k, h, cc, part_c);
       if (!ts_fin_fused<VT, NC>(n))
-        k_ts_gramfin<NC><<<1, 256, 0, c->stream>>>(cond, (int)nnblocks, part_c, rinv, c->flags.as<int>());
+        k_ts_gramfin<NC><<<1, ts_gramfin_threads<NC>(), 0, c->stream>>>(cond, (int)nnblocks, part_c, rinv,
+                                                                   c->flags.as<int>());
     } else if (k > 0)
       k_ts_nn_v<VT, DA, NA, false><<<nnblocks, nt, 0, c->stream>>>(cond, n, z, ldz, k, h, cc,
                                                                    nullptr);
   } else {
     if (gram) {
       k_ts_nn<VT, DA, NA, true><<<nnblocks, kThreads, 0, c->stream>>>(cond, n, z, ldz, k, h, cc, part_c);
-      k_ts_gramfin<NC><<<1, 256, 0, c->stream>>>(cond, (int)nnblocks, part_c, rinv, c->flags.as<int>());
+      k_ts_gramfin<NC><<<1, ts_gramfin_threads<NC>(), 0, c->stream>>>(cond, (int)nnblocks, part_c, rinv,
+                                                                 c->flags.as<int>());
     } else if (k > 0) {
       k_ts_nn<VT, DA, NA, false><<<nnblocks, kThreads, 0, c->stream>>>(cond, n, z, ldz, k, h, cc,
                                                                        nullptr);

@@ -698,6 +698,12 @@ static int spmmT_step_d(nsp_ctx* c, const VT* y, const VT* x, const VT* xp, cons
 template <typename VT>
 int spmmT_step(nsp_ctx* c, int d, const VT* y, const VT* x, const VT* xp, const double* gprev,
                VT* out, double* part_xi) {
+  if (d == 8 && part_xi) {
+    // block size 8: the product without its own Xi sums (their 64 per-thread
+    // accumulators spill), then the Xi partials on the matrix cores
+    spmmT_step<VT>(c, d, y, x, xp, gprev, out, nullptr);
+    return xi8_parts<VT>(c, c->AT.rows, x, out, part_xi);
+  }
   const bool prev = xp != nullptr, dots = part_xi != nullptr;
   const Csr& at = c->AT;
   if (at.rblk && at.rblk_d == d) {
