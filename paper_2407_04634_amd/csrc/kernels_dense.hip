@@ -75,6 +75,63 @@ __device__ bool chol_upper_inv(const double* g, double* r, double* ri) {
   return true;
 }
 
+// chol_upper_inv by the threads of a block, in shared memory (for K = 16 R and
+// R^{-1} do not fit one thread's registers, for K = 8 they take most of them):
+// row i of R from rows 0..i-1 with its entries in parallel (each entry by the
+// same formula and summation order as chol_upper_inv), then the columns of
+// R^{-1} in parallel (each column as there).  g, r, ri: shared, K * K doubles;
+// bad: shared int.  Every thread calls it; the result is valid in all threads.
+template <int K>
+__device__ bool chol_upper_inv_par(const double* g, double* r, double* ri, int* bad) {
+  const int t = threadIdx.x;
+  double gmax = 0.0;
+  for (int i = 0; i < K; ++i) gmax = fmax(gmax, g[i + i * K]);
+  const bool ok0 = isfinite(gmax) && gmax > 0.0;
+  if (t == 0) *bad = ok0 ? 0 : 1;
+  for (int i = t; i < K * K; i += blockDim.x) { r[i] = 0.0; ri[i] = 0.0; }
+  __syncthreads();
+  for (int i = 0; i < K; ++i) {
+    if (t == 0) {
+      double s = g[i + i * K];
+      for (int l = 0; l < i; ++l) s -= r[l + i * K] * r[l + i * K];
+      if (!(s > 1e-24 * gmax) || !isfinite(s)) {
+        *bad = 1;  // rank loss: dummy pivot, the result is replaced below
+        s = 1.0;
+      }
+      r[i + i * K] = sqrt(s);
+    }
+    __syncthreads();
+    const int j = i + 1 + t;
+    if (j < K) {
+      double s = g[i + j * K];
+      for (int l = 0; l < i; ++l) s -= r[l + i * K] * r[l + j * K];
+      r[i + j * K] = s / r[i + i * K];
+    }
+    __syncthreads();
+  }
+  if (*bad) {
+    __syncthreads();
+    for (int i = t; i < K * K; i += blockDim.x) {
+      const double e = (i % K == i / K) ? 1.0 : 0.0;
+      r[i] = e;
+      ri[i] = e;
+    }
+    __syncthreads();
+    return false;
+  }
+  if (t < K) {
+    const int j = t;
+    ri[j + j * K] = 1.0 / r[j + j * K];
+    for (int i = j - 1; i >= 0; --i) {
+      double s = 0.0;
+      for (int l = i + 1; l <= j; ++l) s += r[i + l * K] * ri[l + j * K];
+      ri[i + j * K] = -s / r[i + i * K];
+    }
+  }
+  __syncthreads();
+  return true;
+}
+
 template <int K>
 __device__ double fro(const double* a) {
   double s = 0.0;
@@ -376,10 +433,13 @@ __global__ __launch_bounds__(kThreads) void k_xi8(int64_t n, const VT* __restric
   g8_finish(acc, tile, part + (size_t)blockIdx.x * 64);
 }
 
-// Grid of the block-size-8 kernels above: one 8-row group per wave and step.
+// Grid of the block-size-8 kernels above: one 8-row group per wave and step,
+// at least 16 groups per wave and at most 256 blocks, so the next kernel's
+// fixed-order sum of the partials (a few loads in flight per thread) stays
+// short.
 static unsigned g8_grid(int64_t n) {
-  const int64_t groups = (n + 7) / 8, waves = kThreads / kWave;
-  return (unsigned)std::max<int64_t>(1, std::min<int64_t>((groups + waves - 1) / waves, kRedBlocks));
+  const int64_t groups = (n + 7) / 8, per_block = 16 * (kThreads / kWave);
+  return (unsigned)std::max<int64_t>(1, std::min<int64_t>((groups + per_block - 1) / per_block, 256));
 }
 
 template <typename VT>
@@ -502,20 +562,18 @@ __global__ __launch_bounds__(kThreads) void k_scale8(int64_t n, const VT* p,
   __shared__ double smem[kSmem];
   __shared__ double res[NV];
   __shared__ double ri[NV];
+  __shared__ double rs[NV];
+  __shared__ int bad;
   reduce_partials<NV>(part_g, nparts, res, smem);
-  if (threadIdx.x == 0) {
-    double r[NV], rv[NV];
-    const bool ok = chol_upper_inv<D>(res, r, rv);
-    for (int i = 0; i < NV; ++i) ri[i] = rv[i];
-    if (blockIdx.x == 0) {
+  const bool ok = chol_upper_inv_par<D>(res, rs, ri, &bad);
+  if (blockIdx.x == 0) {
+    if (gam_out && threadIdx.x < NV) gam_out[threadIdx.x] = rs[threadIdx.x];
+    if (threadIdx.x == 0) {
       if (!ok) atomicOr(flags + 1, 1);
-      if (gam_out)
-        for (int i = 0; i < NV; ++i) gam_out[i] = r[i];
-      if (nrm_gam) *nrm_gam = fro<D>(r);
-      if (nrm_ginv) *nrm_ginv = fro<D>(rv);
+      if (nrm_gam) *nrm_gam = fro<D>(rs);
+      if (nrm_ginv) *nrm_ginv = fro<D>(ri);
     }
   }
-  __syncthreads();
   const int lane = threadIdx.x % kWave, wid = threadIdx.x / kWave;
   const int col = lane & 7, off = g8_off(lane);
   double rc[D];  // column ``col`` of R^{-1} (upper triangular)
@@ -559,47 +617,50 @@ __global__ __launch_bounds__(kThreads) void k_scale2(int64_t n, const double* __
   __shared__ double ri[NV];
   __shared__ double gi_s;
   reduce_partials<NV>(part_g2, nparts, res, smem);
-  if (threadIdx.x == 0) {
+  __shared__ double r2s[NV];
+  if constexpr (D == 8) {
+    __shared__ int bad;
+    const bool ok = chol_upper_inv_par<D>(res, r2s, ri, &bad);
+    if (blockIdx.x == 0 && threadIdx.x == 0 && !ok) atomicOr(flags + 1, 1);
+  } else if (threadIdx.x == 0) {
     double r2[NV], r2i[NV];
     const bool ok = chol_upper_inv<D>(res, r2, r2i);
-    for (int i = 0; i < NV; ++i) ri[i] = r2i[i];
-    if (blockIdx.x == 0) {
-      if (!ok) atomicOr(flags + 1, 1);
-      if (gam) {
-        double g0[NV], g0i[NV], gn[NV], gni[NV];
-        for (int i = 0; i < NV; ++i) g0[i] = gam[i];
-        // inverse of the upper triangular old Gamma
-#pragma unroll
-        for (int i = 0; i < NV; ++i) g0i[i] = 0.0;
-#pragma unroll
-        for (int j = 0; j < D; ++j) {
-          g0i[j + j * D] = 1.0 / g0[j + j * D];
-#pragma unroll
-          for (int i = j - 1; i >= 0; --i) {
-            double s = 0.0;
-#pragma unroll
-            for (int l = i + 1; l <= j; ++l) s += g0[i + l * D] * g0i[l + j * D];
-            g0i[i + j * D] = -s / g0[i + i * D];
-          }
-        }
-#pragma unroll
-        for (int i = 0; i < D; ++i)
-#pragma unroll
-          for (int j = 0; j < D; ++j) {
-            double s = 0.0, t = 0.0;
-#pragma unroll
-            for (int l = 0; l < D; ++l) {
-              s += r2[i + l * D] * g0[l + j * D];
-              t += g0i[i + l * D] * r2i[l + j * D];
-            }
-            gn[i + j * D] = s;
-            gni[i + j * D] = t;
-          }
-        for (int i = 0; i < NV; ++i) gam[i] = gn[i];
-        if (nrm_gam) *nrm_gam = fro<D>(gn);
-        gi_s = fro<D>(gni);
-        if (nrm_ginv) *nrm_ginv = gi_s;
+    for (int i = 0; i < NV; ++i) { ri[i] = r2i[i]; r2s[i] = r2[i]; }
+    if (blockIdx.x == 0 && !ok) atomicOr(flags + 1, 1);
+  }
+  if (blockIdx.x == 0 && gam) {
+    // Gamma <- R2 Gamma and its inverse Gamma^{-1} R2^{-1}: the inverse of the
+    // old (upper triangular) Gamma by columns, then one thread per entry
+    __shared__ double g0[NV], g0i[NV], gn[NV], gni[NV];
+    __syncthreads();
+    if (threadIdx.x < NV) { g0[threadIdx.x] = gam[threadIdx.x]; g0i[threadIdx.x] = 0.0; }
+    __syncthreads();
+    if (threadIdx.x < D) {
+      const int j = threadIdx.x;
+      g0i[j + j * D] = 1.0 / g0[j + j * D];
+      for (int i = j - 1; i >= 0; --i) {
+        double s = 0.0;
+        for (int l = i + 1; l <= j; ++l) s += g0[i + l * D] * g0i[l + j * D];
+        g0i[i + j * D] = -s / g0[i + i * D];
       }
+    }
+    __syncthreads();
+    if (threadIdx.x < NV) {
+      const int i = threadIdx.x % D, j = threadIdx.x / D;
+      double s = 0.0, t = 0.0;
+      for (int l = 0; l < D; ++l) {
+        s += r2s[i + l * D] * g0[l + j * D];
+        t += g0i[i + l * D] * ri[l + j * D];
+      }
+      gn[threadIdx.x] = s;
+      gni[threadIdx.x] = t;
+      gam[threadIdx.x] = s;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      if (nrm_gam) *nrm_gam = fro<D>(gn);
+      gi_s = fro<D>(gni);
+      if (nrm_ginv) *nrm_ginv = gi_s;
     }
   }
   __syncthreads();
@@ -1147,63 +1208,6 @@ __device__ bool kahan_parlett_ok(int k, const double* g) {
 // Rows per block of the C -= Z H kernel (and so the number of Gram partials).
 template <typename VT, int NC> constexpr int ts_nn_rows() {
   return ts_nn_vec<VT, NC>() ? kWave * RowVec<VT>::R : kWave;
-}
-
-// chol_upper_inv for K = 16 by the threads of a block, in shared memory (R and
-// R^{-1} of that size do not fit one thread's registers and went to scratch):
-// row i of R from rows 0..i-1 with its entries in parallel (each entry by the
-// same formula and summation order as chol_upper_inv), then the columns of
-// R^{-1} in parallel (each column as there).  g, r, ri: shared, K * K doubles;
-// bad: shared int.  Every thread calls it; the result is valid in all threads.
-template <int K>
-__device__ bool chol_upper_inv_par(const double* g, double* r, double* ri, int* bad) {
-  const int t = threadIdx.x;
-  double gmax = 0.0;
-  for (int i = 0; i < K; ++i) gmax = fmax(gmax, g[i + i * K]);
-  const bool ok0 = isfinite(gmax) && gmax > 0.0;
-  if (t == 0) *bad = ok0 ? 0 : 1;
-  for (int i = t; i < K * K; i += blockDim.x) { r[i] = 0.0; ri[i] = 0.0; }
-  __syncthreads();
-  for (int i = 0; i < K; ++i) {
-    if (t == 0) {
-      double s = g[i + i * K];
-      for (int l = 0; l < i; ++l) s -= r[l + i * K] * r[l + i * K];
-      if (!(s > 1e-24 * gmax) || !isfinite(s)) {
-        *bad = 1;  // rank loss: dummy pivot, the result is replaced below
-        s = 1.0;
-      }
-      r[i + i * K] = sqrt(s);
-    }
-    __syncthreads();
-    const int j = i + 1 + t;
-    if (j < K) {
-      double s = g[i + j * K];
-      for (int l = 0; l < i; ++l) s -= r[l + i * K] * r[l + j * K];
-      r[i + j * K] = s / r[i + i * K];
-    }
-    __syncthreads();
-  }
-  if (*bad) {
-    __syncthreads();
-    for (int i = t; i < K * K; i += blockDim.x) {
-      const double e = (i % K == i / K) ? 1.0 : 0.0;
-      r[i] = e;
-      ri[i] = e;
-    }
-    __syncthreads();
-    return false;
-  }
-  if (t < K) {
-    const int j = t;
-    ri[j + j * K] = 1.0 / r[j + j * K];
-    for (int i = j - 1; i >= 0; --i) {
-      double s = 0.0;
-      for (int l = i + 1; l <= j; ++l) s += r[i + l * K] * ri[l + j * K];
-      ri[i + j * K] = -s / r[i + i * K];
-    }
-  }
-  __syncthreads();
-  return true;
 }
 
 // Threads of k_ts_gramfin: 1024 for 16 columns (four groups of threads per
