@@ -1,13 +1,14 @@
 """Parity across thick restarts and in the FP32 streaming kernels (through the C ABI).
 
-* Ritz pairs after three restart cycles (two thick restarts, Sec. 4.1), d = 1
-  and d = 4: every Ritz value lies within its Lanczos residual norm of the
+* Ritz pairs after three restart cycles (two thick restarts, Sec. 4.1), d = 1,
+  4 and 8 (block size 8 runs its Gram sums and its 16-column projection on the
+  matrix cores): every Ritz value lies within its Lanczos residual norm of the
   spectrum of B (which a wrong coupling block F or arrowhead in Eq. "defT"
   would break), the converged pairs agree with the oracle's Algorithm 2 on the
   same D and Omega, and so does the count below 3 eps.
 * Mixed precision (FP32 storage, FP64 accumulation) in the streaming SpMV
   kernels: first-cycle Ritz values of a Laplacian with more than 2^21 stored
-  entries in the normal form, d = 1 and d = 4, against the FP64 oracle.
+  entries in the normal form, d = 1, 4 and 8, against the FP64 oracle.
 * apply_op through the streaming kernels on a matrix with one row longer than
   a row block (the kernels' long-row branch).
 """
@@ -87,7 +88,7 @@ def _check_restart(c, a, eps, d, dim_k, seed=2):
     return th, res, r
 
 
-@pytest.mark.parametrize("d", [1, 4])
+@pytest.mark.parametrize("d", [1, 4, 8])
 def test_restart_decomposition_planted(d):
     c, a, eps = _planted600()
     print(f"[restart] planted600 d={d}, 3 cycles", flush=True)
@@ -109,7 +110,7 @@ def _laplacian_2m():
     return c
 
 
-@pytest.mark.parametrize("d", [1, 4])
+@pytest.mark.parametrize("d", [1, 4, 8])
 def test_mixed_streaming_first_cycle_ritz_values(d):
     from paper_2407_04634_amd import PREC_MIXED
     from tests.gpu_util import context
