@@ -765,6 +765,17 @@ __global__ __launch_bounds__(64) void k_leaf(int nb, int nb2, int toff, double b
         for (int r = 0; r < D; ++r) a[r + c * D] -= p[r + k * D] * sk * p[c + k * D];
     }
   }
+  // The corrections round differently in (r, c) and (c, r).  Jacobi's stopping
+  // test (off-diagonal mass below 16 u^2 of the total) cannot be met while the
+  // block is asymmetric at that level, and such leaves ran all 50 sweeps.
+#pragma unroll
+  for (int c = 1; c < D; ++c)
+#pragma unroll
+    for (int r = 0; r < c; ++r) {
+      const double m = 0.5 * (a[r + c * D] + a[c + r * D]);
+      a[r + c * D] = m;
+      a[c + r * D] = m;
+    }
   eig_small<D>(a, lt, ut);
 }
 
