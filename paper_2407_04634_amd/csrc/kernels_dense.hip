@@ -325,9 +325,10 @@ __global__ __launch_bounds__(kThreads) void k_sub_gram(int64_t n, VT* __restrict
 }
 
 // k_sub_gram for block size 8 on the matrix cores: the same Xi, the same
-// subtraction (per value, in the same order, so P is bit-identical), and the
-// Gram partials of P from g8_step with P's value as both operands.  Grid-stride
-// over 8-row groups, one group per wave and step; grid <= kRedBlocks.
+// subtraction (per value, the same operations in the same order as k_sub_gram),
+// and the Gram partials of P from g8_step with P's value as both operands.
+// Grid-stride over 8-row groups, one group per wave and step; grid from
+// g8_grid (at most 256 blocks).
 template <typename VT, bool XI, bool SUB>
 __global__ __launch_bounds__(kThreads) void k_sub_gram8(int64_t n, VT* __restrict__ p,
                                                         const VT* __restrict__ x,
@@ -547,10 +548,10 @@ __global__ __launch_bounds__(kThreads) void k_scale(int64_t n, const VT* p,
 
 // k_scale for block size 8 with the Gram partials of Xn (first Cholesky-QR
 // pass) on the matrix cores.  Lane l computes value (row, l % 8) of an 8-row
-// group from the whole row (the same products in the same order as k_scale,
-// so Xn is bit-identical) and feeds it to g8_step as both operands.  P and Xn
-// may be the same array: a row is read and written by one wave, the loads
-// before the stores.  Grid-stride over 8-row groups; grid <= kRedBlocks.
+// group from the whole row (the same products in the same order as k_scale)
+// and feeds it to g8_step as both operands.  P and Xn may be the same array: a
+// row is read and written by one wave, the loads before the stores.
+// Grid-stride over 8-row groups; grid from g8_grid (at most 256 blocks).
 template <typename VT>
 __global__ __launch_bounds__(kThreads) void k_scale8(int64_t n, const VT* p,
                                                      const double* __restrict__ part_g, int nparts,
